@@ -1,0 +1,88 @@
+"""Seeded synthetic workloads: inverse-temperature ladders and run shapes.
+
+This module only describes inputs (lattice model and size, replica count, the
+beta ladder, seeds, the sweep/exchange/record schedule).  It holds none of the
+method's arithmetic, so both the GPU binding and the CPU oracle tests can take
+their inputs from here.  All random content of a run (initial spins, EA
+couplings, flip and swap draws) is generated inside each implementation from
+the seeds, by its own Philox4x32-10.
+
+The paper's own workload is a 2D Ising lattice with J = 1 and no field
+(Sec. 4.2); the shapes below are the synthetic configurations this project is
+measured on.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+ISING2D = 0
+EA3D = 1
+
+
+def beta_geometric(b0: float, b1: float, R: int) -> np.ndarray:
+    """beta_k = b0 * (b1/b0)^(k/(R-1)), slot 0 = b0 (FP64, computed once)."""
+    if R == 1:
+        return np.array([b0], dtype=np.float64)
+    k = np.arange(R, dtype=np.float64)
+    return np.array([b0 * (b1 / b0) ** (kk / (R - 1)) for kk in k], dtype=np.float64)
+
+
+def beta_linear(b0: float, b1: float, R: int) -> np.ndarray:
+    """beta_k = b0 + k (b1 - b0)/(R-1), slot 0 = b0."""
+    if R == 1:
+        return np.array([b0], dtype=np.float64)
+    return np.array([b0 + k * (b1 - b0) / (R - 1) for k in range(R)], dtype=np.float64)
+
+
+@dataclass
+class Workload:
+    name: str
+    model: int
+    L: int
+    R: int
+    beta: np.ndarray
+    sweeps: int
+    exchange_every: int
+    record_every: int
+    seed: int
+    coupling_seed: int = 0
+    J: float = 1.0
+    h: float = 0.0
+    stream_id: int = 0
+    notes: str = ""
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def dim(self) -> int:
+        return 3 if self.model == EA3D else 2
+
+    @property
+    def sites(self) -> int:
+        return self.L ** self.dim
+
+    @property
+    def attempts_per_sweep(self) -> int:
+        return self.R * self.sites
+
+
+def ising16() -> Workload:
+    """2D Ising 16x16, R=8, beta geometric 0.20..0.60, 1000 sweeps, exchange every 10."""
+    return Workload("ising2d_L16_R8", ISING2D, 16, 8, beta_geometric(0.20, 0.60, 8),
+                    sweeps=1000, exchange_every=10, record_every=1, seed=1)
+
+
+def ising1024() -> Workload:
+    """2D Ising 1024x1024, R=64, beta linear 0.30..0.55 (spans beta_c), 10^4 sweeps."""
+    return Workload("ising2d_L1024_R64", ISING2D, 1024, 64, beta_linear(0.30, 0.55, 64),
+                    sweeps=10_000, exchange_every=10, record_every=1, seed=2)
+
+
+def ea32() -> Workload:
+    """3D +-J EA spin glass 32^3, R=128, beta geometric 0.5..3.0, 5000 sweeps, exchange every sweep."""
+    return Workload("ea3d_L32_R128", EA3D, 32, 128, beta_geometric(0.5, 3.0, 128),
+                    sweeps=5_000, exchange_every=1, record_every=1, seed=3, coupling_seed=3)
+
+
+HOT_PATH = {w.name: w for w in (ising16(), ising1024(), ea32())}

@@ -1,0 +1,180 @@
+/*
+ * pt.h -- C ABI of the MI355X (gfx950) parallel-tempering Metropolis library.
+ *
+ * Method: Metropolis-Hastings (paper Sec. 2.1, acceptance Eq. 1) sampling the
+ * Boltzmann distribution (Eq. 2) of a lattice spin model (Ising energy, Eq. 3),
+ * with Parallel Tempering (Sec. 2.1): R replicas at their own inverse
+ * temperatures that, between intervals of sweeps, try to exchange states with
+ * a neighbouring temperature, pairs alternating between (0,1),(2,3),... and
+ * (1,2),(3,4),... (Sec. 3), accepted with the logistic probability of Sec. 3.
+ * As in the paper's GPU design (Sec. 3), all simulation state stays in device
+ * memory between calls.
+ *
+ * Decomposition: sites are updated in checkerboard order (colour 0, then
+ * colour 1, per sweep); each flip draws one 32-bit word of a Philox4x32-10
+ * stream keyed by (seed, stream_id) and counted by (site group, sweep, slot,
+ * colour); acceptance is an integer compare against thresholds precomputed on
+ * the host in FP64; a replica exchange permutes the temperature slots of the
+ * walkers (no lattice is copied).  Results are a pure function of the
+ * configuration and the sequence of calls: they do not depend on the plan
+ * (tiling, sweeps per launch, block size), and they equal those of a
+ * sequential implementation that swaps states literally.
+ *
+ * Conventions
+ *   - Sites: 2D i = y*L + x; 3D i = (z*L + y)*L + x; periodic boundaries.
+ *     Colour of a site = (x + y [+ z]) mod 2.
+ *   - Energy: 2D  E = -J sum_<ij> s_i s_j - h sum_i s_i  (each bond once);
+ *             EA  E = -sum_<ij> J_ij s_i s_j, J_ij = +-1 per bond.
+ *     Integer energy E_int = -sum_<ij> J_b s_i s_j (J_b = 1 in 2D), so that
+ *     E = J*E_int - h*M; series and observables report E_int and M = sum s_i.
+ *   - "Slot" k is the temperature index (beta[k]); "walker" w is a replica
+ *     state.  walker_at[k] is the walker held by slot k; walker w starts at
+ *     slot w.
+ *
+ * Threading: one context must not be used from two host threads at once;
+ * distinct contexts may run concurrently on distinct streams.  All calls
+ * except pt_observables are asynchronous on the context's stream.
+ *
+ * Errors: every pt_status function returns PT_OK (0) or a negative code and
+ * never throws.  Configuration errors are detected synchronously (PT_EINVAL).
+ * A failed HIP call (launch or copy) returns PT_EDEVICE; after PT_EDEVICE the
+ * context is poisoned and every later call returns PT_ESTATE.  pt_last_error()
+ * returns a thread-local message describing the last failure of this thread.
+ */
+#ifndef PT_H
+#define PT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PT_ABI_VERSION 1u
+#define PT_ALL_SLOTS 0xFFFFFFFFu
+#define PT_MAX_SWEEPS_PER_LAUNCH 8u
+
+typedef enum {
+  PT_OK = 0,
+  PT_EINVAL = -1,      /* invalid argument or configuration */
+  PT_ENOMEM = -2,      /* workspace too small or host allocation failed */
+  PT_EDEVICE = -3,     /* a HIP runtime call failed */
+  PT_ESTATE = -4,      /* context poisoned by an earlier device error */
+  PT_EUNSUPPORTED = -5 /* valid for the method, not implemented by this library */
+} pt_status;
+
+typedef enum { PT_ISING2D = 0, PT_EA3D = 1 } pt_model;
+
+typedef struct {
+  uint32_t abi_version;     /* must be PT_ABI_VERSION */
+  uint32_t model;           /* pt_model */
+  uint32_t L;               /* linear size; multiple of 8, >= 8 */
+  uint32_t R;               /* replicas = temperature slots, 1 .. 4096 */
+  const double *beta;       /* host [R], finite, >= 0, slot order; copied at create */
+  double J;                 /* 2D coupling (ignored for EA) */
+  double h;                 /* 2D field; must be 0 (PT_EUNSUPPORTED otherwise) */
+  uint32_t seed;            /* Philox key word 0 (spins, flips, swaps) */
+  uint32_t stream_id;       /* Philox key word 1 (0, or an instance id) */
+  uint32_t coupling_seed;   /* Philox key word 0 of the EA couplings */
+  const int8_t *init_spins; /* NULL (draw from Philox) or host [R][N] +-1, walker order */
+  const int8_t *couplings;  /* NULL (draw from Philox) or host EA [3][N] +-1, bond (i, i+e_d) */
+  uint32_t record_every;    /* record E_int, M per slot every n sweeps (0 = never) */
+  uint32_t max_records;     /* capacity of the record series */
+} pt_config;
+
+/* Launch plan: how the work is decomposed.  Any valid plan gives bit-identical
+ * results.  Zero fields mean "choose automatically". */
+typedef enum { PT_PLAN_AUTO = 0, PT_PLAN_FUSED = 1, PT_PLAN_TILED = 2 } pt_plan_mode;
+typedef struct {
+  uint32_t mode;              /* pt_plan_mode */
+  uint32_t tile_planes;       /* TILED: rows (2D) or z-planes (3D) per workgroup tile */
+  uint32_t sweeps_per_launch; /* TILED: 1 .. PT_MAX_SWEEPS_PER_LAUNCH */
+  uint32_t block_threads;     /* 64 .. 1024, multiple of 64 */
+} pt_plan;
+
+typedef struct pt_ctx pt_ctx; /* opaque host-side context */
+
+/* Caller-owned host buffers filled by pt_observables; NULL pointers are skipped. */
+typedef struct {
+  int32_t *E_series;     /* [n_records][R] E_int per slot, oldest first */
+  int32_t *M_series;     /* [n_records][R] M per slot */
+  int32_t *E_slot;       /* [R] current E_int per slot */
+  int32_t *M_slot;       /* [R] current M per slot */
+  uint64_t *swap_att;    /* [R][R] attempted swaps; only |i-j| = 1 non-zero, symmetric */
+  uint64_t *swap_acc;    /* [R][R] accepted swaps; same layout */
+  uint32_t *walker_at;   /* [R] walker held by each slot */
+  int8_t *spins;         /* +-1: [N] for slot spins_slot, or [R][N] in slot order if PT_ALL_SLOTS */
+  uint32_t spins_slot;   /* slot to copy, or PT_ALL_SLOTS */
+  uint64_t sweeps_done;    /* out */
+  uint64_t exchanges_done; /* out */
+  uint32_t n_records;      /* out */
+} pt_obs;
+
+/* Device workspace needed for cfg, in bytes (0 and pt_last_error set if cfg is
+ * invalid).  The workspace holds every piece of simulation state: two spin
+ * buffers [R][N] (uint8, 0 = up, 1 = down), EA bond planes [3][N], flip
+ * thresholds [R][16] (uint32), swap tables (uint64), walker/slot maps, per-walker
+ * E_int and M, per-sweep accumulators, the record series and swap counters. */
+size_t pt_workspace_bytes(const pt_config *cfg);
+
+/* Initialisation phase (Sec. 3): validate cfg, build the FP64 -> integer flip
+ * and swap threshold tables on the host, lay the state out in d_workspace
+ * (device memory owned by the caller, >= pt_workspace_bytes(cfg), 256-byte
+ * aligned, left untouched after pt_destroy), draw or upload initial spins and
+ * couplings, and compute the initial E_int and M (the "first iteration").
+ * hip_stream is a hipStream_t (NULL = the null stream); all later work of the
+ * context is ordered on it.  On success *out receives the context.
+ * Errors: PT_EINVAL (cfg, alignment), PT_ENOMEM (ws_bytes too small),
+ * PT_EUNSUPPORTED (h != 0), PT_EDEVICE. */
+pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, size_t ws_bytes,
+                    pt_ctx **out);
+
+/* Override the launch plan (validated; PT_EINVAL if impossible for this size). */
+pt_status pt_set_plan(pt_ctx *ctx, const pt_plan *plan);
+/* Read the plan in use. */
+pt_status pt_get_plan(const pt_ctx *ctx, pt_plan *plan);
+
+/* Execution phase, MH part (Sec. 2.1, Eq. 1): n_sweeps checkerboard sweeps
+ * s, s+1, ..., s+n-1 of every walker at its current slot's beta, recording
+ * E_int and M after every sweep with (s'+1) % record_every == 0.  Asynchronous.
+ * PT_EINVAL if the records would exceed max_records. */
+pt_status pt_sweep(pt_ctx *ctx, uint32_t n_sweeps);
+
+/* Execution phase, PT part (Sec. 3): one exchange step e with pair parity e mod 2:
+ * for every slot k = e mod 2, e mod 2 + 2, ... with k+1 < R, the walkers a, b at
+ * slots k, k+1 swap slots with probability e^x/(1+e^x), x = (beta_k - beta_k+1)
+ * (E_a - E_b).  Then e += 1.  Asynchronous. */
+pt_status pt_exchange(pt_ctx *ctx);
+
+/* The paper's interval schedule (Sec. 3, Fig. 2): n_sweeps sweeps, and after
+ * every sweep s with exchange_every > 0 and (s+1) % exchange_every == 0 one
+ * exchange step.  Equivalent to the corresponding sequence of pt_sweep and
+ * pt_exchange calls (same results, bit for bit), with fewer launches. */
+pt_status pt_run(pt_ctx *ctx, uint32_t n_sweeps, uint32_t exchange_every);
+
+/* Synchronise the context's stream and copy the requested observables into
+ * caller-owned host buffers (layouts in pt_obs).  The only device-to-host
+ * transfer of the library. */
+pt_status pt_observables(pt_ctx *ctx, pt_obs *obs);
+
+/* Host-side view of the threshold tables built at create (for tests and tools):
+ * flip thresholds [R][16] (accept a flip of class c in slot k iff r <= T[k][c];
+ * class c = 8*b + u with b = 1 for a down spin and u = number of unsatisfied
+ * bonds of the site), and for each pair k (0 .. R-2) the half-width D[k] of its
+ * swap table.  Buffers may be NULL. */
+pt_status pt_flip_thresholds(const pt_ctx *ctx, uint32_t *out_R_by_16);
+/* Swap threshold of pair k for energy difference E_a - E_b = 4*d: the number of
+ * accepted 32-bit draws (accept iff r < T), 0 .. 2^32. */
+pt_status pt_swap_threshold(const pt_ctx *ctx, uint32_t k, int64_t d, uint64_t *out_T);
+
+/* Free the host context (never the caller's workspace or stream). NULL is a no-op. */
+void pt_destroy(pt_ctx *ctx);
+
+/* Thread-local message of the last failure on this thread ("" if none). */
+const char *pt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PT_H */

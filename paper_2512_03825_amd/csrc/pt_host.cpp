@@ -1,0 +1,570 @@
+// pt_host.cpp -- host side of the parallel-tempering Metropolis library: the C
+// ABI of include/pt.h, configuration checks, the FP64 threshold tables, the
+// workspace layout, plan selection and the launch schedule.
+#include "pt.h"
+#include "pt_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace ptmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+pt_status fail(pt_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+bool is_pow2(uint32_t v) { return v && !(v & (v - 1u)); }
+
+constexpr uint32_t kMaxR = 4096;
+constexpr uint32_t kFusedChunk = 4096;   // sweeps per fused launch
+constexpr size_t kAlign = 256;
+
+// Saturation of the logistic swap rule: beyond |x| >= 32 ln 2 the decision no
+// longer depends on the 32-bit draw.
+constexpr double kSwapSat = 0x1.62e42fefa39efp+4;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// ---- acceptance rules, FP64, evaluated once per table entry ---------------
+// Eq. (1) with the Boltzmann target of Eq. (2): accept a flip with energy
+// change dE iff r < min(1, exp(-beta dE)) * 2^32; stored as the largest
+// accepted r.  The caller guarantees p > 0.
+uint32_t flip_threshold(double beta, double dE) {
+  const double p = (dE <= 0.0) ? 1.0 : std::exp(-(beta * dE));
+  const double q = std::ceil(std::ldexp(p, 32));
+  const uint64_t n = std::min<uint64_t>((uint64_t)q, 1ull << 32); // accepted draws
+  return (uint32_t)(n - 1u);
+}
+
+// Swap probability of Sec. 3, e^x/(1+e^x) evaluated as 1/(1+e^-x), x = dBeta * dE;
+// returned as the number of accepted 32-bit draws (accept iff r < T).
+uint64_t swap_threshold(double dbeta, double dE) {
+  const double x = dbeta * dE;
+  if (x >= kSwapSat) return 1ull << 32;
+  if (x <= -kSwapSat) return 0;
+  const double p = 1.0 / (1.0 + std::exp(-x));
+  return (uint64_t)std::ceil(std::ldexp(p, 32));
+}
+
+struct Tables {
+  std::vector<uint32_t> flip; // [R][16]
+  std::vector<uint64_t> swap; // concatenated pair tables
+  std::vector<uint32_t> off;  // [R]
+  std::vector<uint32_t> D;    // [R]
+  std::vector<uint64_t> sat;  // [R][2]
+};
+
+struct Layout {
+  size_t spins[2], bonds, flip, swap_tab, swap_off, swap_D, swap_sat, wat, sof, E, M, acc3, att,
+      acc, Es, Ms, counter, total;
+};
+
+struct Derived {
+  Geometry geo;
+  double jscale; // energy unit of E_int: J (2D), 1 (EA)
+  uint32_t z;    // coordination number
+};
+
+pt_status derive(const pt_config *cfg, Derived *d) {
+  if (!cfg) return fail(PT_EINVAL, "config is NULL");
+  if (cfg->abi_version != PT_ABI_VERSION)
+    return fail(PT_EINVAL, "abi_version %u, library expects %u", cfg->abi_version, PT_ABI_VERSION);
+  if (cfg->model != PT_ISING2D && cfg->model != PT_EA3D)
+    return fail(PT_EINVAL, "unknown model %u", cfg->model);
+  const uint32_t dim = cfg->model == PT_EA3D ? 3u : 2u;
+  const uint32_t maxL = dim == 3 ? 64u : 16384u;
+  if (!is_pow2(cfg->L) || cfg->L < 8u || cfg->L > maxL)
+    return fail(PT_EINVAL, "L = %u: must be a power of two in [8, %u]", cfg->L, maxL);
+  if (cfg->R < 1u || cfg->R > kMaxR) return fail(PT_EINVAL, "R = %u: must be in [1, %u]", cfg->R, kMaxR);
+  if (!cfg->beta) return fail(PT_EINVAL, "beta is NULL");
+  if (dim == 2 && !std::isfinite(cfg->J)) return fail(PT_EINVAL, "J is not finite");
+  if (!std::isfinite(cfg->h)) return fail(PT_EINVAL, "h is not finite");
+  if (dim == 2 && cfg->h != 0.0)
+    return fail(PT_EUNSUPPORTED, "h != 0: replica exchange with a field is not implemented");
+  d->z = 2u * dim;
+  d->jscale = dim == 2 ? cfg->J : 1.0;
+  const double dEmax = 2.0 * (std::fabs(d->jscale) * d->z + (dim == 2 ? std::fabs(cfg->h) : 0.0));
+  for (uint32_t k = 0; k < cfg->R; ++k) {
+    const double b = cfg->beta[k];
+    if (!std::isfinite(b) || b < 0.0) return fail(PT_EINVAL, "beta[%u] = %g: must be finite and >= 0", k, b);
+    if (b * dEmax >= 700.0)
+      return fail(PT_EINVAL, "beta[%u] * max dE = %g: flip probabilities would underflow", k, b * dEmax);
+  }
+  Geometry &g = d->geo;
+  g.dim = dim;
+  g.L = cfg->L;
+  g.R = cfg->R;
+  g.N = cfg->L * cfg->L * (dim == 3 ? cfg->L : 1u);
+  g.gpr = cfg->L / 8u;
+  g.rows = dim == 3 ? cfg->L : 1u;
+  g.plane = cfg->L * g.rows;
+  return PT_OK;
+}
+
+// Half-width of pair k's swap table: beyond it |x| >= 32 ln 2 + 1 (saturated).
+uint32_t swap_half_width(const pt_config *cfg, const Derived &d, uint32_t k) {
+  const double scale = std::fabs(d.jscale * (cfg->beta[k] - cfg->beta[k + 1]));
+  const double dmax = (double)d.z * d.geo.N / 4.0; // |E_a - E_b| / 4 never exceeds this
+  if (scale == 0.0) return 0;
+  const double D = std::ceil((kSwapSat + 1.0) / (4.0 * scale));
+  return (uint32_t)std::min(D, std::ceil(dmax));
+}
+
+size_t swap_entries(const pt_config *cfg, const Derived &d) {
+  size_t n = 0;
+  for (uint32_t k = 0; k + 1 < cfg->R; ++k) n += 2u * (size_t)swap_half_width(cfg, d, k) + 1u;
+  return n;
+}
+
+Layout layout(const pt_config *cfg, const Derived &d) {
+  const Geometry &g = d.geo;
+  const size_t R = g.R, N = g.N;
+  Layout l;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t spin_bytes = std::max<size_t>(R, 3) * N; // also the upload staging area
+  l.spins[0] = take(spin_bytes);
+  l.spins[1] = take(spin_bytes);
+  l.bonds = take(g.dim == 3 ? 3 * N : 0);
+  l.flip = take(R * kClasses * 4);
+  l.swap_tab = take(std::max<size_t>(swap_entries(cfg, d), 1) * 8);
+  l.swap_off = take(R * 4);
+  l.swap_D = take(R * 4);
+  l.swap_sat = take(R * 16);
+  l.wat = take(R * 4);
+  l.sof = take(R * 4);
+  l.E = take(R * 4);
+  l.M = take(R * 4);
+  l.acc3 = take(kMaxSweepsPerLaunch * R * 16);
+  l.att = take(R * 4);
+  l.acc = take(R * 4);
+  l.Es = take((size_t)cfg->max_records * R * 4);
+  l.Ms = take((size_t)cfg->max_records * R * 4);
+  l.counter = take(16);
+  l.total = o;
+  return l;
+}
+
+void build_tables(const pt_config *cfg, const Derived &d, Tables *t) {
+  const uint32_t R = cfg->R, z = d.z;
+  t->flip.assign((size_t)R * kClasses, 0u);
+  for (uint32_t k = 0; k < R; ++k)
+    for (uint32_t b = 0; b < 2; ++b)
+      for (uint32_t u = 0; u <= z; ++u) {
+        // class (b, u): spin s = +-1 with u unsatisfied bonds, so s * F = z - 2u
+        const int s = b ? -1 : 1;
+        const int F = s * ((int)z - 2 * (int)u);
+        const double dE = (d.geo.dim == 2)
+                              ? (2.0 * (double)s) * (cfg->J * (double)F + cfg->h)
+                              : (2.0 * (double)s) * (double)F;
+        t->flip[(size_t)k * kClasses + 8u * b + u] = flip_threshold(cfg->beta[k], dE);
+      }
+  t->off.assign(R, 0u);
+  t->D.assign(R, 0u);
+  t->sat.assign(2 * (size_t)R, 0u);
+  t->swap.clear();
+  for (uint32_t k = 0; k + 1 < R; ++k) {
+    const uint32_t D = swap_half_width(cfg, d, k);
+    const double db = cfg->beta[k] - cfg->beta[k + 1];
+    auto rule = [&](int64_t dd) { return swap_threshold(db, d.jscale * (double)(4 * dd)); };
+    t->off[k] = (uint32_t)t->swap.size();
+    t->D[k] = D;
+    for (int64_t dd = -(int64_t)D; dd <= (int64_t)D; ++dd) t->swap.push_back(rule(dd));
+    t->sat[2 * k] = rule(-(int64_t)D - 1);
+    t->sat[2 * k + 1] = rule((int64_t)D + 1);
+  }
+  if (t->swap.empty()) t->swap.push_back(0);
+}
+
+uint32_t records_between(uint32_t every, uint64_t s0, uint64_t s1) {
+  return every ? (uint32_t)(s1 / every - s0 / every) : 0u;
+}
+
+}  // namespace
+
+struct pt_ctx {
+  pt_config cfg;
+  std::vector<double> beta;
+  Derived d;
+  Keys keys;
+  DevState st;
+  Layout lay;
+  Tables tab;
+  hipStream_t stream;
+  pt_plan plan;
+  uint64_t sweeps = 0, exchanges = 0;
+  uint32_t n_records = 0;
+  uint32_t cur = 0;
+  bool poisoned = false;
+};
+
+namespace {
+
+pt_status device_fail(pt_ctx *c, hipError_t e, const char *what) {
+  if (c) c->poisoned = true;
+  return fail(PT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
+  const Geometry &g = c->d.geo;
+  if (p.block_threads < 64 || p.block_threads > 1024 || p.block_threads % 64)
+    return fail(PT_EINVAL, "block_threads = %u: must be a multiple of 64 in [64, 1024]", p.block_threads);
+  if (p.mode == PT_PLAN_FUSED) {
+    if (fused_lds_bytes(g) > max_lds_bytes())
+      return fail(PT_EINVAL, "fused plan needs %zu bytes of LDS (max %zu)", fused_lds_bytes(g),
+                  max_lds_bytes());
+    return PT_OK;
+  }
+  if (p.mode != PT_PLAN_TILED) return fail(PT_EINVAL, "unknown plan mode %u", p.mode);
+  if (p.tile_planes < 1) return fail(PT_EINVAL, "tile_planes must be >= 1");
+  if (p.sweeps_per_launch < 1 || p.sweeps_per_launch > kMaxSweepsPerLaunch)
+    return fail(PT_EINVAL, "sweeps_per_launch = %u: must be in [1, %u]", p.sweeps_per_launch,
+                kMaxSweepsPerLaunch);
+  const uint32_t H = std::min(p.tile_planes, g.L);
+  const uint32_t halo = H >= g.L ? 0u : 2u * p.sweeps_per_launch;
+  if (halo > g.L / 2)
+    return fail(PT_EINVAL, "halo of %u planes (2 per sweep per launch) exceeds L/2", halo);
+  const size_t lds = tiled_lds_bytes(g, H, halo);
+  if (lds > max_lds_bytes())
+    return fail(PT_EINVAL, "tiled plan needs %zu bytes of LDS (max %zu)", lds, max_lds_bytes());
+  return PT_OK;
+}
+
+pt_plan auto_plan(const pt_ctx *c) {
+  const Geometry &g = c->d.geo;
+  pt_plan p{};
+  const size_t fused = fused_lds_bytes(g);
+  if (fused <= 64u * 1024u) {
+    // Everything fits one workgroup: sweeps and exchanges never leave the kernel.
+    const uint32_t items = (g.R * g.N) >> 3;
+    p.mode = PT_PLAN_FUSED;
+    p.block_threads = std::min<uint32_t>(1024u, std::max<uint32_t>(64u, (items + 63u) & ~63u));
+    p.tile_planes = g.L;
+    p.sweeps_per_launch = 1;
+    return p;
+  }
+  p.mode = PT_PLAN_TILED;
+  p.block_threads = 256;
+  p.sweeps_per_launch = 1;
+  if (g.dim == 3) {
+    p.tile_planes = std::max<uint32_t>(g.L / 2u, 4u);
+  } else {
+    // Tiles of full rows, about 32 KB of LDS each.
+    uint32_t H = std::max<uint32_t>(4u, (32u * 1024u) / g.L);
+    while (H > 4u && (g.L / H) * g.R < 1024u) H /= 2u;
+    p.tile_planes = std::min(H, g.L);
+  }
+  if (check_plan(c, p) != PT_OK) { // fall back to smaller tiles
+    p.tile_planes = 4;
+    p.sweeps_per_launch = 1;
+  }
+  return p;
+}
+
+pt_status usable(pt_ctx *c) {
+  if (!c) return fail(PT_EINVAL, "context is NULL");
+  if (c->poisoned) return fail(PT_ESTATE, "context is poisoned by an earlier device error");
+  return PT_OK;
+}
+
+// Launch n sweeps from the current sweep index; exchange after sweep s when
+// every > 0 and (s+1) % every == 0.
+pt_status advance(pt_ctx *c, uint32_t n, uint32_t every) {
+  const uint32_t re = c->cfg.record_every;
+  const uint32_t need = records_between(re, c->sweeps, c->sweeps + n);
+  if ((uint64_t)c->n_records + need > c->cfg.max_records)
+    return fail(PT_EINVAL, "%u more records would exceed max_records = %u", need, c->cfg.max_records);
+  if (c->sweeps + n > 0xFFFFFFFFull) return fail(PT_EINVAL, "sweep counter would exceed 2^32");
+  const Geometry &g = c->d.geo;
+  uint32_t left = n;
+  while (left) {
+    Schedule sch{};
+    sch.s0 = (uint32_t)c->sweeps;
+    sch.record_every = re;
+    sch.rec_base = c->n_records;
+    sch.ex_step = (uint32_t)c->exchanges;
+    uint32_t nsw, nex = 0;
+    hipError_t err;
+    if (c->plan.mode == PT_PLAN_FUSED) {
+      nsw = std::min(left, kFusedChunk);
+      sch.nsw = nsw;
+      sch.exchange_every = every;
+      nex = records_between(every, c->sweeps, c->sweeps + nsw);
+      err = launch_fused(c->st, g, c->keys, c->cur, c->plan.block_threads, sch, c->stream);
+    } else {
+      nsw = std::min(left, c->plan.sweeps_per_launch);
+      if (every) nsw = std::min<uint32_t>(nsw, every - (uint32_t)(c->sweeps % every));
+      sch.nsw = nsw;
+      sch.do_exchange = (every && (c->sweeps + nsw) % every == 0) ? 1u : 0u;
+      nex = sch.do_exchange;
+      const uint32_t H = std::min(c->plan.tile_planes, g.L);
+      const uint32_t halo = H >= g.L ? 0u : 2u * nsw;
+      err = launch_tiled(c->st, g, c->keys, c->cur, H, halo, c->plan.block_threads, sch, c->stream);
+      if (err == hipSuccess && halo) c->cur ^= 1u;
+    }
+    if (err != hipSuccess) return device_fail(c, err, "sweep launch");
+    c->n_records += records_between(re, c->sweeps, c->sweeps + nsw);
+    c->sweeps += nsw;
+    c->exchanges += nex;
+    left -= nsw;
+  }
+  return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pt_workspace_bytes(const pt_config *cfg) {
+  Derived d;
+  if (derive(cfg, &d) != PT_OK) return 0;
+  return layout(cfg, d).total;
+}
+
+pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, size_t ws_bytes,
+                    pt_ctx **out) {
+  if (!out) return fail(PT_EINVAL, "out is NULL");
+  *out = nullptr;
+  Derived d;
+  pt_status s = derive(cfg, &d);
+  if (s != PT_OK) return s;
+  if (cfg->record_every && cfg->max_records == 0)
+    return fail(PT_EINVAL, "record_every > 0 needs max_records > 0");
+  const size_t N = d.geo.N, R = d.geo.R;
+  if (cfg->init_spins)
+    for (size_t i = 0; i < R * N; ++i)
+      if (cfg->init_spins[i] != 1 && cfg->init_spins[i] != -1)
+        return fail(PT_EINVAL, "init_spins[%zu] = %d: must be +1 or -1", i, cfg->init_spins[i]);
+  if (cfg->couplings && d.geo.dim == 3)
+    for (size_t i = 0; i < 3 * N; ++i)
+      if (cfg->couplings[i] != 1 && cfg->couplings[i] != -1)
+        return fail(PT_EINVAL, "couplings[%zu] = %d: must be +1 or -1", i, cfg->couplings[i]);
+  if (!d_workspace) return fail(PT_EINVAL, "workspace is NULL");
+  if ((uintptr_t)d_workspace % kAlign) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
+
+  pt_ctx *c = new (std::nothrow) pt_ctx();
+  if (!c) return fail(PT_ENOMEM, "host allocation failed");
+  c->cfg = *cfg;
+  c->beta.assign(cfg->beta, cfg->beta + cfg->R);
+  c->cfg.beta = c->beta.data();
+  c->cfg.init_spins = nullptr;
+  c->cfg.couplings = nullptr;
+  c->d = d;
+  c->keys = {cfg->seed, cfg->stream_id, cfg->coupling_seed};
+  c->lay = layout(&c->cfg, d);
+  if (ws_bytes < c->lay.total) {
+    delete c;
+    return fail(PT_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, layout(cfg, d).total);
+  }
+  build_tables(&c->cfg, d, &c->tab);
+  c->stream = (hipStream_t)hip_stream;
+
+  uint8_t *base = (uint8_t *)d_workspace;
+  const Layout &l = c->lay;
+  DevState &st = c->st;
+  st.spins[0] = base + l.spins[0];
+  st.spins[1] = base + l.spins[1];
+  st.bonds = base + l.bonds;
+  st.flip_thr = (uint32_t *)(base + l.flip);
+  st.swap_tab = (uint64_t *)(base + l.swap_tab);
+  st.swap_off = (uint32_t *)(base + l.swap_off);
+  st.swap_D = (uint32_t *)(base + l.swap_D);
+  st.swap_sat = (uint64_t *)(base + l.swap_sat);
+  st.walker_at = (uint32_t *)(base + l.wat);
+  st.slot_of = (uint32_t *)(base + l.sof);
+  st.E = (int32_t *)(base + l.E);
+  st.M = (int32_t *)(base + l.M);
+  st.acc3 = (int32_t *)(base + l.acc3);
+  st.att = (uint32_t *)(base + l.att);
+  st.acc = (uint32_t *)(base + l.acc);
+  st.E_series = (int32_t *)(base + l.Es);
+  st.M_series = (int32_t *)(base + l.Ms);
+  st.counter = (uint32_t *)(base + l.counter);
+  st.staging = st.spins[1];
+
+  hipError_t e = hipSuccess;
+  const hipStream_t sm = c->stream;
+  auto H2D = [&](void *dst, const void *src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, sm);
+  };
+  H2D(st.flip_thr, c->tab.flip.data(), c->tab.flip.size() * 4);
+  H2D(st.swap_tab, c->tab.swap.data(), c->tab.swap.size() * 8);
+  H2D(st.swap_off, c->tab.off.data(), R * 4);
+  H2D(st.swap_D, c->tab.D.data(), R * 4);
+  H2D(st.swap_sat, c->tab.sat.data(), R * 16);
+  if (e == hipSuccess) e = launch_reset(st, d.geo, sm);
+  if (d.geo.dim == 3) {
+    if (cfg->couplings) H2D(st.staging, cfg->couplings, 3 * N);
+    if (e == hipSuccess) e = launch_init_bonds(st, d.geo, c->keys, cfg->couplings != nullptr, sm);
+  }
+  if (cfg->init_spins) H2D(st.staging, cfg->init_spins, R * N);
+  if (e == hipSuccess) e = launch_init_spins(st, d.geo, c->keys, cfg->init_spins != nullptr, sm);
+  if (e == hipSuccess) e = launch_recount(st, d.geo, 0, sm);
+  if (e == hipSuccess) e = hipStreamSynchronize(sm);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(PT_EDEVICE, "initialisation: %s", hipGetErrorString(e));
+  }
+  c->plan = auto_plan(c);
+  *out = c;
+  return PT_OK;
+}
+
+pt_status pt_set_plan(pt_ctx *ctx, const pt_plan *plan) {
+  pt_status s = usable(ctx);
+  if (s != PT_OK) return s;
+  if (!plan) return fail(PT_EINVAL, "plan is NULL");
+  if (plan->mode == PT_PLAN_AUTO) {
+    ctx->plan = auto_plan(ctx);
+    return PT_OK;
+  }
+  s = check_plan(ctx, *plan);
+  if (s != PT_OK) return s;
+  ctx->plan = *plan;
+  if (ctx->plan.mode == PT_PLAN_FUSED) {
+    ctx->plan.tile_planes = ctx->d.geo.L;
+    ctx->plan.sweeps_per_launch = 1;
+  }
+  return PT_OK;
+}
+
+pt_status pt_get_plan(const pt_ctx *ctx, pt_plan *plan) {
+  if (!ctx || !plan) return fail(PT_EINVAL, "NULL argument");
+  *plan = ctx->plan;
+  return PT_OK;
+}
+
+pt_status pt_sweep(pt_ctx *ctx, uint32_t n_sweeps) {
+  pt_status s = usable(ctx);
+  if (s != PT_OK) return s;
+  return advance(ctx, n_sweeps, 0);
+}
+
+pt_status pt_exchange(pt_ctx *ctx) {
+  pt_status s = usable(ctx);
+  if (s != PT_OK) return s;
+  hipError_t e = launch_exchange(ctx->st, ctx->d.geo, ctx->keys, (uint32_t)ctx->exchanges, ctx->stream);
+  if (e != hipSuccess) return device_fail(ctx, e, "exchange launch");
+  ctx->exchanges++;
+  return PT_OK;
+}
+
+pt_status pt_run(pt_ctx *ctx, uint32_t n_sweeps, uint32_t exchange_every) {
+  pt_status s = usable(ctx);
+  if (s != PT_OK) return s;
+  return advance(ctx, n_sweeps, exchange_every);
+}
+
+pt_status pt_observables(pt_ctx *ctx, pt_obs *obs) {
+  pt_status s = usable(ctx);
+  if (s != PT_OK) return s;
+  if (!obs) return fail(PT_EINVAL, "obs is NULL");
+  const size_t R = ctx->d.geo.R, N = ctx->d.geo.N;
+  if (obs->spins && obs->spins_slot != PT_ALL_SLOTS && obs->spins_slot >= R)
+    return fail(PT_EINVAL, "spins_slot = %u out of range", obs->spins_slot);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return device_fail(ctx, e, "stream synchronise");
+  const DevState &st = ctx->st;
+  std::vector<uint32_t> wat(R), att(R), acc(R);
+  std::vector<int32_t> E(R), M(R);
+  auto D2H = [&](void *dst, const void *src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpy(dst, src, n, hipMemcpyDeviceToHost);
+  };
+  D2H(wat.data(), st.walker_at, R * 4);
+  D2H(E.data(), st.E, R * 4);
+  D2H(M.data(), st.M, R * 4);
+  D2H(att.data(), st.att, R * 4);
+  D2H(acc.data(), st.acc, R * 4);
+  if (obs->E_series) D2H(obs->E_series, st.E_series, (size_t)ctx->n_records * R * 4);
+  if (obs->M_series) D2H(obs->M_series, st.M_series, (size_t)ctx->n_records * R * 4);
+  std::vector<uint8_t> bits;
+  if (obs->spins) {
+    if (obs->spins_slot == PT_ALL_SLOTS) {
+      bits.resize(R * N);
+      D2H(bits.data(), st.spins[ctx->cur], R * N);
+    } else {
+      bits.resize(N);
+      if (e == hipSuccess && wat[obs->spins_slot] < R)
+        D2H(bits.data(), st.spins[ctx->cur] + (size_t)wat[obs->spins_slot] * N, N);
+    }
+  }
+  if (e != hipSuccess) return device_fail(ctx, e, "observables copy");
+  for (size_t k = 0; k < R; ++k)
+    if (wat[k] >= R) {
+      ctx->poisoned = true;
+      return fail(PT_EDEVICE, "walker map corrupted (slot %zu holds %u)", k, wat[k]);
+    }
+  if (obs->walker_at) std::memcpy(obs->walker_at, wat.data(), R * 4);
+  for (size_t k = 0; k < R; ++k) {
+    if (obs->E_slot) obs->E_slot[k] = E[wat[k]];
+    if (obs->M_slot) obs->M_slot[k] = M[wat[k]];
+  }
+  if (obs->swap_att || obs->swap_acc) {
+    if (obs->swap_att) std::memset(obs->swap_att, 0, R * R * 8);
+    if (obs->swap_acc) std::memset(obs->swap_acc, 0, R * R * 8);
+    for (size_t k = 0; k + 1 < R; ++k) {
+      if (obs->swap_att) obs->swap_att[k * R + k + 1] = obs->swap_att[(k + 1) * R + k] = att[k];
+      if (obs->swap_acc) obs->swap_acc[k * R + k + 1] = obs->swap_acc[(k + 1) * R + k] = acc[k];
+    }
+  }
+  if (obs->spins) {
+    if (obs->spins_slot == PT_ALL_SLOTS) {
+      for (size_t k = 0; k < R; ++k) {
+        const uint8_t *src = bits.data() + (size_t)wat[k] * N;
+        int8_t *dst = obs->spins + k * N;
+        for (size_t i = 0; i < N; ++i) dst[i] = src[i] ? -1 : 1;
+      }
+    } else {
+      for (size_t i = 0; i < N; ++i) obs->spins[i] = bits[i] ? -1 : 1;
+    }
+  }
+  obs->sweeps_done = ctx->sweeps;
+  obs->exchanges_done = ctx->exchanges;
+  obs->n_records = ctx->n_records;
+  return PT_OK;
+}
+
+pt_status pt_flip_thresholds(const pt_ctx *ctx, uint32_t *out) {
+  if (!ctx || !out) return fail(PT_EINVAL, "NULL argument");
+  std::memcpy(out, ctx->tab.flip.data(), ctx->tab.flip.size() * 4);
+  return PT_OK;
+}
+
+pt_status pt_swap_threshold(const pt_ctx *ctx, uint32_t k, int64_t d, uint64_t *out_T) {
+  if (!ctx || !out_T) return fail(PT_EINVAL, "NULL argument");
+  if (k + 1 >= ctx->d.geo.R) return fail(PT_EINVAL, "pair %u out of range", k);
+  const int64_t D = ctx->tab.D[k];
+  if (d < -D)
+    *out_T = ctx->tab.sat[2 * (size_t)k];
+  else if (d > D)
+    *out_T = ctx->tab.sat[2 * (size_t)k + 1];
+  else
+    *out_T = ctx->tab.swap[ctx->tab.off[k] + (size_t)(d + D)];
+  return PT_OK;
+}
+
+void pt_destroy(pt_ctx *ctx) { delete ctx; }
+
+const char *pt_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// pt_internal.h -- structures shared by the host library (pt_host.cpp) and the
+// gfx950 kernels (pt_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ptmi {
+
+// Philox purpose tags (counter word 3, bits 8+).
+constexpr uint32_t kPurposeFlip = 0u;
+constexpr uint32_t kPurposeSwap = 1u << 8;
+constexpr uint32_t kPurposeSpin = 2u << 8;
+constexpr uint32_t kPurposeBond = 3u << 8;
+
+constexpr uint32_t kClasses = 16;      // flip-threshold classes per slot: 8*b + u
+constexpr uint32_t kMaxSweepsPerLaunch = 8;
+
+// Device pointers into the caller's workspace.
+struct DevState {
+  uint8_t *spins[2];   // [R][N] 0 = up, 1 = down; walker-indexed
+  uint8_t *bonds;      // [3][N] 0 = J +1, 1 = J -1 (EA), bond (i, i+e_d)
+  uint32_t *flip_thr;  // [R][16] accept iff r <= T
+  uint64_t *swap_tab;  // concatenated per-pair tables, accept iff r < T
+  uint32_t *swap_off;  // [R] index in swap_tab of pair k's entry d = -D[k]
+  uint32_t *swap_D;    // [R] half-width D[k]
+  uint64_t *swap_sat;  // [R][2] T for d < -D, T for d > D
+  uint32_t *walker_at; // [R] slot -> walker
+  uint32_t *slot_of;   // [R] walker -> slot
+  int32_t *E;          // [R] walker E_int
+  int32_t *M;          // [R] walker magnetisation
+  int32_t *acc3;       // [kMaxSweepsPerLaunch][R][4] per-sweep accumulators (n, sum b, sum cls, -)
+  uint32_t *att;       // [R] pair attempts
+  uint32_t *acc;       // [R] pair accepts
+  int32_t *E_series;   // [max_records][R] slot order
+  int32_t *M_series;
+  uint32_t *counter;   // [4] workgroup-arrival counter of the tiled sweep
+  uint8_t *staging;    // scratch for host uploads (aliases spins[1])
+};
+
+struct Geometry {
+  uint32_t dim;        // 2 or 3
+  uint32_t L;
+  uint32_t R;
+  uint32_t N;          // sites per replica
+  uint32_t gpr;        // 8-site groups per row = L/8
+  uint32_t rows;       // rows per plane: 1 (2D) or L (3D)
+  uint32_t plane;      // bytes per plane = L*rows
+};
+
+struct Keys {
+  uint32_t k0, k1;     // flip / swap / spin stream key
+  uint32_t b0;         // bond stream key word 0
+};
+
+// Bookkeeping for sweeps, records and exchanges done inside one launch.
+struct Schedule {
+  uint32_t s0;           // first sweep of the launch
+  uint32_t nsw;          // sweeps in the launch
+  uint32_t record_every; // 0 = never
+  uint32_t rec_base;     // index of the next record
+  uint32_t exchange_every; // fused kernel: exchange after sweep s when (s+1) % every == 0
+  uint32_t do_exchange;  // tiled kernel: one exchange step after the last sweep
+  uint32_t ex_step;      // index e of the next exchange step
+};
+
+hipError_t launch_init_spins(const DevState &st, const Geometry &g, const Keys &k, bool upload,
+                             hipStream_t stream);
+hipError_t launch_init_bonds(const DevState &st, const Geometry &g, const Keys &k, bool upload,
+                             hipStream_t stream);
+hipError_t launch_reset(const DevState &st, const Geometry &g, hipStream_t stream);
+hipError_t launch_recount(const DevState &st, const Geometry &g, uint32_t cur,
+                          hipStream_t stream);
+hipError_t launch_exchange(const DevState &st, const Geometry &g, const Keys &k, uint32_t e,
+                           hipStream_t stream);
+hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
+                        uint32_t tile_planes, uint32_t halo, uint32_t threads,
+                        const Schedule &sch, hipStream_t stream);
+hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
+                        uint32_t threads, const Schedule &sch, hipStream_t stream);
+
+// LDS bytes needed by the kernels (host-side planning).
+size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo);
+size_t fused_lds_bytes(const Geometry &g);
+size_t max_lds_bytes();
+
+}  // namespace ptmi

@@ -1,0 +1,141 @@
+"""GPU library vs CPU oracle, bit for bit, through the C ABI.
+
+Every case runs the same seeded configuration on both sides and compares all
+spins of all slots, the walker map, the E/M record series, the current E and M,
+and the swap attempt/accept counts.  Plans (fused, tiled with whole-replica or
+halo tiles, ragged last tiles, 1..4 sweeps per launch, 64..1024 threads) must
+all give the identical result, which doubles as the race detector.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import compare, make_gpu, make_oracle, requires_gpu, say
+from paper_2512_03825_amd.workloads import beta_geometric, beta_linear, ising16
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+FUSED, TILED = 1, 2
+
+
+@pytest.fixture(scope="module")
+def pt():
+    from paper_2512_03825_amd import pt as _pt
+    return _pt
+
+
+def run_case(pt, oracle_mod, model, L, R, beta, seed, sweeps, every, record_every=1, plan=None,
+             coupling_seed=None, init_spins=None, couplings=None, split=False, tag=""):
+    say("case", tag, "model", model, "L", L, "R", R, "sweeps", sweeps, "every", every, "plan", plan)
+    rec = sweeps // record_every if record_every else 0
+    sim = make_gpu(pt, model, L, R, beta, seed, coupling_seed, init_spins, couplings,
+                   record_every, rec, plan)
+    orc = make_oracle(oracle_mod, model, L, R, beta, seed, coupling_seed, init_spins, couplings,
+                      record_every, rec)
+    if split:
+        # the primitive calls: pt_sweep intervals and pt_exchange steps
+        done = 0
+        while done < sweeps:
+            n = min(every, sweeps - done) if every else sweeps - done
+            sim.sweep(n)
+            orc.sweep(n)
+            done += n
+            if every and done % every == 0:
+                sim.exchange()
+                orc.exchange()
+    else:
+        sim.run(sweeps, every)
+        orc.run(sweeps, every)
+    compare(sim, orc, tag)
+    return sim, orc
+
+
+def test_ising16_full_run_auto_plan(pt, oracle_mod):
+    """2D Ising 16x16, R = 8, 1000 sweeps, exchange every 10: the whole run, default plan."""
+    w = ising16()
+    sim, orc = run_case(pt, oracle_mod, 0, w.L, w.R, w.beta, w.seed, w.sweeps, w.exchange_every,
+                        tag="ising16")
+    assert sim.plan()["mode"] == FUSED
+    assert orc.swaps()[1].sum() > 0  # swaps really happen
+
+
+@pytest.mark.parametrize("plan", [
+    dict(mode=TILED, tile_planes=16, sweeps_per_launch=1, block_threads=64),    # whole replica
+    dict(mode=TILED, tile_planes=16, sweeps_per_launch=3, block_threads=256),
+    dict(mode=TILED, tile_planes=4, sweeps_per_launch=1, block_threads=64),     # halo tiles
+    dict(mode=TILED, tile_planes=5, sweeps_per_launch=2, block_threads=128),    # ragged last tile
+    dict(mode=TILED, tile_planes=3, sweeps_per_launch=4, block_threads=1024),
+    dict(mode=FUSED, block_threads=64),
+    dict(mode=FUSED, block_threads=1024),
+])
+def test_ising16_every_plan_is_identical(pt, oracle_mod, plan):
+    w = ising16()
+    run_case(pt, oracle_mod, 0, w.L, w.R, w.beta, w.seed, 200, w.exchange_every, plan=plan,
+             tag="ising16-plan")
+
+
+@pytest.mark.parametrize("plan", [
+    None,
+    dict(mode=TILED, tile_planes=64, sweeps_per_launch=2, block_threads=256),
+    dict(mode=TILED, tile_planes=8, sweeps_per_launch=1, block_threads=256),
+    dict(mode=TILED, tile_planes=13, sweeps_per_launch=3, block_threads=512),
+])
+def test_ising64_odd_R(pt, oracle_mod, plan):
+    """Several tiles, a ragged tail, odd R (the top slot sits out every other step)."""
+    beta = beta_linear(0.30, 0.55, 5)
+    run_case(pt, oracle_mod, 0, 64, 5, beta, 7, 60, 3, record_every=2, plan=plan, tag="ising64")
+
+
+@pytest.mark.parametrize("plan", [
+    None,
+    dict(mode=FUSED, block_threads=256),
+    dict(mode=TILED, tile_planes=8, sweeps_per_launch=1, block_threads=256),
+    dict(mode=TILED, tile_planes=2, sweeps_per_launch=1, block_threads=128),
+    dict(mode=TILED, tile_planes=3, sweeps_per_launch=2, block_threads=256),
+])
+def test_ea8(pt, oracle_mod, plan):
+    beta = beta_geometric(0.5, 3.0, 6)
+    run_case(pt, oracle_mod, 1, 8, 6, beta, 3, 50, 1, plan=plan, coupling_seed=3, tag="ea8")
+
+
+@pytest.mark.parametrize("plan", [
+    None,
+    dict(mode=TILED, tile_planes=4, sweeps_per_launch=2, block_threads=256),
+    dict(mode=TILED, tile_planes=16, sweeps_per_launch=1, block_threads=512),
+])
+def test_ea16(pt, oracle_mod, plan):
+    beta = beta_geometric(0.5, 3.0, 4)
+    run_case(pt, oracle_mod, 1, 16, 4, beta, 3, 20, 1, plan=plan, coupling_seed=5, tag="ea16")
+
+
+def test_primitive_calls_equal_run(pt, oracle_mod):
+    """pt_sweep / pt_exchange in intervals give the same result as pt_run."""
+    beta = beta_geometric(0.2, 0.6, 8)
+    for plan in (None, dict(mode=TILED, tile_planes=4, sweeps_per_launch=2, block_threads=256)):
+        run_case(pt, oracle_mod, 0, 32, 8, beta, 11, 40, 4, plan=plan, split=True, tag="split")
+
+
+def test_uploaded_spins_and_couplings(pt, oracle_mod):
+    rng = np.random.default_rng(5)
+    L, R = 8, 4
+    N = L ** 3
+    J = np.where(rng.random((3, N)) < 0.5, -1, 1).astype(np.int8)
+    s0 = np.where(rng.random((R, N)) < 0.3, -1, 1).astype(np.int8)
+    beta = beta_geometric(0.6, 2.0, R)
+    run_case(pt, oracle_mod, 1, L, R, beta, 9, 30, 2, init_spins=s0, couplings=J, tag="upload")
+    s2 = np.where(rng.random((3, 32 * 32)) < 0.5, -1, 1).astype(np.int8)
+    run_case(pt, oracle_mod, 0, 32, 3, beta_linear(0.3, 0.6, 3), 2, 30, 2, init_spins=s2,
+             plan=dict(mode=TILED, tile_planes=8, sweeps_per_launch=1, block_threads=256),
+             tag="upload2d")
+
+
+def test_beta_zero_negates_every_sweep(pt, oracle_mod):
+    """At beta = 0 every attempt flips: after t sweeps each state is (-1)^t times its start."""
+    from paper_2512_03825_amd import pt as ptm
+    L, R = 32, 4
+    sim = make_gpu(ptm, 0, L, R, np.zeros(R), 3, record_every=1, max_records=16,
+                   plan=dict(mode=TILED, tile_planes=8, sweeps_per_launch=2, block_threads=256))
+    s0 = sim.observables(spins="all")["spins"].copy()
+    sim.run(5, 1)
+    obs = sim.observables(spins="all")
+    wat = obs["walker_at"]
+    np.testing.assert_array_equal(obs["spins"], -s0[wat])

@@ -71,8 +71,8 @@ struct Tables {
 };
 
 struct Layout {
-  size_t spins[2], bonds, flip, swap_tab, swap_off, swap_D, swap_sat, wat, sof, E, M, acc3, att,
-      acc, Es, Ms, counter, total;
+  size_t spins[2], bonds, staging, flip, swap_tab, swap_off, swap_D, swap_sat, wat, sof, E, M,
+      acc3, att, acc, Es, Ms, counter, total;
 };
 
 struct Derived {
@@ -142,10 +142,14 @@ Layout layout(const pt_config *cfg, const Derived &d) {
     o = align_up(o + bytes);
     return at;
   };
-  const size_t spin_bytes = std::max<size_t>(R, 3) * N; // also the upload staging area
-  l.spins[0] = take(spin_bytes);
-  l.spins[1] = take(spin_bytes);
-  l.bonds = take(g.dim == 3 ? 3 * N : 0);
+  l.spins[0] = take(R * N / 8); // bit-packed
+  l.spins[1] = take(R * N / 8);
+  l.bonds = take(g.dim == 3 ? 3 * N / 8 : 0);
+  // +-1 bytes the host uploads at create (only when the config provides them)
+  size_t stage = 0;
+  if (cfg->init_spins) stage = std::max(stage, R * N);
+  if (cfg->couplings && g.dim == 3) stage = std::max(stage, 3 * N);
+  l.staging = take(stage);
   l.flip = take(R * kClasses * 4);
   l.swap_tab = take(std::max<size_t>(swap_entries(cfg, d), 1) * 8);
   l.swap_off = take(R * 4);
@@ -242,6 +246,9 @@ pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
                 kMaxSweepsPerLaunch);
   const uint32_t H = std::min(p.tile_planes, g.L);
   const uint32_t halo = H >= g.L ? 0u : 2u * p.sweeps_per_launch;
+  if (halo && g.plane % 32u)
+    return fail(PT_EINVAL, "tiles smaller than the lattice need planes of a multiple of 32 sites "
+                "(2D: L >= 32)");
   if (halo > g.L / 2)
     return fail(PT_EINVAL, "halo of %u planes (2 per sweep per launch) exceeds L/2", halo);
   const size_t lds = tiled_lds_bytes(g, H, halo);
@@ -256,7 +263,7 @@ pt_plan auto_plan(const pt_ctx *c) {
   const size_t fused = fused_lds_bytes(g);
   if (fused <= 64u * 1024u) {
     // Everything fits one workgroup: sweeps and exchanges never leave the kernel.
-    const uint32_t items = (g.R * g.N) >> 3;
+    const uint32_t items = (g.R * g.N) / (8u * span_groups(g));
     p.mode = PT_PLAN_FUSED;
     p.block_threads = std::min<uint32_t>(1024u, std::max<uint32_t>(64u, (items + 63u) & ~63u));
     p.tile_planes = g.L;
@@ -264,19 +271,24 @@ pt_plan auto_plan(const pt_ctx *c) {
     return p;
   }
   p.mode = PT_PLAN_TILED;
-  p.block_threads = 256;
-  p.sweeps_per_launch = 1;
+  p.block_threads = 512;
+  p.sweeps_per_launch = 2;
   if (g.dim == 3) {
     p.tile_planes = std::max<uint32_t>(g.L / 2u, 4u);
-  } else {
-    // Tiles of full rows, about 32 KB of LDS each.
-    uint32_t H = std::max<uint32_t>(4u, (32u * 1024u) / g.L);
-    while (H > 4u && (g.L / H) * g.R < 1024u) H /= 2u;
-    p.tile_planes = std::min(H, g.L);
-  }
-  if (check_plan(c, p) != PT_OK) { // fall back to smaller tiles
-    p.tile_planes = 4;
     p.sweeps_per_launch = 1;
+    p.block_threads = 256;
+  } else if (g.plane % 32u) {
+    p.tile_planes = g.L; // small rows: whole-replica tiles, updated in place
+    p.block_threads = 256;
+  } else {
+    // Tiles of full rows with about 64 KB of spins in LDS.
+    p.tile_planes = std::max<uint32_t>(8u, std::min<uint32_t>(g.L, (64u * 1024u) / g.L));
+  }
+  for (int tries = 0; tries < 8 && check_plan(c, p) != PT_OK; ++tries) {
+    // shrink until the plan fits (LDS, halo rules); whole-replica tiles always fit
+    if (p.sweeps_per_launch > 1) p.sweeps_per_launch /= 2;
+    else if (p.tile_planes > 1u && g.plane % 32u == 0) p.tile_planes /= 2;
+    else p.tile_planes = g.L;
   }
   return p;
 }
@@ -371,7 +383,8 @@ pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, s
   c->cfg.couplings = nullptr;
   c->d = d;
   c->keys = {cfg->seed, cfg->stream_id, cfg->coupling_seed};
-  c->lay = layout(&c->cfg, d);
+  // Laid out from the caller's config: its upload pointers size the staging area.
+  c->lay = layout(cfg, d);
   if (ws_bytes < c->lay.total) {
     delete c;
     return fail(PT_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, layout(cfg, d).total);
@@ -382,14 +395,15 @@ pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, s
   uint8_t *base = (uint8_t *)d_workspace;
   const Layout &l = c->lay;
   DevState &st = c->st;
-  st.spins[0] = base + l.spins[0];
-  st.spins[1] = base + l.spins[1];
-  st.bonds = base + l.bonds;
+  st.spins[0] = (uint32_t *)(base + l.spins[0]);
+  st.spins[1] = (uint32_t *)(base + l.spins[1]);
+  st.bonds = (uint32_t *)(base + l.bonds);
   st.flip_thr = (uint32_t *)(base + l.flip);
   st.swap_tab = (uint64_t *)(base + l.swap_tab);
   st.swap_off = (uint32_t *)(base + l.swap_off);
   st.swap_D = (uint32_t *)(base + l.swap_D);
   st.swap_sat = (uint64_t *)(base + l.swap_sat);
+  st.swap_n = (uint32_t)c->tab.swap.size();
   st.walker_at = (uint32_t *)(base + l.wat);
   st.slot_of = (uint32_t *)(base + l.sof);
   st.E = (int32_t *)(base + l.E);
@@ -400,7 +414,7 @@ pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, s
   st.E_series = (int32_t *)(base + l.Es);
   st.M_series = (int32_t *)(base + l.Ms);
   st.counter = (uint32_t *)(base + l.counter);
-  st.staging = st.spins[1];
+  st.staging = base + l.staging;
 
   hipError_t e = hipSuccess;
   const hipStream_t sm = c->stream;
@@ -497,15 +511,16 @@ pt_status pt_observables(pt_ctx *ctx, pt_obs *obs) {
   D2H(acc.data(), st.acc, R * 4);
   if (obs->E_series) D2H(obs->E_series, st.E_series, (size_t)ctx->n_records * R * 4);
   if (obs->M_series) D2H(obs->M_series, st.M_series, (size_t)ctx->n_records * R * 4);
-  std::vector<uint8_t> bits;
+  std::vector<uint32_t> bits; // packed walker lattices
+  const size_t wpr = N / 32;
   if (obs->spins) {
     if (obs->spins_slot == PT_ALL_SLOTS) {
-      bits.resize(R * N);
-      D2H(bits.data(), st.spins[ctx->cur], R * N);
+      bits.resize(R * wpr);
+      D2H(bits.data(), st.spins[ctx->cur], R * wpr * 4);
     } else {
-      bits.resize(N);
+      bits.resize(wpr);
       if (e == hipSuccess && wat[obs->spins_slot] < R)
-        D2H(bits.data(), st.spins[ctx->cur] + (size_t)wat[obs->spins_slot] * N, N);
+        D2H(bits.data(), st.spins[ctx->cur] + (size_t)wat[obs->spins_slot] * wpr, wpr * 4);
     }
   }
   if (e != hipSuccess) return device_fail(ctx, e, "observables copy");
@@ -527,15 +542,14 @@ pt_status pt_observables(pt_ctx *ctx, pt_obs *obs) {
       if (obs->swap_acc) obs->swap_acc[k * R + k + 1] = obs->swap_acc[(k + 1) * R + k] = acc[k];
     }
   }
+  auto unpack = [&](const uint32_t *src, int8_t *dst) {
+    for (size_t i = 0; i < N; ++i) dst[i] = ((src[i >> 5] >> (i & 31)) & 1u) ? -1 : 1;
+  };
   if (obs->spins) {
     if (obs->spins_slot == PT_ALL_SLOTS) {
-      for (size_t k = 0; k < R; ++k) {
-        const uint8_t *src = bits.data() + (size_t)wat[k] * N;
-        int8_t *dst = obs->spins + k * N;
-        for (size_t i = 0; i < N; ++i) dst[i] = src[i] ? -1 : 1;
-      }
+      for (size_t k = 0; k < R; ++k) unpack(bits.data() + (size_t)wat[k] * wpr, obs->spins + k * N);
     } else {
-      for (size_t i = 0; i < N; ++i) obs->spins[i] = bits[i] ? -1 : 1;
+      unpack(bits.data(), obs->spins);
     }
   }
   obs->sweeps_done = ctx->sweeps;

@@ -18,13 +18,14 @@ constexpr uint32_t kMaxSweepsPerLaunch = 8;
 
 // Device pointers into the caller's workspace.
 struct DevState {
-  uint8_t *spins[2];   // [R][N] 0 = up, 1 = down; walker-indexed
-  uint8_t *bonds;      // [3][N] 0 = J +1, 1 = J -1 (EA), bond (i, i+e_d)
+  uint32_t *spins[2];  // [R][N/32] bit-packed, bit set = down (s = -1); walker-indexed
+  uint32_t *bonds;     // [3][N/32] bit-packed, bit set = J -1 (EA), bond (i, i+e_d)
   uint32_t *flip_thr;  // [R][16] accept iff r <= T
   uint64_t *swap_tab;  // concatenated per-pair tables, accept iff r < T
   uint32_t *swap_off;  // [R] index in swap_tab of pair k's entry d = -D[k]
   uint32_t *swap_D;    // [R] half-width D[k]
   uint64_t *swap_sat;  // [R][2] T for d < -D, T for d > D
+  uint32_t swap_n;     // entries in swap_tab
   uint32_t *walker_at; // [R] slot -> walker
   uint32_t *slot_of;   // [R] walker -> slot
   int32_t *E;          // [R] walker E_int
@@ -35,7 +36,7 @@ struct DevState {
   int32_t *E_series;   // [max_records][R] slot order
   int32_t *M_series;
   uint32_t *counter;   // [4] workgroup-arrival counter of the tiled sweep
-  uint8_t *staging;    // scratch for host uploads (aliases spins[1])
+  uint8_t *staging;    // +-1 bytes uploaded by the host (only if the config uploads)
 };
 
 struct Geometry {
@@ -78,6 +79,9 @@ hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, ui
                         const Schedule &sch, hipStream_t stream);
 hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
                         uint32_t threads, const Schedule &sch, hipStream_t stream);
+
+// Groups of 8 sites one lane updates per item (V): 2D min(4, L/8), 3D min(2, L/8).
+uint32_t span_groups(const Geometry &g);
 
 // LDS bytes needed by the kernels (host-side planning).
 size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo);

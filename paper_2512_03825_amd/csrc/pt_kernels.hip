@@ -66,106 +66,166 @@ __device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, u
   return {c0, c1, c2, c3};
 }
 
-__device__ __forceinline__ uint2 lds_ld8(const uint8_t *p) {
-  return *reinterpret_cast<const uint2 *>(p);
+// LDS span of V consecutive 8-byte groups (2V dwords), 8V-byte aligned.
+template <int V>
+__device__ __forceinline__ void lds_load(uint32_t (&d)[2 * V], const uint8_t *p) {
+  if constexpr (V == 1) {
+    const uint2 a = *reinterpret_cast<const uint2 *>(p);
+    d[0] = a.x;
+    d[1] = a.y;
+  } else {
+#pragma unroll
+    for (int i = 0; i < V / 2; ++i) {
+      const uint4 a = reinterpret_cast<const uint4 *>(p)[i];
+      d[4 * i] = a.x;
+      d[4 * i + 1] = a.y;
+      d[4 * i + 2] = a.z;
+      d[4 * i + 3] = a.w;
+    }
+  }
 }
-__device__ __forceinline__ void lds_st8(uint8_t *p, uint32_t lo, uint32_t hi) {
-  *reinterpret_cast<uint2 *>(p) = make_uint2(lo, hi);
+template <int V>
+__device__ __forceinline__ void lds_store(uint8_t *p, const uint32_t (&d)[2 * V]) {
+  if constexpr (V == 1) {
+    *reinterpret_cast<uint2 *>(p) = make_uint2(d[0], d[1]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V / 2; ++i)
+      reinterpret_cast<uint4 *>(p)[i] = make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]);
+  }
 }
 
 // Per-lane tallies of accepted flips: n = count, sb = sum of b (down spins
-// flipped up), sc = sum of class index 8b+u.  Energy change of the tally:
-// dE_int = 2z n - 4 (sc - 8 sb), magnetisation change dM = 4 sb - 2 n.
+// flipped up), sc = 4 x sum of class index 8b+u.  Energy change of the tally:
+// dE_int = 2z n - (sc - 32 sb), magnetisation change dM = 4 sb - 2 n.
 struct Tally {
   int n, sb, sc;
 };
 
-// Metropolis decision for the four colour sites of a group, given the centre
-// word W, the per-byte unsatisfied-bond counts u (valid at the colour bytes),
-// the colour offset and the four draws; returns the new centre word.
-__device__ __forceinline__ uint2 decide(uint32_t wlo, uint32_t whi, uint32_t ulo, uint32_t uhi,
-                                        uint32_t off, const Words &r, const uint32_t *thr,
-                                        Tally &t) {
-  const uint32_t sh = off << 3;
-  const uint32_t wnlo = wlo >> sh, wnhi = whi >> sh;  // colour sites at bytes 0, 2
-  const uint32_t clo = (wnlo << 3) | (ulo >> sh);     // class 8b+u per colour byte
-  const uint32_t chi = (wnhi << 3) | (uhi >> sh);
-  const uint32_t t0 = thr[clo & 15u];
-  const uint32_t t1 = thr[(clo >> 16) & 15u];
-  const uint32_t t2 = thr[chi & 15u];
-  const uint32_t t3 = thr[(chi >> 16) & 15u];
-  const uint32_t flo = (r.x <= t0 ? 1u : 0u) + (r.y <= t1 ? 0x10000u : 0u);
-  const uint32_t fhi = (r.z <= t2 ? 1u : 0u) + (r.w <= t3 ? 0x10000u : 0u);
-  t.n += (int)(__builtin_popcount(flo) + __builtin_popcount(fhi));
-  t.sb = (int)__builtin_amdgcn_udot4(wnlo, flo, (uint32_t)t.sb, false);
-  t.sb = (int)__builtin_amdgcn_udot4(wnhi, fhi, (uint32_t)t.sb, false);
+// Metropolis decision for the four colour sites of a group.  wlo/whi: the
+// group's 8 spin bytes; ulo/uhi: per-byte unsatisfied-bond counts (valid at
+// the colour bytes, which sit at bit offsets sh and sh+16 of each dword,
+// sh = 8*off); b0 = 1 << sh, b1 = 1 << (sh+16); r: the group's four draws.
+// Writes the new spin bytes.
+__device__ __forceinline__ void decide(uint32_t wlo, uint32_t whi, uint32_t ulo, uint32_t uhi,
+                                       uint32_t sh, uint32_t b0, uint32_t b1, const Words &r,
+                                       const uint32_t *thr, Tally &t, uint32_t &nlo,
+                                       uint32_t &nhi) {
+  // 4*(8b+u) per byte (<= 56): the byte offset of the class threshold
+  const uint32_t clo = (wlo << 5) | (ulo << 2);
+  const uint32_t chi = (whi << 5) | (uhi << 2);
+  const uint8_t *tb = reinterpret_cast<const uint8_t *>(thr);
+  const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(clo, sh, 6));
+  const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(clo, sh + 16u, 6));
+  const uint32_t t2 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(chi, sh, 6));
+  const uint32_t t3 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(chi, sh + 16u, 6));
+  const uint32_t flo = (r.x <= t0 ? b0 : 0u) | (r.y <= t1 ? b1 : 0u);
+  const uint32_t fhi = (r.z <= t2 ? b0 : 0u) | (r.w <= t3 ? b1 : 0u);
+  t.n = (int)__builtin_amdgcn_udot4(flo + fhi, 0x01010101u, (uint32_t)t.n, false);
+  t.sb = (int)__builtin_amdgcn_udot4(wlo, flo, (uint32_t)t.sb, false);
+  t.sb = (int)__builtin_amdgcn_udot4(whi, fhi, (uint32_t)t.sb, false);
   t.sc = (int)__builtin_amdgcn_udot4(clo, flo, (uint32_t)t.sc, false);
   t.sc = (int)__builtin_amdgcn_udot4(chi, fhi, (uint32_t)t.sc, false);
-  return make_uint2(wlo ^ (flo << sh), whi ^ (fhi << sh));
+  nlo = wlo ^ flo;
+  nhi = whi ^ fhi;
 }
 
-// Byte index (within the row) of the edge byte the group needs: the site left
-// of the group for off = 0, the site right of it for off = 1 (periodic).
-__device__ __forceinline__ uint32_t edge_index(uint32_t g, uint32_t off, uint32_t L) {
-  return off ? ((8u * g + 8u) & (L - 1u)) : ((8u * g + L - 1u) & (L - 1u));
+// Byte index within the row of the edge site a span of V groups starting at
+// group g0 needs: left of the span for off = 0, right of it for off = 1.
+template <int V>
+__device__ __forceinline__ uint32_t edge_index(uint32_t g0, uint32_t off, uint32_t L) {
+  return off ? ((8u * (g0 + V)) & (L - 1u)) : ((8u * g0 + L - 1u) & (L - 1u));
 }
 
-// 2D Ising group update.  row/up/dn: LDS rows; g: group; off: colour offset.
-__device__ __forceinline__ void group2d(uint8_t *row, const uint8_t *up, const uint8_t *dn,
-                                        uint32_t g, uint32_t L, uint32_t off, const Words &r,
-                                        const uint32_t *thr, Tally &t) {
-  const uint2 W = lds_ld8(row + 8u * g);
-  const uint2 U = lds_ld8(up + 8u * g);
-  const uint2 D = lds_ld8(dn + 8u * g);
-  const uint32_t e = row[edge_index(g, off, L)];
+// Left / right neighbour words of dword j of a span (0/1 bytes), with the
+// edge byte e0 entering on the left (off = 0) or e1 on the right (off = 1).
+template <int V>
+__device__ __forceinline__ uint32_t left_of(const uint32_t (&w)[2 * V], int j, uint32_t e0) {
+  return j ? __builtin_amdgcn_alignbyte(w[j], w[j - 1], 3) : ((w[0] << 8) | e0);
+}
+template <int V>
+__device__ __forceinline__ uint32_t right_of(const uint32_t (&w)[2 * V], int j, uint32_t e1) {
+  return (j < 2 * V - 1) ? __builtin_amdgcn_alignbyte(w[j + 1], w[j], 1) : ((w[2 * V - 1] >> 8) | (e1 << 24));
+}
+
+// 2D Ising: update the colour sites of V consecutive groups of one row.
+template <int V>
+__device__ __forceinline__ void span2d(uint8_t *row, const uint8_t *up, const uint8_t *dn,
+                                       uint32_t g0, uint32_t L, uint32_t off,
+                                       const Words (&r)[V], const uint32_t *thr, Tally &t) {
+  uint32_t w[2 * V], a[2 * V], b[2 * V], nw[2 * V];
+  const uint32_t o = 8u * g0;
+  lds_load<V>(w, row + o);
+  lds_load<V>(a, up + o);
+  lds_load<V>(b, dn + o);
+  const uint32_t e = row[edge_index<V>(g0, off, L)];
   const uint32_t e0 = off ? 0u : e, e1 = off ? e : 0u;
-  const uint32_t llo = (W.x << 8) | e0;                       // left neighbours
-  const uint32_t lhi = __builtin_amdgcn_alignbyte(W.y, W.x, 3);
-  const uint32_t rlo = __builtin_amdgcn_alignbyte(W.y, W.x, 1); // right neighbours
-  const uint32_t rhi = (W.y >> 8) | (e1 << 24);
-  const uint32_t ulo = ((U.x ^ W.x) + (D.x ^ W.x)) + ((llo ^ W.x) + (rlo ^ W.x));
-  const uint32_t uhi = ((U.y ^ W.y) + (D.y ^ W.y)) + ((lhi ^ W.y) + (rhi ^ W.y));
-  const uint2 nw = decide(W.x, W.y, ulo, uhi, off, r, thr, t);
-  lds_st8(row + 8u * g, nw.x, nw.y);
+  const uint32_t sh = off << 3, b0 = 1u << sh, b1 = 0x10000u << sh;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    uint32_t cnt[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = 2 * v + h;
+      cnt[h] = ((a[j] ^ w[j]) + (b[j] ^ w[j])) +
+               ((left_of<V>(w, j, e0) ^ w[j]) + (right_of<V>(w, j, e1) ^ w[j]));
+    }
+    decide(w[2 * v], w[2 * v + 1], cnt[0], cnt[1], sh, b0, b1, r[v], thr, t, nw[2 * v],
+           nw[2 * v + 1]);
+  }
+  lds_store<V>(row + o, nw);
 }
 
-// 3D +-J EA group update.  Spin and bond planes share one LDS plane indexing:
-// plane p of spins at sp + p*P, of x/y/z bonds at bx/by/bz + p*P.
-__device__ __forceinline__ void group3d(uint8_t *sp, const uint8_t *bx, const uint8_t *by,
-                                        const uint8_t *bz, uint32_t P, uint32_t pl, uint32_t pu,
-                                        uint32_t pd, uint32_t y, uint32_t g, uint32_t L,
-                                        uint32_t off, const Words &r, const uint32_t *thr,
-                                        Tally &t) {
+// 3D +-J EA: update the colour sites of V consecutive groups of row y of plane
+// pl.  Spin and bond planes share one LDS plane indexing: plane p of spins at
+// sp + (p << lgP), of x/y/z bonds at bx/by/bz + (p << lgP).
+template <int V>
+__device__ __forceinline__ void span3d(uint8_t *sp, const uint8_t *bx, const uint8_t *by,
+                                       const uint8_t *bz, uint32_t lgL, uint32_t pl, uint32_t pu,
+                                       uint32_t pd, uint32_t y, uint32_t g0, uint32_t L,
+                                       uint32_t off, const Words (&r)[V], const uint32_t *thr,
+                                       Tally &t) {
+  const uint32_t lgP = 2u * lgL;
   const uint32_t yu = (y + L - 1u) & (L - 1u), yd = (y + 1u) & (L - 1u);
-  const uint32_t o = pl * P + y * L + 8u * g;    // this group
-  const uint32_t oyu = pl * P + yu * L + 8u * g; // row y-1
-  const uint32_t oyd = pl * P + yd * L + 8u * g; // row y+1
-  const uint32_t ozu = pu * P + y * L + 8u * g;  // plane z-1
-  const uint32_t ozd = pd * P + y * L + 8u * g;  // plane z+1
-  const uint2 W = lds_ld8(sp + o);
-  const uint2 Sy0 = lds_ld8(sp + oyu), Sy1 = lds_ld8(sp + oyd);
-  const uint2 Sz0 = lds_ld8(sp + ozu), Sz1 = lds_ld8(sp + ozd);
-  const uint2 Jx = lds_ld8(bx + o);              // bond to x+1
-  const uint2 Jy0 = lds_ld8(by + oyu), Jy1 = lds_ld8(by + o);
-  const uint2 Jz0 = lds_ld8(bz + ozu), Jz1 = lds_ld8(bz + o);
-  const uint32_t ei = pl * P + y * L + edge_index(g, off, L);
+  const uint32_t rowb = (pl << lgP) + (y << lgL);
+  const uint32_t o = rowb + 8u * g0;                          // this span
+  const uint32_t oyu = (pl << lgP) + (yu << lgL) + 8u * g0;   // row y-1
+  const uint32_t oyd = (pl << lgP) + (yd << lgL) + 8u * g0;   // row y+1
+  const uint32_t ozu = (pu << lgP) + (y << lgL) + 8u * g0;    // plane z-1
+  const uint32_t ozd = (pd << lgP) + (y << lgL) + 8u * g0;    // plane z+1
+  uint32_t w[2 * V], jx[2 * V], nw[2 * V];
+  lds_load<V>(w, sp + o);
+  lds_load<V>(jx, bx + o);                                    // bonds to x+1
+  const uint32_t ei = rowb + edge_index<V>(g0, off, L);
   const uint32_t e = sp[ei];
-  const uint32_t ej = off ? 0u : (uint32_t)bx[ei]; // bond from the left edge site (off = 0)
+  const uint32_t ej = off ? 0u : (uint32_t)bx[ei];            // bond from the left edge site
   const uint32_t e0 = off ? 0u : e, e1 = off ? e : 0u;
-  const uint32_t llo = (W.x << 8) | e0;
-  const uint32_t lhi = __builtin_amdgcn_alignbyte(W.y, W.x, 3);
-  const uint32_t rlo = __builtin_amdgcn_alignbyte(W.y, W.x, 1);
-  const uint32_t rhi = (W.y >> 8) | (e1 << 24);
-  const uint32_t jllo = (Jx.x << 8) | ej;         // bond to x-1 = Jx of the left site
-  const uint32_t jlhi = __builtin_amdgcn_alignbyte(Jx.y, Jx.x, 3);
-  const uint32_t ulo = (xor3(llo, W.x, jllo) + xor3(rlo, W.x, Jx.x)) +
-                       (xor3(Sy0.x, W.x, Jy0.x) + xor3(Sy1.x, W.x, Jy1.x)) +
-                       (xor3(Sz0.x, W.x, Jz0.x) + xor3(Sz1.x, W.x, Jz1.x));
-  const uint32_t uhi = (xor3(lhi, W.y, jlhi) + xor3(rhi, W.y, Jx.y)) +
-                       (xor3(Sy0.y, W.y, Jy0.y) + xor3(Sy1.y, W.y, Jy1.y)) +
-                       (xor3(Sz0.y, W.y, Jz0.y) + xor3(Sz1.y, W.y, Jz1.y));
-  const uint2 nw = decide(W.x, W.y, ulo, uhi, off, r, thr, t);
-  lds_st8(sp + o, nw.x, nw.y);
+  uint32_t cnt[2 * V];
+#pragma unroll
+  for (int j = 0; j < 2 * V; ++j)
+    cnt[j] = xor3(left_of<V>(w, j, e0), w[j], left_of<V>(jx, j, ej)) +
+             xor3(right_of<V>(w, j, e1), w[j], jx[j]);
+  {
+    uint32_t s0[2 * V], s1[2 * V], j0[2 * V], j1[2 * V];
+    lds_load<V>(s0, sp + oyu);
+    lds_load<V>(s1, sp + oyd);
+    lds_load<V>(j0, by + oyu);
+    lds_load<V>(j1, by + o);
+#pragma unroll
+    for (int j = 0; j < 2 * V; ++j) cnt[j] += xor3(s0[j], w[j], j0[j]) + xor3(s1[j], w[j], j1[j]);
+    lds_load<V>(s0, sp + ozu);
+    lds_load<V>(s1, sp + ozd);
+    lds_load<V>(j0, bz + ozu);
+    lds_load<V>(j1, bz + o);
+#pragma unroll
+    for (int j = 0; j < 2 * V; ++j) cnt[j] += xor3(s0[j], w[j], j0[j]) + xor3(s1[j], w[j], j1[j]);
+  }
+  const uint32_t sh = off << 3, b0 = 1u << sh, b1 = 0x10000u << sh;
+#pragma unroll
+  for (int v = 0; v < V; ++v)
+    decide(w[2 * v], w[2 * v + 1], cnt[2 * v], cnt[2 * v + 1], sh, b0, b1, r[v], thr, t,
+           nw[2 * v], nw[2 * v + 1]);
+  lds_store<V>(sp + o, nw);
 }
 
 __device__ __forceinline__ int wave_sum(int v) {
@@ -187,8 +247,10 @@ __device__ void exchange_step(const DevState &st, uint32_t R, uint32_t k0, uint3
       T = st.swap_sat[2u * k];
     else if (d > D)
       T = st.swap_sat[2u * k + 1u];
-    else
-      T = st.swap_tab[st.swap_off[k] + (uint32_t)(d + D)];
+    else {
+      const uint32_t idx = st.swap_off[k] + (uint32_t)(d + D);
+      T = idx < st.swap_n ? st.swap_tab[idx] : 0u; // a valid table always passes
+    }
     const uint32_t r = philox(k, e, 0u, kPurposeSwap, k0, k1).x;
     st.att[k] += 1u;
     if ((uint64_t)r < T) {
@@ -206,16 +268,69 @@ struct TiledArgs {
   Geometry geo;
   Keys key;
   Schedule sch;
-  const uint8_t *src;
-  uint8_t *dst;
+  const uint32_t *src; // bit-packed spins read by this launch
+  uint32_t *dst;       // bit-packed spins written by this launch
   uint32_t H;      // interior planes per tile (last tile may be shorter)
   uint32_t halo;   // halo planes per side (0 = whole replica, in place)
-  uint32_t lg_gpr; // log2(L/8)
+  uint32_t lg_L;   // log2(L)
+  uint32_t lg_spr; // log2(spans per row) = log2(L / (8 V))
   uint32_t lg_rows;
   int32_t z2;      // 2 * coordination number (8 in 2D, 12 in 3D)
 };
 
-template <int DIM>
+// Global lattices are bit-packed (bit j of word q = site 32q + j); LDS holds
+// one byte per site.  unpack32 spreads a word to 32 bytes, pack32 gathers them.
+__device__ __forceinline__ void unpack32(uint32_t w, uint32_t (&d)[8]) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    d[j] = __umul24(__builtin_amdgcn_ubfe(w, 4u * j, 4u), 0x00204081u) & 0x01010101u;
+}
+__device__ __forceinline__ uint32_t pack32(const uint32_t (&d)[8]) {
+  uint32_t b[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    b[j] = __builtin_amdgcn_udot4(d[2 * j + 1], 0x80402010u,
+                                  __builtin_amdgcn_udot4(d[2 * j], 0x08040201u, 0u, false), false);
+  return b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
+}
+
+// LDS bytes [0, 32 cnt) <- unpacked words src[(f + q) & m], q < cnt.
+__device__ __forceinline__ void unpack_tile(uint8_t *lds, const uint32_t *src, uint32_t f,
+                                            uint32_t cnt, uint32_t m, uint32_t tid, uint32_t nt) {
+  constexpr uint32_t kBatch = 4;
+  for (uint32_t q0 = tid; q0 < cnt; q0 += kBatch * nt) {
+    uint32_t w[kBatch];
+#pragma unroll
+    for (uint32_t j = 0; j < kBatch; ++j) {
+      const uint32_t q = q0 + j * nt;
+      w[j] = (q < cnt) ? src[(f + q) & m] : 0u;
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < kBatch; ++j) {
+      const uint32_t q = q0 + j * nt;
+      if (q < cnt) {
+        uint32_t d[8];
+        unpack32(w[j], d);
+        uint4 *p = reinterpret_cast<uint4 *>(lds + 32u * q);
+        p[0] = make_uint4(d[0], d[1], d[2], d[3]);
+        p[1] = make_uint4(d[4], d[5], d[6], d[7]);
+      }
+    }
+  }
+}
+
+// dst[q] <- packed LDS bytes [32q, 32q + 32), q < cnt.
+__device__ __forceinline__ void pack_tile(uint32_t *dst, const uint8_t *lds, uint32_t cnt,
+                                          uint32_t tid, uint32_t nt) {
+  for (uint32_t q = tid; q < cnt; q += nt) {
+    const uint4 *p = reinterpret_cast<const uint4 *>(lds + 32u * q);
+    const uint4 x = p[0], y = p[1];
+    const uint32_t d[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+    dst[q] = pack32(d);
+  }
+}
+
+template <int DIM, int V>
 __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint32_t s_thr[kClasses];
@@ -225,7 +340,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
   const Geometry &G = a.geo;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const uint32_t tile = blockIdx.x, w = blockIdx.y;
-  const uint32_t L = G.L, P = G.plane;
+  const uint32_t L = G.L, lgL = a.lg_L;
+  const uint32_t lgP = (DIM == 3 ? 2u : 1u) * lgL;     // bytes per plane = 2^lgP
   const uint32_t y0 = tile * a.H;
   const uint32_t Ht = min(a.H, L - y0);
   const uint32_t halo = a.halo;
@@ -235,52 +351,50 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
   if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
 
   uint8_t *sp = smem;
-  uint8_t *bx = smem + (size_t)np * P;
-  uint8_t *by = bx + (size_t)np * P;
-  uint8_t *bz = by + (size_t)np * P;
+  uint8_t *bx = smem + ((size_t)np << lgP);
+  uint8_t *by = bx + ((size_t)np << lgP);
+  uint8_t *bz = by + ((size_t)np << lgP);
 
-  // Stage planes [base, base+np) mod L of this walker (and the bonds) in LDS.
+  // Stage planes [base, base+np) mod L of this walker (and the bonds) in LDS,
+  // one byte per site.  Halo tiles have planes of a multiple of 32 sites.
   {
-    const uint32_t words = np * (P >> 3), nw = G.N >> 3, first = base * (P >> 3);
-    const uint2 *src = reinterpret_cast<const uint2 *>(a.src + (size_t)w * G.N);
-    for (uint32_t q = tid; q < words; q += nt)
-      reinterpret_cast<uint2 *>(sp)[q] = src[(first + q) & (nw - 1u)];
+    const uint32_t nwr = G.N >> 5, first = (base << lgP) >> 5, cnt = (np << lgP) >> 5;
+    unpack_tile(sp, a.src + (size_t)w * nwr, first, cnt, nwr - 1u, tid, nt);
     if (DIM == 3) {
-      const uint2 *b = reinterpret_cast<const uint2 *>(a.st.bonds);
-      for (uint32_t q = tid; q < words; q += nt) {
-        const uint32_t gq = (first + q) & (nw - 1u);
-        reinterpret_cast<uint2 *>(bx)[q] = b[gq];
-        reinterpret_cast<uint2 *>(by)[q] = b[nw + gq];
-        reinterpret_cast<uint2 *>(bz)[q] = b[2u * nw + gq];
-      }
+      unpack_tile(bx, a.st.bonds, first, cnt, nwr - 1u, tid, nt);
+      unpack_tile(by, a.st.bonds + nwr, first, cnt, nwr - 1u, tid, nt);
+      unpack_tile(bz, a.st.bonds + 2u * nwr, first, cnt, nwr - 1u, tid, nt);
     }
   }
   __syncthreads();
 
-  const uint32_t gmask = G.gpr - 1u, rmask = G.rows - 1u;
-  const uint32_t shp = a.lg_gpr + a.lg_rows;
+  const uint32_t smask = (1u << a.lg_spr) - 1u, rmask = G.rows - 1u;
+  const uint32_t shp = a.lg_spr + a.lg_rows;
   Tally t = {0, 0, 0};
   for (uint32_t hs = 0; hs < 2u * a.sch.nsw; ++hs) {
     const uint32_t c = hs & 1u;
     const uint32_t s = a.sch.s0 + (hs >> 1);
     const uint32_t ext = halo ? (halo - 1u - hs) : 0u;
-    const uint32_t plo = halo - ext;                 // computed LDS planes [plo, phi)
+    const uint32_t plo = halo - ext;                 // computed LDS planes [plo, plo+Ht+2ext)
     const uint32_t items = (Ht + 2u * ext) << shp;
     for (uint32_t q = tid; q < items; q += nt) {
-      const uint32_t g = q & gmask;
-      const uint32_t y = (q >> a.lg_gpr) & rmask;
+      const uint32_t g0 = (q & smask) * V;
+      const uint32_t y = (q >> a.lg_spr) & rmask;
       const uint32_t pl = plo + (q >> shp);
       const uint32_t pu = (pl == 0u) ? np - 1u : pl - 1u;
       const uint32_t pd = (pl + 1u == np) ? 0u : pl + 1u;
       const uint32_t gp = (base + pl) & (L - 1u);   // global plane coordinate
       const uint32_t off = (c + gp + (DIM == 3 ? y : 0u)) & 1u;
-      const uint32_t ctr0 = ((gp << a.lg_rows) + y) * G.gpr + g;
-      const Words r = philox(ctr0, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+      const uint32_t ctr0 = (((gp << a.lg_rows) + y) << (lgL - 3u)) + g0;
+      Words r[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
       Tally tg = {0, 0, 0};
       if (DIM == 2)
-        group2d(sp + pl * P, sp + pu * P, sp + pd * P, g, L, off, r, s_thr, tg);
+        span2d<V>(sp + (pl << lgP), sp + (pu << lgP), sp + (pd << lgP), g0, L, off, r, s_thr, tg);
       else
-        group3d(sp, bx, by, bz, P, pl, pu, pd, y, g, L, off, r, s_thr, tg);
+        span3d<V>(sp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, s_thr, tg);
       if (pl >= halo && pl < halo + Ht) {
         t.n += tg.n;
         t.sb += tg.sb;
@@ -288,7 +402,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
       }
     }
     if (c == 1u) {
-      int dE = a.z2 * t.n - 4 * (t.sc - 8 * t.sb);
+      int dE = a.z2 * t.n - (t.sc - 32 * t.sb);
       int dM = 4 * t.sb - 2 * t.n;
       t = {0, 0, 0};
       dE = wave_sum(dE);
@@ -311,13 +425,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
     }
   }
 
-  // Write the interior planes back (contiguous in global memory).
-  {
-    const uint32_t words = Ht * (P >> 3);
-    uint2 *dst = reinterpret_cast<uint2 *>(a.dst + (size_t)w * G.N + (size_t)y0 * P);
-    const uint2 *lsrc = reinterpret_cast<const uint2 *>(sp + (size_t)halo * P);
-    for (uint32_t q = tid; q < words; q += nt) dst[q] = lsrc[q];
-  }
+  // Write the interior planes back, packed (contiguous in global memory).
+  pack_tile(a.dst + (size_t)w * (G.N >> 5) + ((y0 << lgP) >> 5), sp + ((size_t)halo << lgP),
+            (Ht << lgP) >> 5, tid, nt);
 
   // The last workgroup to arrive folds the sweep results, records, exchanges.
   __syncthreads();
@@ -369,8 +479,8 @@ struct FusedArgs {
   Geometry geo;
   Keys key;
   Schedule sch;
-  uint8_t *spins;  // in place
-  uint32_t lg_gpr, lg_rows, lg_items; // log2(L/8), log2(rows), log2(N/8)
+  uint32_t *spins; // bit-packed, updated in place
+  uint32_t lg_L, lg_spr, lg_rows, lg_items; // log2 of L, spans per row, rows per plane, spans per replica
   int32_t z2;
 };
 
@@ -392,11 +502,12 @@ __host__ __device__ inline FusedLayout fused_layout(uint32_t R, uint32_t N, uint
   return f;
 }
 
-template <int DIM>
+template <int DIM, int V>
 __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const Geometry &G = a.geo;
-  const uint32_t R = G.R, N = G.N, L = G.L, P = G.plane;
+  const uint32_t R = G.R, N = G.N, L = G.L, lgL = a.lg_L;
+  const uint32_t lgP = (DIM == 3 ? 2u : 1u) * lgL;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const FusedLayout F = fused_layout(R, N, DIM);
   uint32_t *thr = reinterpret_cast<uint32_t *>(smem + F.thr);
@@ -417,19 +528,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
     acc[2u * q] = 0;
     acc[2u * q + 1u] = 0;
   }
-  {
-    const uint32_t words = (R * N) >> 3;
-    const uint2 *src = reinterpret_cast<const uint2 *>(a.spins);
-    for (uint32_t q = tid; q < words; q += nt) reinterpret_cast<uint2 *>(sp)[q] = src[q];
-    if (DIM == 3) {
-      const uint2 *b = reinterpret_cast<const uint2 *>(a.st.bonds);
-      for (uint32_t q = tid; q < (3u * N) >> 3; q += nt) reinterpret_cast<uint2 *>(bx)[q] = b[q];
-    }
-  }
+  unpack_tile(sp, a.spins, 0u, (R * N) >> 5, 0xFFFFFFFFu, tid, nt);
+  if (DIM == 3) unpack_tile(bx, a.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
   __syncthreads();
 
-  const uint32_t gmask = G.gpr - 1u, rmask = G.rows - 1u, imask = (N >> 3) - 1u;
-  const uint32_t shp = a.lg_gpr + a.lg_rows;
+  const uint32_t smask = (1u << a.lg_spr) - 1u, rmask = G.rows - 1u, imask = (1u << a.lg_items) - 1u;
+  const uint32_t shp = a.lg_spr + a.lg_rows;
   const uint32_t items = R << a.lg_items;
   uint32_t rec = a.sch.rec_base, e = a.sch.ex_step;
   for (uint32_t j = 0; j < a.sch.nsw; ++j) {
@@ -442,29 +546,33 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
         const uint32_t li = q & imask;
         if (w != cur) {
           if (cur != 0xFFFFFFFFu) {
-            atomicAdd(&acc[2u * cur], a.z2 * t.n - 4 * (t.sc - 8 * t.sb));
+            atomicAdd(&acc[2u * cur], a.z2 * t.n - (t.sc - 32 * t.sb));
             atomicAdd(&acc[2u * cur + 1u], 4 * t.sb - 2 * t.n);
           }
           cur = w;
           t = {0, 0, 0};
         }
-        const uint32_t g = li & gmask;
-        const uint32_t y = (li >> a.lg_gpr) & rmask;
+        const uint32_t g0 = (li & smask) * V;
+        const uint32_t y = (li >> a.lg_spr) & rmask;
         const uint32_t pl = li >> shp;
         const uint32_t pu = (pl + L - 1u) & (L - 1u);
         const uint32_t pd = (pl + 1u) & (L - 1u);
         const uint32_t off = (c + pl + (DIM == 3 ? y : 0u)) & 1u;
         const uint32_t slot = sof[w];
-        const uint32_t ctr0 = ((pl << a.lg_rows) + y) * G.gpr + g;
-        const Words r = philox(ctr0, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+        const uint32_t ctr0 = (((pl << a.lg_rows) + y) << (lgL - 3u)) + g0;
+        Words r[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
         uint8_t *wsp = sp + (size_t)w * N;
         if (DIM == 2)
-          group2d(wsp + pl * P, wsp + pu * P, wsp + pd * P, g, L, off, r, thr + slot * kClasses, t);
+          span2d<V>(wsp + (pl << lgP), wsp + (pu << lgP), wsp + (pd << lgP), g0, L, off, r,
+                    thr + slot * kClasses, t);
         else
-          group3d(wsp, bx, by, bz, P, pl, pu, pd, y, g, L, off, r, thr + slot * kClasses, t);
+          span3d<V>(wsp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, thr + slot * kClasses, t);
       }
       if (cur != 0xFFFFFFFFu) {
-        atomicAdd(&acc[2u * cur], a.z2 * t.n - 4 * (t.sc - 8 * t.sb));
+        atomicAdd(&acc[2u * cur], a.z2 * t.n - (t.sc - 32 * t.sb));
         atomicAdd(&acc[2u * cur + 1u], 4 * t.sb - 2 * t.n);
       }
       __syncthreads();
@@ -491,11 +599,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
     __syncthreads();
   }
 
-  {
-    const uint32_t words = (R * N) >> 3;
-    uint2 *dst = reinterpret_cast<uint2 *>(a.spins);
-    for (uint32_t q = tid; q < words; q += nt) dst[q] = reinterpret_cast<const uint2 *>(sp)[q];
-  }
+  pack_tile(a.spins, sp, (R * N) >> 5, tid, nt);
   for (uint32_t q = tid; q < R; q += nt) {
     a.st.walker_at[q] = wat[q];
     a.st.slot_of[q] = sof[q];
@@ -511,39 +615,48 @@ __global__ void k_exchange(DevState st, uint32_t R, Keys key, uint32_t e) {
 
 // Initial spins: site i of walker w takes word i mod 4 of block (i/4, w, 0, spin
 // purpose); top bit set = down.  upload: convert caller-provided +-1 bytes.
+// One thread per 32-site word of the packed lattice.
 __global__ void k_init_spins(DevState st, Geometry G, Keys key, uint32_t upload) {
-  const uint32_t quads = G.N >> 2;
-  const uint64_t total = (uint64_t)quads * G.R;
+  const uint32_t wpr = G.N >> 5;
+  const uint64_t total = (uint64_t)wpr * G.R;
   for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
        q += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t w = (uint32_t)(q / quads), i4 = (uint32_t)(q % quads);
-    uint32_t out;
+    const uint32_t w = (uint32_t)(q / wpr), i0 = 32u * (uint32_t)(q % wpr);
+    uint32_t bits = 0;
     if (upload) {
-      const uint32_t v = reinterpret_cast<const uint32_t *>(st.staging)[q];
-      out = (v >> 7) & 0x01010101u; // sign bit of each +-1 byte
+      const uint8_t *src = st.staging + (size_t)w * G.N + i0;
+      for (uint32_t j = 0; j < 32u; ++j) bits |= (uint32_t)((src[j] >> 7) & 1u) << j;
     } else {
-      const Words r = philox(i4, w, 0u, kPurposeSpin, key.k0, key.k1);
-      out = (r.x >> 31) | ((r.y >> 31) << 8) | ((r.z >> 31) << 16) | ((r.w >> 31) << 24);
+#pragma unroll
+      for (uint32_t j = 0; j < 8u; ++j) {
+        const Words r = philox((i0 >> 2) + j, w, 0u, kPurposeSpin, key.k0, key.k1);
+        bits |= ((r.x >> 31) | ((r.y >> 31) << 1) | ((r.z >> 31) << 2) | ((r.w >> 31) << 3)) << (4u * j);
+      }
     }
-    reinterpret_cast<uint32_t *>(st.spins[0])[q] = out;
+    st.spins[0][q] = bits;
   }
 }
 
-// EA couplings: bond b = 3 i + d takes word b mod 4 of block (b/4, 0, 0, bond purpose).
+// EA couplings: bond b = 3 i + d takes word b mod 4 of block (b/4, 0, 0, bond
+// purpose); stored as bit-packed planes [3][N], bit set = J -1.
 __global__ void k_init_bonds(DevState st, Geometry G, Keys key, uint32_t upload) {
-  const uint32_t total = 3u * G.N;
+  const uint32_t wpr = G.N >> 5, total = 3u * wpr;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < total; q += gridDim.x * blockDim.x) {
-    const uint32_t d = q / G.N, i = q % G.N;
-    uint8_t v;
-    if (upload) {
-      v = (uint8_t)(((uint32_t)st.staging[q] >> 7) & 1u);
-    } else {
-      const uint32_t b = 3u * i + d;
-      const Words r = philox(b >> 2, 0u, 0u, kPurposeBond, key.b0, key.k1);
-      const uint32_t word = (b & 3u) == 0 ? r.x : (b & 3u) == 1 ? r.y : (b & 3u) == 2 ? r.z : r.w;
-      v = (uint8_t)(word >> 31);
+    const uint32_t d = q / wpr, i0 = 32u * (q % wpr);
+    uint32_t bits = 0;
+    for (uint32_t j = 0; j < 32u; ++j) {
+      uint32_t v;
+      if (upload) {
+        v = (st.staging[(size_t)d * G.N + i0 + j] >> 7) & 1u;
+      } else {
+        const uint32_t b = 3u * (i0 + j) + d;
+        const Words r = philox(b >> 2, 0u, 0u, kPurposeBond, key.b0, key.k1);
+        const uint32_t word = (b & 3u) == 0 ? r.x : (b & 3u) == 1 ? r.y : (b & 3u) == 2 ? r.z : r.w;
+        v = word >> 31;
+      }
+      bits |= v << j;
     }
-    st.bonds[q] = v;
+    st.bonds[q] = bits;
   }
 }
 
@@ -564,25 +677,30 @@ __global__ void k_reset(DevState st, Geometry G) {
   }
 }
 
+__device__ __forceinline__ uint32_t bit_at(const uint32_t *words, uint32_t i) {
+  return (words[i >> 5] >> (i & 31u)) & 1u;
+}
+
 // Full recount of E_int and M of every walker from spin buffer cur.
 template <int DIM>
 __global__ void k_recount(DevState st, Geometry G, uint32_t cur) {
   const uint32_t w = blockIdx.y;
-  const uint8_t *sp = st.spins[cur] + (size_t)w * G.N;
+  const uint32_t *sp = st.spins[cur] + (size_t)w * (G.N >> 5);
   const uint32_t L = G.L;
   int e = 0, m = 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < G.N; i += gridDim.x * blockDim.x) {
     const uint32_t x = i & (L - 1u), y = (i / L) & (L - 1u);
-    const uint32_t bi = sp[i];
+    const uint32_t bi = bit_at(sp, i);
     const uint32_t jx = i - x + ((x + 1u) & (L - 1u));
     const uint32_t jy = i - y * L + ((y + 1u) & (L - 1u)) * L;
-    uint32_t ux = bi ^ sp[jx], uy = bi ^ sp[jy];
+    uint32_t ux = bi ^ bit_at(sp, jx), uy = bi ^ bit_at(sp, jy);
     if (DIM == 3) {
       const uint32_t z = i / (L * L);
       const uint32_t jz = i - z * L * L + ((z + 1u) & (L - 1u)) * L * L;
-      ux ^= st.bonds[i];
-      uy ^= st.bonds[G.N + i];
-      const uint32_t uz = bi ^ sp[jz] ^ st.bonds[2u * G.N + i];
+      const uint32_t nw = G.N >> 5;
+      ux ^= bit_at(st.bonds, i);
+      uy ^= bit_at(st.bonds + nw, i);
+      const uint32_t uz = bi ^ bit_at(sp, jz) ^ bit_at(st.bonds + 2u * nw, i);
       e += 2 * (int)uz - 1; // bond energy -J s s = +1 if unsatisfied, -1 if satisfied
     }
     e += 2 * (int)(ux + uy) - 2;
@@ -609,6 +727,23 @@ hipError_t allow_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+template <int DIM, int V>
+hipError_t launch_tiled_v(const TiledArgs &a, uint32_t tiles, uint32_t R, uint32_t threads,
+                          size_t lds, hipStream_t stream) {
+  hipError_t err = allow_lds(k_tiled<DIM, V>, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_tiled<DIM, V>), dim3(tiles, R), dim3(threads), lds, stream, a);
+  return hipGetLastError();
+}
+
+template <int DIM, int V>
+hipError_t launch_fused_v(const FusedArgs &a, uint32_t threads, size_t lds, hipStream_t stream) {
+  hipError_t err = allow_lds(k_fused<DIM, V>, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_fused<DIM, V>), dim3(1), dim3(threads), lds, stream, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 size_t max_lds_bytes() { return 160u * 1024u - 1024u; }
@@ -622,7 +757,7 @@ size_t fused_lds_bytes(const Geometry &g) { return fused_layout(g.R, g.N, g.dim)
 
 hipError_t launch_init_spins(const DevState &st, const Geometry &g, const Keys &k, bool upload,
                              hipStream_t stream) {
-  const uint64_t total = (uint64_t)(g.N >> 2) * g.R;
+  const uint64_t total = (uint64_t)(g.N >> 5) * g.R;
   const uint32_t blocks = (uint32_t)std::min<uint64_t>((total + 255) / 256, 65535);
   hipLaunchKernelGGL(k_init_spins, dim3(blocks), dim3(256), 0, stream, st, g, k,
                      upload ? 1u : 0u);
@@ -631,7 +766,7 @@ hipError_t launch_init_spins(const DevState &st, const Geometry &g, const Keys &
 
 hipError_t launch_init_bonds(const DevState &st, const Geometry &g, const Keys &k, bool upload,
                              hipStream_t stream) {
-  const uint32_t blocks = std::min<uint32_t>((3u * g.N + 255u) / 256u, 65535u);
+  const uint32_t blocks = std::min<uint32_t>((3u * (g.N >> 5) + 255u) / 256u, 65535u);
   hipLaunchKernelGGL(k_init_bonds, dim3(blocks), dim3(256), 0, stream, st, g, k,
                      upload ? 1u : 0u);
   return hipGetLastError();
@@ -659,6 +794,10 @@ hipError_t launch_exchange(const DevState &st, const Geometry &g, const Keys &k,
   return hipGetLastError();
 }
 
+uint32_t span_groups(const Geometry &g) {
+  return std::min<uint32_t>(g.gpr, g.dim == 3 ? 2u : 4u);
+}
+
 hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
                         uint32_t tile_planes, uint32_t halo, uint32_t threads,
                         const Schedule &sch, hipStream_t stream) {
@@ -671,20 +810,19 @@ hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, ui
   a.halo = halo;
   a.src = st.spins[cur];
   a.dst = halo ? st.spins[cur ^ 1u] : st.spins[cur];
-  a.lg_gpr = ilog2(g.gpr);
+  const uint32_t V = span_groups(g);
+  a.lg_L = ilog2(g.L);
+  a.lg_spr = ilog2(g.gpr / V);
   a.lg_rows = ilog2(g.rows);
   a.z2 = g.dim == 3 ? 12 : 8;
   const uint32_t tiles = (g.L + a.H - 1u) / a.H;
   const size_t lds = tiled_lds_bytes(g, a.H, halo);
-  hipError_t err;
-  if (g.dim == 3) {
-    if ((err = allow_lds(k_tiled<3>, lds)) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_tiled<3>, dim3(tiles, g.R), dim3(threads), lds, stream, a);
-  } else {
-    if ((err = allow_lds(k_tiled<2>, lds)) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_tiled<2>, dim3(tiles, g.R), dim3(threads), lds, stream, a);
-  }
-  return hipGetLastError();
+  if (g.dim == 3)
+    return V == 2 ? launch_tiled_v<3, 2>(a, tiles, g.R, threads, lds, stream)
+                  : launch_tiled_v<3, 1>(a, tiles, g.R, threads, lds, stream);
+  return V == 4 ? launch_tiled_v<2, 4>(a, tiles, g.R, threads, lds, stream)
+       : V == 2 ? launch_tiled_v<2, 2>(a, tiles, g.R, threads, lds, stream)
+                : launch_tiled_v<2, 1>(a, tiles, g.R, threads, lds, stream);
 }
 
 hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
@@ -695,20 +833,19 @@ hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, ui
   a.key = k;
   a.sch = sch;
   a.spins = st.spins[cur];
-  a.lg_gpr = ilog2(g.gpr);
+  const uint32_t V = span_groups(g);
+  a.lg_L = ilog2(g.L);
+  a.lg_spr = ilog2(g.gpr / V);
   a.lg_rows = ilog2(g.rows);
-  a.lg_items = ilog2(g.N >> 3);
+  a.lg_items = ilog2(g.N / (8u * V));
   a.z2 = g.dim == 3 ? 12 : 8;
   const size_t lds = fused_lds_bytes(g);
-  hipError_t err;
-  if (g.dim == 3) {
-    if ((err = allow_lds(k_fused<3>, lds)) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_fused<3>, dim3(1), dim3(threads), lds, stream, a);
-  } else {
-    if ((err = allow_lds(k_fused<2>, lds)) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_fused<2>, dim3(1), dim3(threads), lds, stream, a);
-  }
-  return hipGetLastError();
+  if (g.dim == 3)
+    return V == 2 ? launch_fused_v<3, 2>(a, threads, lds, stream)
+                  : launch_fused_v<3, 1>(a, threads, lds, stream);
+  return V == 4 ? launch_fused_v<2, 4>(a, threads, lds, stream)
+       : V == 2 ? launch_fused_v<2, 2>(a, threads, lds, stream)
+                : launch_fused_v<2, 1>(a, threads, lds, stream);
 }
 
 }  // namespace ptmi

@@ -259,7 +259,10 @@ class Simulation:
 
     def close(self):
         if getattr(self, "ctx", None):
-            pt_destroy(self.ctx)
+            try:
+                pt_destroy(self.ctx)
+            except TypeError:  # interpreter shutdown already tore down ctypes
+                pass
             self.ctx = None
 
     def __del__(self):

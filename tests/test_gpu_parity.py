@@ -61,9 +61,7 @@ def test_ising16_full_run_auto_plan(pt, oracle_mod):
 @pytest.mark.parametrize("plan", [
     dict(mode=TILED, tile_planes=16, sweeps_per_launch=1, block_threads=64),    # whole replica
     dict(mode=TILED, tile_planes=16, sweeps_per_launch=3, block_threads=256),
-    dict(mode=TILED, tile_planes=4, sweeps_per_launch=1, block_threads=64),     # halo tiles
-    dict(mode=TILED, tile_planes=5, sweeps_per_launch=2, block_threads=128),    # ragged last tile
-    dict(mode=TILED, tile_planes=3, sweeps_per_launch=4, block_threads=1024),
+    dict(mode=TILED, tile_planes=32, sweeps_per_launch=8, block_threads=1024),
     dict(mode=FUSED, block_threads=64),
     dict(mode=FUSED, block_threads=1024),
 ])
@@ -71,6 +69,20 @@ def test_ising16_every_plan_is_identical(pt, oracle_mod, plan):
     w = ising16()
     run_case(pt, oracle_mod, 0, w.L, w.R, w.beta, w.seed, 200, w.exchange_every, plan=plan,
              tag="ising16-plan")
+
+
+@pytest.mark.parametrize("plan", [
+    dict(mode=TILED, tile_planes=4, sweeps_per_launch=1, block_threads=64),     # halo tiles
+    dict(mode=TILED, tile_planes=5, sweeps_per_launch=2, block_threads=128),    # ragged last tile
+    dict(mode=TILED, tile_planes=3, sweeps_per_launch=4, block_threads=1024),
+    dict(mode=TILED, tile_planes=8, sweeps_per_launch=3, block_threads=256),
+    dict(mode=TILED, tile_planes=32, sweeps_per_launch=5, block_threads=512),   # whole replica
+    dict(mode=FUSED, block_threads=256),
+])
+def test_ising32_halo_plans(pt, oracle_mod, plan):
+    """Halo tiles (2 rows per sweep per side), ragged tails, 1..5 sweeps per launch."""
+    beta = beta_geometric(0.20, 0.60, 8)
+    run_case(pt, oracle_mod, 0, 32, 8, beta, 13, 120, 10, plan=plan, tag="ising32-plan")
 
 
 @pytest.mark.parametrize("plan", [

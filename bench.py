@@ -24,13 +24,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X: 256 compute units x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 VALU lane
-# slots per second for 32-bit integer operations (a 32x32->64 multiply issues
-# at a quarter of that rate and counts as 4 slots).
+# slots per second for 32-bit integer operations.  On gfx950 the 32x32->64
+# multiply-add (v_mad_u64_u32) and the three-input XOR (v_bitop3_b32) both issue
+# at that full rate (measured: 34.8e12 and 33.4e12 lane ops/s in dependent-free
+# probe loops).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # Algorithmic VALU slots per flip attempt: a quarter of one Philox4x32-10 block
-# (20 32x32->64 multiplies at 4 slots + 20 three-way XORs = 100 slots per
-# block) plus the stencil and decision (2D: 10, 3D +-J: 20).
-SLOTS_PER_ATTEMPT = {2: 25 + 10, 3: 25 + 20}
+# (20 multiplies + 20 three-input XORs = 40 slots per block of 4 draws) plus the
+# stencil and decision (2D: 10 -- neighbour sum, spin product, class, threshold
+# compare, conditional flip, E/M update; 3D +-J: 20 with the six couplings).
+SLOTS_PER_ATTEMPT = {2: 10 + 10, 3: 10 + 20}
 
 
 def parse():
@@ -44,6 +47,9 @@ def parse():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 64 MiB device-to-device copy (a kernel of known "
+                         "traffic, to scale HBM counters)")
     return ap.parse_args()
 
 
@@ -120,12 +126,29 @@ def main():
     avg_ms = sum(durs) / len(durs)
     slots = SLOTS_PER_ATTEMPT[w.dim] * per_launch * w.attempts_per_sweep
     achieved = slots / (avg_ms * 1e-3) / 1e12
+    # algorithmic HBM bytes of one launch: every walker's packed lattice read
+    # (interior plus 2 halo planes per sweep per side and tile) and written once
+    tiles = -(-w.L // plan["tile_planes"]) if plan["mode"] == pt.PT_PLAN_TILED else 1
+    halo_planes = 2 * 2 * per_launch * tiles if tiles > 1 else 0
+    plane_bits = w.L ** (w.dim - 1)
+    hbm_bytes = w.R * ((w.L + halo_planes) * plane_bits + w.L * plane_bits) / 8
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 VALU lane slots)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": None, "kernel": "k_tiled" if plan["mode"] == pt.PT_PLAN_TILED else "k_fused",
+                "slots_per_attempt": SLOTS_PER_ATTEMPT[w.dim],
                 "avg_launch_ms": round(avg_ms, 5), "median_launch_ms": round(durs[len(durs) // 2], 5),
                 "sweeps_per_launch": per_launch,
-                "attempts_per_s_in_kernel": per_launch * w.attempts_per_sweep / (avg_ms * 1e-3)}
+                "attempts_per_s_in_kernel": per_launch * w.attempts_per_sweep / (avg_ms * 1e-3),
+                "hbm_algorithmic_bytes_per_launch": int(hbm_bytes),
+                "hbm_algorithmic_GBps": round(hbm_bytes / (avg_ms * 1e-3) / 1e9, 1)}
+
+    if args.copy_calibration:
+        a = torch.empty(64 << 20, dtype=torch.uint8, device="cuda:0").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     obs = sim.observables(series=False)
     assert obs["sweeps_done"] == total_sweeps - roof_launches * 8 + roof_launches * per_launch

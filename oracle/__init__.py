@@ -21,14 +21,20 @@ ISING2D = 0
 EA3D = 1
 
 
+def compile_source(src: str, out: str) -> str:
+    """gcc one oracle source file into a shared library (FP contraction off)."""
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.check_call([
+        "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+        "-shared", "-Wall", "-Wextra", "-I", _HERE, "-o", tmp, src, "-lm"])
+    os.replace(tmp, out)
+    return out
+
+
 def build(force: bool = True) -> str:
-    """Compile oracle.c into liboracle.so (FP contraction off, no fast-math)."""
+    """Compile oracle.c into liboracle.so."""
     if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call([
-            "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-            "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_PATH)
+        compile_source(_SRC, _LIB_PATH)
     return _LIB_PATH
 
 
@@ -42,15 +48,16 @@ class _Config(C.Structure):
     ]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
+def lib(path: str = None):
+    """The loaded oracle library (the default build, or another compiled copy)."""
+    path = path or _LIB_PATH
+    if path not in _libs:
+        if path == _LIB_PATH and not os.path.exists(_LIB_PATH):
             build()
-        L = C.CDLL(_LIB_PATH)
+        L = C.CDLL(path)
         vp = C.c_void_p
         L.orc_create.restype = vp
         L.orc_create.argtypes = [C.POINTER(_Config)]
@@ -71,8 +78,8 @@ def lib():
         L.orc_flip_accept.argtypes = [C.c_double, C.c_double, C.c_uint32]
         L.orc_swap_accept.restype = C.c_int
         L.orc_swap_accept.argtypes = [C.c_double, C.c_double, C.c_double, C.c_uint32]
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 def _ptr(a):
@@ -99,9 +106,12 @@ def swap_accept(beta_k: float, beta_k1: float, dE: float, r: int) -> bool:
 class Oracle:
     """One parallel-tempering simulation held by the C oracle."""
 
+    lib_path = None  # subclasses bound to another compiled copy override this
+
     def __init__(self, model, L, R, beta, J=1.0, h=0.0, seed=1, stream_id=0,
                  coupling_seed=None, init_spins=None, couplings=None,
                  record_every=0, max_records=0):
+        self._L = lib(self.lib_path)
         self.model, self.L, self.R = int(model), int(L), int(R)
         self.dim = 3 if self.model == EA3D else 2
         self.N = self.L ** self.dim
@@ -123,64 +133,64 @@ class Oracle:
             keep.append(a)
             cfg.couplings = a.ctypes.data_as(C.POINTER(C.c_int8))
         cfg.record_every, cfg.max_records = int(record_every), int(max_records)
-        self._st = lib().orc_create(C.byref(cfg))
+        self._st = self._L.orc_create(C.byref(cfg))
         if not self._st:
             raise ValueError("oracle rejected the configuration")
 
     def __del__(self):
         st = getattr(self, "_st", None)
         if st:
-            lib().orc_destroy(st)
+            self._L.orc_destroy(st)
             self._st = None
 
     # -- dynamics -----------------------------------------------------------
     def sweep(self, n=1):
-        lib().orc_sweep(self._st, int(n))
+        self._L.orc_sweep(self._st, int(n))
 
     def exchange(self):
-        lib().orc_exchange(self._st)
+        self._L.orc_exchange(self._st)
 
     def run(self, n, every=0):
-        lib().orc_run(self._st, int(n), int(every))
+        self._L.orc_run(self._st, int(n), int(every))
 
     # -- state ----------------------------------------------------------------
     @property
     def sweeps_done(self):
-        return int(lib().orc_sweeps_done(self._st))
+        return int(self._L.orc_sweeps_done(self._st))
 
     @property
     def exchanges_done(self):
-        return int(lib().orc_exchanges_done(self._st))
+        return int(self._L.orc_exchanges_done(self._st))
 
     @property
     def n_records(self):
-        return int(lib().orc_n_records(self._st))
+        return int(self._L.orc_n_records(self._st))
 
     def spins(self):
         out = np.empty((self.R, self.N), dtype=np.int8)
-        lib().orc_get_spins(self._st, _ptr(out))
+        self._L.orc_get_spins(self._st, _ptr(out))
         return out
 
     def couplings(self):
         out = np.empty((3, self.N), dtype=np.int8)
-        lib().orc_get_couplings(self._st, _ptr(out))
+        self._L.orc_get_couplings(self._st, _ptr(out))
         return out
 
     def labels(self):
         out = np.empty(self.R, dtype=np.uint32)
-        lib().orc_get_labels(self._st, _ptr(out))
+        self._L.orc_get_labels(self._st, _ptr(out))
         return out
 
     def energy(self):
         E = np.empty(self.R, dtype=np.int64)
         M = np.empty(self.R, dtype=np.int64)
-        lib().orc_get_energy(self._st, _ptr(E), _ptr(M))
+        self._L.orc_get_energy(self._st, _ptr(E), _ptr(M))
         return E, M
 
     def recount(self):
         E = np.empty(self.R, dtype=np.int64)
         M = np.empty(self.R, dtype=np.int64)
-        lib().orc_recount(self._st, _ptr(E), _ptr(M))
+        self._L.orc_recount(self._st, _ptr(E), _ptr(M))
         return E, M
 
     def series(self):
@@ -188,12 +198,34 @@ class Oracle:
         E = np.empty((n, self.R), dtype=np.int32)
         M = np.empty((n, self.R), dtype=np.int32)
         if n:
-            lib().orc_get_series(self._st, _ptr(E), _ptr(M))
+            self._L.orc_get_series(self._st, _ptr(E), _ptr(M))
         return E, M
 
     def swaps(self):
         n = max(self.R - 1, 0)
         att = np.zeros(max(n, 1), dtype=np.uint64)
         acc = np.zeros(max(n, 1), dtype=np.uint64)
-        lib().orc_get_swaps(self._st, _ptr(att), _ptr(acc))
+        self._L.orc_get_swaps(self._st, _ptr(att), _ptr(acc))
         return att[:n], acc[:n]
+
+
+def bind(lib_path: str):
+    """The oracle API bound to another compiled copy of oracle.c."""
+    from types import SimpleNamespace
+
+    class _Bound(Oracle):
+        pass
+    _Bound.lib_path = lib_path
+    L = lib(lib_path)
+
+    def _philox(ctr, key):
+        c = np.ascontiguousarray(ctr, dtype=np.uint32)
+        k = np.ascontiguousarray(key, dtype=np.uint32)
+        out = np.zeros(4, dtype=np.uint32)
+        L.orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+        return out
+
+    return SimpleNamespace(
+        Oracle=_Bound, philox4x32_10=_philox, ISING2D=ISING2D, EA3D=EA3D,
+        flip_accept=lambda b, dE, r: bool(L.orc_flip_accept(b, dE, r)),
+        swap_accept=lambda bk, bk1, dE, r: bool(L.orc_swap_accept(bk, bk1, dE, r)))

@@ -19,7 +19,14 @@
  *   - Swap acceptance (Sec. 3): P = e^x / (1 + e^x) with x = dBeta * dE, where
  *     dBeta = beta_k - beta_{k+1} and dE = E_a - E_b for the states a, b held by
  *     slots k, k+1; evaluated as 1/(1+exp(-x)), saturated beyond |x| >= 32 ln 2;
- *     accepted iff r < P * 2^32.
+ *     accepted iff r < P * 2^32.  The paper's model has no field; with a field
+ *     (2D, h != 0) dE = J dE_int - h dM splits into x = x1 + y with
+ *     x1 = dBeta J dE_int and y = -dBeta h dM, and the swap is accepted iff the
+ *     logistic test on x1 passes and a Metropolis test min(1, e^y) passes.  The
+ *     latter is a product of independent tests, one per set binary digit j of
+ *     |dM|/2, each accepted with probability exp(-2^(j+1) |dBeta h|).  The ratio
+ *     of forward to reverse acceptance stays e^(x1 + y) (detailed balance), and
+ *     for h = 0 the rule is the logistic test alone.
  *   - Pairing (Sec. 3): exchange step e pairs slots (k, k+1) with k = e mod 2,
  *     e mod 2 + 2, ...; each slot takes part in at most one pair per step.
  *   - Checkerboard order: colour c = (x + y [+ z]) mod 2; a sweep updates every
@@ -30,6 +37,7 @@
  *              key (seed, stream_id), ctr (j/4, s, k, c),        word j mod 4
  *       swap   for pair (k, k+1) at exchange step e:
  *              key (seed, stream_id), ctr (k, e, 0, 1<<8),        word 0
+ *              field digit j: ctr (k, e, 1 + j/4, 1<<8),          word j mod 4
  *       spin   initial value of site i in slot k:
  *              key (seed, stream_id), ctr (i/4, k, 0, 2<<8),      word i mod 4
  *       bond   EA coupling b = 3 i + d (d = 0,1,2 for +x,+y,+z):
@@ -92,6 +100,13 @@ static uint32_t draw(uint32_t k0, uint32_t k1, uint32_t c0, uint32_t c1, uint32_
 /* Eq. (1) with the Boltzmann target of Eq. (2): A = min(1, exp(-beta dE)). */
 int orc_flip_accept(double beta, double dE, uint32_t r) {
   double p = (dE <= 0.0) ? 1.0 : exp(-(beta * dE));
+  return (double)r < ldexp(p, 32);
+}
+
+/* Field factor of a swap, one binary digit j of |dM|/2: accept with
+ * probability exp(-2^(j+1) |dBeta h|). */
+int orc_field_digit_accept(double dbeta_h_abs, int j, uint32_t r) {
+  double p = exp(-(dbeta_h_abs * ldexp(2.0, j)));
   return (double)r < ldexp(p, 32);
 }
 
@@ -281,11 +296,26 @@ void orc_exchange(orc_state *st) {
   for (int k = (int)(e & 1u); k + 1 < R; k += 2) {
     uint32_t r = draw(cfg->seed, cfg->stream_id, (uint32_t)k, e, 0u, PURPOSE_SWAP << 8, 0);
     int64_t dEint = st->E[k] - st->E[k + 1];
-    double dE = (st->dim == 2)
-                    ? cfg->J * (double)dEint - cfg->h * (double)(st->M[k] - st->M[k + 1])
-                    : (double)dEint;
+    double dE = (st->dim == 2) ? cfg->J * (double)dEint : (double)dEint;
+    int accept = orc_swap_accept(st->beta[k], st->beta[k + 1], dE, r);
+    if (accept && st->dim == 2 && cfg->h != 0.0) {
+      /* field part y = -dBeta h dM; Metropolis min(1, e^y) as a product over digits */
+      double dbeta = st->beta[k] - st->beta[k + 1];
+      int64_t dM = st->M[k] - st->M[k + 1];
+      double y = (dbeta * -cfg->h) * (double)dM;
+      if (y < 0.0) {
+        double a = fabs(dbeta * cfg->h);
+        uint64_t n = (uint64_t)(dM < 0 ? -dM : dM) / 2u;
+        for (int j = 0; n >> j; ++j)
+          if ((n >> j) & 1u) {
+            uint32_t rj = draw(cfg->seed, cfg->stream_id, (uint32_t)k, e, 1u + (uint32_t)(j >> 2),
+                               PURPOSE_SWAP << 8, (unsigned)(j & 3));
+            if (!orc_field_digit_accept(a, j, rj)) { accept = 0; break; }
+          }
+      }
+    }
     st->att[k]++;
-    if (orc_swap_accept(st->beta[k], st->beta[k + 1], dE, r)) {
+    if (accept) {
       int8_t *a = st->spins + (int64_t)k * st->N, *b = a + st->N;
       memcpy(tmp, a, (size_t)st->N);
       memcpy(a, b, (size_t)st->N);

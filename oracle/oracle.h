@@ -81,6 +81,8 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 int orc_flip_accept(double beta, double dE, uint32_t r);
 /* Replica-exchange decision for slots (k, k+1): x = (beta_k - beta_k1) * dE, dE = E_a - E_b. */
 int orc_swap_accept(double beta_k, double beta_k1, double dE, uint32_t r);
+/* Field factor of a swap for binary digit j of |dM|/2 (2D with h != 0). */
+int orc_field_digit_accept(double dbeta_h_abs, int j, uint32_t r);
 
 #ifdef __cplusplus
 }

@@ -243,6 +243,29 @@ def test_swaps_preserve_each_slot_distribution(oracle_mod):
             assert abs(f - p_exact[levels == lev][0]) < 5 * sf + 1e-3
 
 
+@pytest.mark.parametrize("h", [0.3, -0.2])
+def test_field_swaps_preserve_each_slot_distribution(oracle_mod, h):
+    """With a field, flips (Eq. 1 with E = -J sum ss - h sum s) and the factorised
+    swap rule keep every slot on its exact Boltzmann law: <E_int>, <M>, <|M|>."""
+    beta = np.array([0.25, 0.40, 0.55])
+    E_all, M_all = _enumerate_ising2d(4)
+    n = 200_000
+    o = oracle_mod.Oracle(ISING2D, 4, 3, beta, h=h, seed=23, record_every=1, max_records=n)
+    o.run(n, every=1)
+    att, acc = o.swaps()
+    assert np.all(acc > 0.05 * att)
+    Es, Ms = o.series()
+    for k in range(3):
+        logw = -beta[k] * (E_all - h * M_all)
+        wts = np.exp(logw - logw.max())
+        Z = wts.sum()
+        for obs, exact in ((Es[1000:, k], (E_all * wts).sum() / Z),
+                           (Ms[1000:, k], (M_all * wts).sum() / Z),
+                           (np.abs(Ms[1000:, k]), (np.abs(M_all) * wts).sum() / Z)):
+            m, se = _block_stats(obs, 100)
+            assert abs(m - exact) < 5 * se, (k, m, exact, se)
+
+
 # ---------------------------------------------------------------------------
 # Closed forms for the infinite 2D Ising model (Onsager 1944, Yang 1952).
 # ---------------------------------------------------------------------------

@@ -38,7 +38,9 @@
  * Errors: every pt_status function returns PT_OK (0) or a negative code and
  * never throws.  Configuration errors are detected synchronously (PT_EINVAL).
  * A failed HIP call (launch or copy) returns PT_EDEVICE; after PT_EDEVICE the
- * context is poisoned and every later call returns PT_ESTATE.  pt_last_error()
+ * context is poisoned and every later call returns PT_ESTATE.  A persistent
+ * launch whose pairwise exchange wait exceeds its bound stops early and is
+ * reported as PT_EDEVICE by the next pt_observables.  pt_last_error()
  * returns a thread-local message describing the last failure of this thread.
  */
 #ifndef PT_H
@@ -69,11 +71,11 @@ typedef enum { PT_ISING2D = 0, PT_EA3D = 1 } pt_model;
 typedef struct {
   uint32_t abi_version;     /* must be PT_ABI_VERSION */
   uint32_t model;           /* pt_model */
-  uint32_t L;               /* linear size; multiple of 8, >= 8 */
+  uint32_t L;               /* linear size; power of two, 8 .. 16384 (2D), 8 .. 64 (EA) */
   uint32_t R;               /* replicas = temperature slots, 1 .. 4096 */
   const double *beta;       /* host [R], finite, >= 0, slot order; copied at create */
   double J;                 /* 2D coupling (ignored for EA) */
-  double h;                 /* 2D field; must be 0 (PT_EUNSUPPORTED otherwise) */
+  double h;                 /* 2D field (finite); ignored for EA */
   uint32_t seed;            /* Philox key word 0 (spins, flips, swaps) */
   uint32_t stream_id;       /* Philox key word 1 (0, or an instance id) */
   uint32_t coupling_seed;   /* Philox key word 0 of the EA couplings */
@@ -84,8 +86,21 @@ typedef struct {
 } pt_config;
 
 /* Launch plan: how the work is decomposed.  Any valid plan gives bit-identical
- * results.  Zero fields mean "choose automatically". */
-typedef enum { PT_PLAN_AUTO = 0, PT_PLAN_FUSED = 1, PT_PLAN_TILED = 2 } pt_plan_mode;
+ * results.  Zero fields mean "choose automatically".
+ *   FUSED       one workgroup holds every walker in LDS; whole schedules run in
+ *               one launch (small systems).
+ *   TILED       a workgroup per (tile of planes, walker); halo tiles, up to
+ *               PT_MAX_SWEEPS_PER_LAUNCH sweeps per launch; exchanges run in the
+ *               epilogue of the last workgroup.
+ *   PERSISTENT  one co-resident workgroup per walker keeps its lattice in LDS
+ *               for a whole pt_run call; exchange steps are decided pairwise
+ *               between neighbouring slots without a global barrier. */
+typedef enum {
+  PT_PLAN_AUTO = 0,
+  PT_PLAN_FUSED = 1,
+  PT_PLAN_TILED = 2,
+  PT_PLAN_PERSISTENT = 3
+} pt_plan_mode;
 typedef struct {
   uint32_t mode;              /* pt_plan_mode */
   uint32_t tile_planes;       /* TILED: rows (2D) or z-planes (3D) per workgroup tile */
@@ -112,10 +127,12 @@ typedef struct {
 } pt_obs;
 
 /* Device workspace needed for cfg, in bytes (0 and pt_last_error set if cfg is
- * invalid).  The workspace holds every piece of simulation state: two spin
- * buffers [R][N] (uint8, 0 = up, 1 = down), EA bond planes [3][N], flip
- * thresholds [R][16] (uint32), swap tables (uint64), walker/slot maps, per-walker
- * E_int and M, per-sweep accumulators, the record series and swap counters. */
+ * invalid).  The workspace holds every piece of simulation state: two
+ * bit-packed spin buffers [R][N/32] (uint32, bit set = down), bit-packed EA bond
+ * planes [3][N/32], flip thresholds [R][16] (uint32), swap tables (uint64),
+ * walker/slot maps, per-walker E_int and M, per-sweep accumulators, the record
+ * series, swap counters, exchange mailboxes, and (only when cfg uploads spins or
+ * couplings) a staging area of one byte per uploaded value. */
 size_t pt_workspace_bytes(const pt_config *cfg);
 
 /* Initialisation phase (Sec. 3): validate cfg, build the FP64 -> integer flip
@@ -125,8 +142,7 @@ size_t pt_workspace_bytes(const pt_config *cfg);
  * couplings, and compute the initial E_int and M (the "first iteration").
  * hip_stream is a hipStream_t (NULL = the null stream); all later work of the
  * context is ordered on it.  On success *out receives the context.
- * Errors: PT_EINVAL (cfg, alignment), PT_ENOMEM (ws_bytes too small),
- * PT_EUNSUPPORTED (h != 0), PT_EDEVICE. */
+ * Errors: PT_EINVAL (cfg, alignment), PT_ENOMEM (ws_bytes too small), PT_EDEVICE. */
 pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, size_t ws_bytes,
                     pt_ctx **out);
 
@@ -144,7 +160,10 @@ pt_status pt_sweep(pt_ctx *ctx, uint32_t n_sweeps);
 /* Execution phase, PT part (Sec. 3): one exchange step e with pair parity e mod 2:
  * for every slot k = e mod 2, e mod 2 + 2, ... with k+1 < R, the walkers a, b at
  * slots k, k+1 swap slots with probability e^x/(1+e^x), x = (beta_k - beta_k+1)
- * (E_a - E_b).  Then e += 1.  Asynchronous. */
+ * (E_a - E_b).  With a field (2D, h != 0) x splits into x1 = dBeta J dE_int and
+ * y = -dBeta h dM, and the swap needs the logistic test on x1 and a Metropolis
+ * test min(1, e^y), realised as one test per set binary digit of |dM|/2 (the
+ * paper's experiments have no field).  Then e += 1.  Asynchronous. */
 pt_status pt_exchange(pt_ctx *ctx);
 
 /* The paper's interval schedule (Sec. 3, Fig. 2): n_sweeps sweeps, and after
@@ -165,11 +184,42 @@ pt_status pt_observables(pt_ctx *ctx, pt_obs *obs);
  * swap table.  Buffers may be NULL. */
 pt_status pt_flip_thresholds(const pt_ctx *ctx, uint32_t *out_R_by_16);
 /* Swap threshold of pair k for energy difference E_a - E_b = 4*d: the number of
- * accepted 32-bit draws (accept iff r < T), 0 .. 2^32. */
+ * accepted 32-bit draws (accept iff r < T), 0 .. 2^32, for every d a lattice of
+ * this size can reach (|d| <= z N / 4, z = 2 dim); larger |d| return the value at
+ * the edge of the table. */
 pt_status pt_swap_threshold(const pt_ctx *ctx, uint32_t k, int64_t d, uint64_t *out_T);
 
 /* Free the host context (never the caller's workspace or stream). NULL is a no-op. */
 void pt_destroy(pt_ctx *ctx);
+
+/* ---- batched form: many independent instances advanced together ------------
+ * n instances, each a full pt_config (give each its own stream_id so that their
+ * random streams differ), share one workspace and advance in lockstep cycles:
+ * every cycle runs up to K sweeps of every active instance (K = a divisor of the
+ * exchange interval), then the exchange step of the instances whose interval
+ * ends, then a device-side counter update -- so the whole cycle is a fixed
+ * sequence of launches, captured once in a HIP graph and replayed.  The first
+ * cycles of a run time candidate decompositions (walkers per workgroup, block
+ * size) per lattice-size group and keep the fastest; decompositions never
+ * change results, so every instance is bit-identical to running it alone. */
+typedef struct pt_batch pt_batch;
+
+/* Workspace for the batch (the instances' workspaces plus the batch's tables). */
+size_t pt_batch_workspace_bytes(const pt_config *cfgs, uint32_t n);
+/* Create n instances (initialisation phase of each) in d_workspace (caller-owned,
+ * 256-byte aligned).  hip_stream orders the batch's work against the caller's. */
+pt_status pt_batch_create(const pt_config *cfgs, uint32_t n, void *hip_stream, void *d_workspace,
+                          size_t ws_bytes, pt_batch **out);
+/* Advance every instance by n_sweeps sweeps with an exchange step after every
+ * exchange_every-th sweep (0 = none).  Asynchronous on the caller's stream. */
+pt_status pt_batch_run(pt_batch *b, uint32_t n_sweeps, uint32_t exchange_every);
+/* Observables of instance i (synchronises). */
+pt_status pt_batch_observables(pt_batch *b, uint32_t i, pt_obs *obs);
+/* Decomposition chosen for lattice-size group g (0 .. groups-1): walkers per
+ * workgroup and block size; returns PT_EINVAL past the last group. */
+pt_status pt_batch_group_plan(const pt_batch *b, uint32_t g, uint32_t *L, uint32_t *walkers_per_wg,
+                              uint32_t *block_threads);
+void pt_batch_destroy(pt_batch *b);
 
 /* Thread-local message of the last failure on this thread ("" if none). */
 const char *pt_last_error(void);

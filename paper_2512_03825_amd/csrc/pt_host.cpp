@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -32,7 +34,10 @@ pt_status fail(pt_status st, const char *fmt, ...) {
 bool is_pow2(uint32_t v) { return v && !(v & (v - 1u)); }
 
 constexpr uint32_t kMaxR = 4096;
-constexpr uint32_t kFusedChunk = 4096;   // sweeps per fused launch
+constexpr uint32_t kFusedChunk = 4096;   // sweeps per fused or persistent launch
+// Polls of a partner's mailbox (each followed by a short sleep) before a
+// persistent launch gives up: orders of magnitude above any legitimate wait.
+constexpr uint32_t kSpinLimit = 1u << 24;
 constexpr size_t kAlign = 256;
 
 // Saturation of the logistic swap rule: beyond |x| >= 32 ln 2 the decision no
@@ -68,11 +73,13 @@ struct Tables {
   std::vector<uint32_t> off;  // [R]
   std::vector<uint32_t> D;    // [R]
   std::vector<uint64_t> sat;  // [R][2]
+  std::vector<uint64_t> field; // [R][kFieldDigits]
+  std::vector<int32_t> fsign;  // [R]
 };
 
 struct Layout {
   size_t spins[2], bonds, staging, flip, swap_tab, swap_off, swap_D, swap_sat, wat, sof, E, M,
-      acc3, att, acc, Es, Ms, counter, total;
+      acc3, att, acc, Es, Ms, counter, mailbox, field, fsign, total;
 };
 
 struct Derived {
@@ -95,8 +102,6 @@ pt_status derive(const pt_config *cfg, Derived *d) {
   if (!cfg->beta) return fail(PT_EINVAL, "beta is NULL");
   if (dim == 2 && !std::isfinite(cfg->J)) return fail(PT_EINVAL, "J is not finite");
   if (!std::isfinite(cfg->h)) return fail(PT_EINVAL, "h is not finite");
-  if (dim == 2 && cfg->h != 0.0)
-    return fail(PT_EUNSUPPORTED, "h != 0: replica exchange with a field is not implemented");
   d->z = 2u * dim;
   d->jscale = dim == 2 ? cfg->J : 1.0;
   const double dEmax = 2.0 * (std::fabs(d->jscale) * d->z + (dim == 2 ? std::fabs(cfg->h) : 0.0));
@@ -165,6 +170,9 @@ Layout layout(const pt_config *cfg, const Derived &d) {
   l.Es = take((size_t)cfg->max_records * R * 4);
   l.Ms = take((size_t)cfg->max_records * R * 4);
   l.counter = take(16);
+  l.mailbox = take(4 * R * 8);
+  l.field = take(R * kFieldDigits * 8);
+  l.fsign = take(R * 4);
   l.total = o;
   return l;
 }
@@ -198,6 +206,21 @@ void build_tables(const pt_config *cfg, const Derived &d, Tables *t) {
     t->sat[2 * k + 1] = rule((int64_t)D + 1);
   }
   if (t->swap.empty()) t->swap.push_back(0);
+  // Field factor of a swap (2D, h != 0): digit j of |dM|/2 passes with
+  // probability exp(-2^(j+1) |dBeta h|); sign of (dBeta * -h) decides when it applies.
+  t->field.assign((size_t)R * kFieldDigits, 1ull << 32);
+  t->fsign.assign(R, 0);
+  if (d.geo.dim == 2 && cfg->h != 0.0)
+    for (uint32_t k = 0; k + 1 < R; ++k) {
+      const double db = cfg->beta[k] - cfg->beta[k + 1];
+      const double c = db * -cfg->h;
+      t->fsign[k] = c > 0.0 ? 1 : (c < 0.0 ? -1 : 0);
+      const double a = std::fabs(db * cfg->h);
+      for (uint32_t j = 0; j < kFieldDigits; ++j) {
+        const double p = std::exp(-(a * std::ldexp(2.0, (int)j)));
+        t->field[(size_t)k * kFieldDigits + j] = (uint64_t)std::ceil(std::ldexp(p, 32));
+      }
+    }
 }
 
 uint32_t records_between(uint32_t every, uint64_t s0, uint64_t s1) {
@@ -239,6 +262,18 @@ pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
                   max_lds_bytes());
     return PT_OK;
   }
+  if (p.mode == PT_PLAN_PERSISTENT) {
+    if (c->cfg.h != 0.0 && g.dim == 2)
+      return fail(PT_EINVAL, "the persistent plan exchanges energies only; it needs h = 0");
+    if (persist_lds_bytes(g) > max_lds_bytes())
+      return fail(PT_EINVAL, "persistent plan needs %zu bytes of LDS per walker (max %zu)",
+                  persist_lds_bytes(g), max_lds_bytes());
+    const uint32_t cap = persist_max_workgroups(g, p.block_threads);
+    if (cap < g.R)
+      return fail(PT_EINVAL, "persistent plan needs %u co-resident workgroups, the device holds %u",
+                  g.R, cap);
+    return PT_OK;
+  }
   if (p.mode != PT_PLAN_TILED) return fail(PT_EINVAL, "unknown plan mode %u", p.mode);
   if (p.tile_planes < 1) return fail(PT_EINVAL, "tile_planes must be >= 1");
   if (p.sweeps_per_launch < 1 || p.sweeps_per_launch > kMaxSweepsPerLaunch)
@@ -269,6 +304,16 @@ pt_plan auto_plan(const pt_ctx *c) {
     p.tile_planes = g.L;
     p.sweeps_per_launch = 1;
     return p;
+  }
+  // Many walkers whose lattices fit a workgroup's LDS: one co-resident workgroup
+  // per walker for a whole run, exchanges decided pairwise (no launch per sweep).
+  if (g.R >= 128 && !(g.dim == 2 && c->cfg.h != 0.0)) {
+    pt_plan q{};
+    q.mode = PT_PLAN_PERSISTENT;
+    q.block_threads = 1024;
+    q.tile_planes = g.L;
+    q.sweeps_per_launch = 1;
+    if (check_plan(c, q) == PT_OK) return q;
   }
   p.mode = PT_PLAN_TILED;
   p.block_threads = 512;
@@ -317,12 +362,15 @@ pt_status advance(pt_ctx *c, uint32_t n, uint32_t every) {
     sch.ex_step = (uint32_t)c->exchanges;
     uint32_t nsw, nex = 0;
     hipError_t err;
-    if (c->plan.mode == PT_PLAN_FUSED) {
+    if (c->plan.mode == PT_PLAN_FUSED || c->plan.mode == PT_PLAN_PERSISTENT) {
       nsw = std::min(left, kFusedChunk);
       sch.nsw = nsw;
       sch.exchange_every = every;
       nex = records_between(every, c->sweeps, c->sweeps + nsw);
-      err = launch_fused(c->st, g, c->keys, c->cur, c->plan.block_threads, sch, c->stream);
+      err = c->plan.mode == PT_PLAN_FUSED
+                ? launch_fused(c->st, g, c->keys, c->cur, c->plan.block_threads, sch, c->stream)
+                : launch_persist(c->st, g, c->keys, c->cur, c->plan.block_threads, sch,
+                                 kSpinLimit, c->stream);
     } else {
       nsw = std::min(left, c->plan.sweeps_per_launch);
       if (every) nsw = std::min<uint32_t>(nsw, every - (uint32_t)(c->sweeps % every));
@@ -404,6 +452,8 @@ pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, s
   st.swap_D = (uint32_t *)(base + l.swap_D);
   st.swap_sat = (uint64_t *)(base + l.swap_sat);
   st.swap_n = (uint32_t)c->tab.swap.size();
+  st.field_thr = (uint64_t *)(base + l.field);
+  st.field_sign = (int32_t *)(base + l.fsign);
   st.walker_at = (uint32_t *)(base + l.wat);
   st.slot_of = (uint32_t *)(base + l.sof);
   st.E = (int32_t *)(base + l.E);
@@ -414,6 +464,7 @@ pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, s
   st.E_series = (int32_t *)(base + l.Es);
   st.M_series = (int32_t *)(base + l.Ms);
   st.counter = (uint32_t *)(base + l.counter);
+  st.mailbox = (uint64_t *)(base + l.mailbox);
   st.staging = base + l.staging;
 
   hipError_t e = hipSuccess;
@@ -426,6 +477,8 @@ pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, s
   H2D(st.swap_off, c->tab.off.data(), R * 4);
   H2D(st.swap_D, c->tab.D.data(), R * 4);
   H2D(st.swap_sat, c->tab.sat.data(), R * 16);
+  H2D(st.field_thr, c->tab.field.data(), c->tab.field.size() * 8);
+  H2D(st.field_sign, c->tab.fsign.data(), R * 4);
   if (e == hipSuccess) e = launch_reset(st, d.geo, sm);
   if (d.geo.dim == 3) {
     if (cfg->couplings) H2D(st.staging, cfg->couplings, 3 * N);
@@ -455,7 +508,7 @@ pt_status pt_set_plan(pt_ctx *ctx, const pt_plan *plan) {
   s = check_plan(ctx, *plan);
   if (s != PT_OK) return s;
   ctx->plan = *plan;
-  if (ctx->plan.mode == PT_PLAN_FUSED) {
+  if (ctx->plan.mode == PT_PLAN_FUSED || ctx->plan.mode == PT_PLAN_PERSISTENT) {
     ctx->plan.tile_planes = ctx->d.geo.L;
     ctx->plan.sweeps_per_launch = 1;
   }
@@ -509,6 +562,8 @@ pt_status pt_observables(pt_ctx *ctx, pt_obs *obs) {
   D2H(M.data(), st.M, R * 4);
   D2H(att.data(), st.att, R * 4);
   D2H(acc.data(), st.acc, R * 4);
+  uint32_t flags[4] = {0, 0, 0, 0};
+  D2H(flags, st.counter, sizeof flags);
   if (obs->E_series) D2H(obs->E_series, st.E_series, (size_t)ctx->n_records * R * 4);
   if (obs->M_series) D2H(obs->M_series, st.M_series, (size_t)ctx->n_records * R * 4);
   std::vector<uint32_t> bits; // packed walker lattices
@@ -524,6 +579,10 @@ pt_status pt_observables(pt_ctx *ctx, pt_obs *obs) {
     }
   }
   if (e != hipSuccess) return device_fail(ctx, e, "observables copy");
+  if (flags[1]) {
+    ctx->poisoned = true;
+    return fail(PT_EDEVICE, "a persistent launch stopped: a pairwise exchange wait exceeded its bound");
+  }
   for (size_t k = 0; k < R; ++k)
     if (wat[k] >= R) {
       ctx->poisoned = true;
@@ -580,5 +639,396 @@ pt_status pt_swap_threshold(const pt_ctx *ctx, uint32_t k, int64_t d, uint64_t *
 void pt_destroy(pt_ctx *ctx) { delete ctx; }
 
 const char *pt_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ---- batched form -------------------------------------------------------------
+namespace {
+
+uint32_t lg2(uint32_t v) {
+  uint32_t r = 0;
+  while ((1u << r) < v) ++r;
+  return r;
+}
+
+struct BatchGroup {
+  Geometry g;                 // dim, L (R varies inside the group)
+  std::vector<uint32_t> inst; // instance indices
+  uint32_t max_R = 0;
+  uint32_t W = 1, threads = 256;
+  uint32_t item_off = 0;      // into the device item array
+  std::vector<BatchItem> items;
+  // online tuning: candidate (W, threads) pairs timed on real cycles
+  std::vector<std::pair<uint32_t, uint32_t>> cand;
+  std::vector<float> cand_ms;
+  bool tuned = false;
+};
+
+// Decompositions found fastest, per (model dim, L), for this process.
+std::map<std::pair<uint32_t, uint32_t>, std::pair<uint32_t, uint32_t>> g_tuned;
+std::mutex g_tuned_mu;
+
+std::vector<std::pair<uint32_t, uint32_t>> batch_candidates(const Geometry &g, uint32_t max_R) {
+  std::vector<std::pair<uint32_t, uint32_t>> c;
+  const uint32_t spans = g.N / (8u * span_groups(g));
+  for (uint32_t W = 1; W <= 32 && W <= max_R; W *= 2) {
+    if (batch_lds_bytes(g, W) > 64u * 1024u) break;
+    const uint32_t work = W * spans; // lanes' worth of work per half sweep
+    uint32_t t = std::min<uint32_t>(512u, std::max<uint32_t>(64u, ((work / 2u) + 63u) & ~63u));
+    c.push_back({W, t});
+    if (t > 64u) c.push_back({W, t / 2u});
+  }
+  if (c.empty()) c.push_back({1u, 256u});
+  return c;
+}
+
+}  // namespace
+
+struct pt_batch {
+  std::vector<pt_ctx *> ctx;
+  hipStream_t user = nullptr, own = nullptr;
+  hipEvent_t ev_sync = nullptr;
+  BatchInst *d_insts = nullptr;
+  BatchItem *d_items = nullptr;
+  uint2 *d_pairs = nullptr;
+  uint32_t *d_ctr = nullptr;
+  uint32_t n_pairs = 0;
+  std::vector<BatchGroup> groups;
+  std::vector<uint2> pairs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint32_t graph_K = 0;
+  bool graph_dirty = true;
+  bool poisoned = false;
+};
+
+namespace {
+
+struct BatchLayoutHost {
+  std::vector<size_t> slice;
+  size_t insts, ctr, items, pairs, total;
+};
+
+BatchLayoutHost batch_host_layout(const pt_config *cfgs, uint32_t n, pt_status *st) {
+  BatchLayoutHost l;
+  size_t o = 0, sumR = 0, sumP = 0;
+  *st = PT_OK;
+  for (uint32_t i = 0; i < n; ++i) {
+    const size_t b = pt_workspace_bytes(&cfgs[i]);
+    if (!b) {
+      *st = PT_EINVAL;
+      return l;
+    }
+    l.slice.push_back(o);
+    o = align_up(o + b);
+    sumR += cfgs[i].R;
+    sumP += cfgs[i].R - 1;
+  }
+  l.insts = o;
+  o = align_up(o + n * sizeof(BatchInst));
+  l.ctr = o;
+  o = align_up(o + n * kCtrWords * 4);
+  l.items = o;
+  o = align_up(o + sumR * sizeof(BatchItem));
+  l.pairs = o;
+  o = align_up(o + std::max<size_t>(sumP, 1) * sizeof(uint2));
+  l.total = o;
+  return l;
+}
+
+pt_status batch_fail(pt_batch *b, hipError_t e, const char *what) {
+  if (b) b->poisoned = true;
+  return fail(PT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void build_items(pt_batch *b, BatchGroup &G) {
+  G.items.clear();
+  for (uint32_t i : G.inst)
+    for (uint32_t w0 = 0; w0 < b->ctx[i]->d.geo.R; w0 += G.W) G.items.push_back({i, w0});
+}
+
+hipError_t upload_items(pt_batch *b, BatchGroup &G, hipStream_t s) {
+  return hipMemcpyAsync(b->d_items + G.item_off, G.items.data(), G.items.size() * sizeof(BatchItem),
+                        hipMemcpyHostToDevice, s);
+}
+
+hipError_t launch_cycle(pt_batch *b, uint32_t K, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  for (auto &G : b->groups) {
+    e = launch_batch_sweep(b->d_insts, b->d_items + G.item_off, (uint32_t)G.items.size(), G.g, G.W,
+                           G.threads, K, s);
+    if (e != hipSuccess) return e;
+  }
+  if ((e = launch_batch_exchange(b->d_insts, b->d_pairs, b->n_pairs, K, s)) != hipSuccess) return e;
+  return launch_batch_advance(b->d_insts, (uint32_t)b->ctx.size(), K, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pt_batch_workspace_bytes(const pt_config *cfgs, uint32_t n) {
+  if (!cfgs || n == 0) {
+    fail(PT_EINVAL, "empty batch");
+    return 0;
+  }
+  pt_status st;
+  BatchLayoutHost l = batch_host_layout(cfgs, n, &st);
+  return st == PT_OK ? l.total : 0;
+}
+
+pt_status pt_batch_create(const pt_config *cfgs, uint32_t n, void *hip_stream, void *d_workspace,
+                          size_t ws_bytes, pt_batch **out) {
+  if (!out) return fail(PT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfgs || n == 0) return fail(PT_EINVAL, "empty batch");
+  pt_status st;
+  BatchLayoutHost l = batch_host_layout(cfgs, n, &st);
+  if (st != PT_OK) return st;
+  if (!d_workspace || (uintptr_t)d_workspace % kAlign) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < l.total) return fail(PT_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, l.total);
+  pt_batch *b = new (std::nothrow) pt_batch();
+  if (!b) return fail(PT_ENOMEM, "host allocation failed");
+  b->user = (hipStream_t)hip_stream;
+  uint8_t *base = (uint8_t *)d_workspace;
+  for (uint32_t i = 0; i < n; ++i) {
+    pt_ctx *c = nullptr;
+    st = pt_create(&cfgs[i], hip_stream, base + l.slice[i], pt_workspace_bytes(&cfgs[i]), &c);
+    if (st != PT_OK) {
+      pt_batch_destroy(b);
+      return st;
+    }
+    b->ctx.push_back(c);
+  }
+  b->d_insts = (BatchInst *)(base + l.insts);
+  b->d_ctr = (uint32_t *)(base + l.ctr);
+  b->d_items = (BatchItem *)(base + l.items);
+  b->d_pairs = (uint2 *)(base + l.pairs);
+  std::vector<BatchInst> hi(n);
+  std::map<std::pair<uint32_t, uint32_t>, size_t> gidx;
+  for (uint32_t i = 0; i < n; ++i) {
+    const pt_ctx *c = b->ctx[i];
+    const Geometry &g = c->d.geo;
+    BatchInst &I = hi[i];
+    I.st = c->st;
+    I.geo = g;
+    I.key = c->keys;
+    I.record_every = c->cfg.record_every;
+    const uint32_t V = span_groups(g);
+    I.lg_L = lg2(g.L);
+    I.lg_spr = lg2(g.gpr / V);
+    I.lg_rows = lg2(g.rows);
+    I.lg_items = lg2(g.N / (8u * V));
+    I.z2 = g.dim == 3 ? 12 : 8;
+    I.ctr = b->d_ctr + (size_t)i * kCtrWords;
+    for (uint32_t k = 0; k + 1 < g.R; ++k) b->pairs.push_back(make_uint2(i, k));
+    const auto key = std::make_pair(g.dim, g.L);
+    if (!gidx.count(key)) {
+      gidx[key] = b->groups.size();
+      b->groups.emplace_back();
+      b->groups.back().g = g;
+    }
+    BatchGroup &G = b->groups[gidx[key]];
+    G.inst.push_back(i);
+    G.max_R = std::max(G.max_R, g.R);
+  }
+  // largest lattices first, so the longest workgroups start first
+  std::sort(b->groups.begin(), b->groups.end(),
+            [](const BatchGroup &x, const BatchGroup &y) { return x.g.N * (x.g.dim == 3 ? 4 : 1) > y.g.N * (y.g.dim == 3 ? 4 : 1); });
+  uint32_t off = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    for (auto &G : b->groups) {
+      G.cand = batch_candidates(G.g, G.max_R);
+      auto it = g_tuned.find({G.g.dim, G.g.L});
+      if (it != g_tuned.end()) {
+        G.W = std::min(it->second.first, G.max_R);
+        G.threads = it->second.second;
+        G.tuned = true;
+      } else {
+        G.W = G.cand[0].first;
+        G.threads = G.cand[0].second;
+      }
+      G.item_off = off;
+      uint32_t sumR = 0;
+      for (uint32_t i : G.inst) sumR += b->ctx[i]->d.geo.R;
+      off += sumR; // room for W = 1
+      build_items(b, G);
+    }
+  }
+  b->n_pairs = (uint32_t)b->pairs.size();
+  std::vector<uint32_t> zeros((size_t)n * kCtrWords, 0u);
+  hipError_t e = hipMemcpyAsync(b->d_insts, hi.data(), n * sizeof(BatchInst), hipMemcpyHostToDevice, b->user);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_ctr, zeros.data(), zeros.size() * 4, hipMemcpyHostToDevice, b->user);
+  if (e == hipSuccess && b->n_pairs)
+    e = hipMemcpyAsync(b->d_pairs, b->pairs.data(), b->pairs.size() * sizeof(uint2), hipMemcpyHostToDevice, b->user);
+  for (auto &G : b->groups)
+    if (e == hipSuccess) e = upload_items(b, G, b->user);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->user);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_sync, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    pt_batch_destroy(b);
+    return fail(PT_EDEVICE, "batch initialisation: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return PT_OK;
+}
+
+pt_status pt_batch_run(pt_batch *b, uint32_t n_sweeps, uint32_t exchange_every) {
+  if (!b) return fail(PT_EINVAL, "batch is NULL");
+  if (b->poisoned) return fail(PT_ESTATE, "batch is poisoned by an earlier device error");
+  if (n_sweeps == 0) return PT_OK;
+  for (pt_ctx *c : b->ctx) {
+    const uint32_t need = records_between(c->cfg.record_every, c->sweeps, c->sweeps + n_sweeps);
+    if ((uint64_t)c->n_records + need > c->cfg.max_records)
+      return fail(PT_EINVAL, "%u more records would exceed max_records = %u", need, c->cfg.max_records);
+    if (c->sweeps + n_sweeps > 0xFFFFFFFFull) return fail(PT_EINVAL, "sweep counter would exceed 2^32");
+  }
+  // cycle length: the largest divisor of the exchange interval up to 16 sweeps
+  uint32_t K = 16;
+  if (exchange_every) {
+    K = 1;
+    for (uint32_t d = 1; d <= 16 && d <= exchange_every; ++d)
+      if (exchange_every % d == 0) K = d;
+  }
+  const uint32_t n = (uint32_t)b->ctx.size();
+  hipError_t e = hipEventRecord(b->ev_sync, b->user);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->own, b->ev_sync, 0);
+  if (e == hipSuccess) e = launch_batch_target(b->d_insts, n, n_sweeps, exchange_every, b->own);
+  if (e != hipSuccess) return batch_fail(b, e, "batch start");
+  // cycles needed: each runs up to K sweeps and ends on the next exchange point
+  uint32_t cycles = 0;
+  for (uint64_t s = b->ctx[0]->sweeps, t = s + n_sweeps; s < t; ++cycles) {
+    uint64_t step = std::min<uint64_t>(K, t - s);
+    if (exchange_every) step = std::min<uint64_t>(step, exchange_every - s % exchange_every);
+    s += step;
+  }
+
+  // online tuning: untuned groups try one candidate per cycle, timed by events
+  bool tuning = false;
+  for (auto &G : b->groups) tuning |= !G.tuned;
+  while (tuning && cycles > 0) {
+    struct Pending { BatchGroup *G; size_t c; hipEvent_t a, z; };
+    std::vector<Pending> pend;
+    for (auto &G : b->groups) {
+      if (G.tuned || G.cand_ms.size() >= G.cand.size()) continue;
+      const size_t ci = G.cand_ms.size();
+      G.W = G.cand[ci].first;
+      G.threads = G.cand[ci].second;
+      build_items(b, G);
+      if ((e = upload_items(b, G, b->own)) != hipSuccess) return batch_fail(b, e, "batch items");
+      pend.push_back({&G, ci, nullptr, nullptr});
+    }
+    for (auto &p : pend) {
+      hipEventCreate(&p.a);
+      hipEventCreate(&p.z);
+    }
+    size_t pi = 0;
+    for (auto &G : b->groups) {
+      const bool timed = pi < pend.size() && pend[pi].G == &G;
+      if (timed) hipEventRecord(pend[pi].a, b->own);
+      e = launch_batch_sweep(b->d_insts, b->d_items + G.item_off, (uint32_t)G.items.size(), G.g,
+                             G.W, G.threads, K, b->own);
+      if (e != hipSuccess) return batch_fail(b, e, "batch sweep launch");
+      if (timed) hipEventRecord(pend[pi++].z, b->own);
+    }
+    if ((e = launch_batch_exchange(b->d_insts, b->d_pairs, b->n_pairs, K, b->own)) != hipSuccess ||
+        (e = launch_batch_advance(b->d_insts, n, K, b->own)) != hipSuccess)
+      return batch_fail(b, e, "batch cycle launch");
+    --cycles;
+    if ((e = hipStreamSynchronize(b->own)) != hipSuccess) return batch_fail(b, e, "batch tuning");
+    for (auto &p : pend) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, p.a, p.z);
+      p.G->cand_ms.push_back(ms);
+      hipEventDestroy(p.a);
+      hipEventDestroy(p.z);
+    }
+    tuning = false;
+    for (auto &G : b->groups) {
+      if (!G.tuned && G.cand_ms.size() == G.cand.size()) {
+        const size_t best = std::min_element(G.cand_ms.begin(), G.cand_ms.end()) - G.cand_ms.begin();
+        G.W = G.cand[best].first;
+        G.threads = G.cand[best].second;
+        G.tuned = true;
+        build_items(b, G);
+        if ((e = upload_items(b, G, b->own)) != hipSuccess) return batch_fail(b, e, "batch items");
+        std::lock_guard<std::mutex> lk(g_tuned_mu);
+        g_tuned[{G.g.dim, G.g.L}] = {G.W, G.threads};
+        b->graph_dirty = true;
+      }
+      tuning |= !G.tuned;
+    }
+  }
+  if (cycles > 0) {
+    if (b->graph_dirty || b->graph_K != K) {
+      if (b->exec) hipGraphExecDestroy(b->exec);
+      if (b->graph) hipGraphDestroy(b->graph);
+      b->exec = nullptr;
+      b->graph = nullptr;
+      e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        hipError_t le = launch_cycle(b, K, b->own);
+        e = hipStreamEndCapture(b->own, &b->graph);
+        if (e == hipSuccess) e = le;
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) return batch_fail(b, e, "batch graph capture");
+      b->graph_K = K;
+      b->graph_dirty = false;
+    }
+    for (uint32_t c = 0; c < cycles; ++c)
+      if ((e = hipGraphLaunch(b->exec, b->own)) != hipSuccess) return batch_fail(b, e, "batch graph launch");
+  }
+  if ((e = hipEventRecord(b->ev_sync, b->own)) != hipSuccess ||
+      (e = hipStreamWaitEvent(b->user, b->ev_sync, 0)) != hipSuccess)
+    return batch_fail(b, e, "batch end");
+  for (pt_ctx *c : b->ctx) {
+    c->n_records += records_between(c->cfg.record_every, c->sweeps, c->sweeps + n_sweeps);
+    if (exchange_every) c->exchanges += records_between(exchange_every, c->sweeps, c->sweeps + n_sweeps);
+    c->sweeps += n_sweeps;
+  }
+  return PT_OK;
+}
+
+pt_status pt_batch_observables(pt_batch *b, uint32_t i, pt_obs *obs) {
+  if (!b) return fail(PT_EINVAL, "batch is NULL");
+  if (b->poisoned) return fail(PT_ESTATE, "batch is poisoned by an earlier device error");
+  if (i >= b->ctx.size()) return fail(PT_EINVAL, "instance %u out of range", i);
+  hipError_t e = hipStreamSynchronize(b->own);
+  uint32_t ctr[kCtrWords];
+  if (e == hipSuccess) e = hipMemcpy(ctr, b->d_ctr + (size_t)i * kCtrWords, sizeof ctr, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return batch_fail(b, e, "batch observables");
+  pt_ctx *c = b->ctx[i];
+  if (ctr[kCtrSweeps] != c->sweeps || ctr[kCtrExchanges] != c->exchanges || ctr[kCtrRecords] != c->n_records) {
+    b->poisoned = true;
+    return fail(PT_EDEVICE, "instance %u: device schedule (%u sweeps, %u exchanges, %u records) "
+                "disagrees with the host (%llu, %llu, %u)", i, ctr[kCtrSweeps], ctr[kCtrExchanges],
+                ctr[kCtrRecords], (unsigned long long)c->sweeps, (unsigned long long)c->exchanges,
+                c->n_records);
+  }
+  return pt_observables(c, obs);
+}
+
+pt_status pt_batch_group_plan(const pt_batch *b, uint32_t g, uint32_t *L, uint32_t *W,
+                              uint32_t *threads) {
+  if (!b || g >= b->groups.size()) return fail(PT_EINVAL, "group %u out of range", g);
+  if (L) *L = b->groups[g].g.L;
+  if (W) *W = b->groups[g].W;
+  if (threads) *threads = b->groups[g].threads;
+  return PT_OK;
+}
+
+void pt_batch_destroy(pt_batch *b) {
+  if (!b) return;
+  if (b->own) hipStreamSynchronize(b->own);
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->ev_sync) hipEventDestroy(b->ev_sync);
+  if (b->own) hipStreamDestroy(b->own);
+  for (pt_ctx *c : b->ctx) pt_destroy(c);
+  delete b;
+}
 
 }  // extern "C"

@@ -14,6 +14,7 @@ constexpr uint32_t kPurposeSpin = 2u << 8;
 constexpr uint32_t kPurposeBond = 3u << 8;
 
 constexpr uint32_t kClasses = 16;      // flip-threshold classes per slot: 8*b + u
+constexpr uint32_t kFieldDigits = 32;  // binary digits of |dM|/2 with a field swap factor
 constexpr uint32_t kMaxSweepsPerLaunch = 8;
 
 // Device pointers into the caller's workspace.
@@ -26,6 +27,8 @@ struct DevState {
   uint32_t *swap_D;    // [R] half-width D[k]
   uint64_t *swap_sat;  // [R][2] T for d < -D, T for d > D
   uint32_t swap_n;     // entries in swap_tab
+  uint64_t *field_thr; // [R][kFieldDigits] per pair: accept digit j iff r < T (h != 0 only)
+  int32_t *field_sign; // [R] sign of (beta_k - beta_k+1) * (-h): the field factor applies when sign * dM < 0
   uint32_t *walker_at; // [R] slot -> walker
   uint32_t *slot_of;   // [R] walker -> slot
   int32_t *E;          // [R] walker E_int
@@ -35,7 +38,8 @@ struct DevState {
   uint32_t *acc;       // [R] pair accepts
   int32_t *E_series;   // [max_records][R] slot order
   int32_t *M_series;
-  uint32_t *counter;   // [4] workgroup-arrival counter of the tiled sweep
+  uint32_t *counter;   // [4] workgroup-arrival counter of the tiled sweep; [1] persistent-kernel abort flag
+  uint64_t *mailbox;   // [4][R] persistent kernel: (step + 1) << 32 | E_int posted by the holder of a slot
   uint8_t *staging;    // +-1 bytes uploaded by the host (only if the config uploads)
 };
 
@@ -65,6 +69,47 @@ struct Schedule {
   uint32_t ex_step;      // index e of the next exchange step
 };
 
+// ---- batched form: many independent instances advanced together ----------
+// Device-resident schedule of one instance (uint32 each).
+enum BatchCtr : uint32_t {
+  kCtrSweeps = 0,    // sweeps done
+  kCtrExchanges = 1, // exchange steps done
+  kCtrRecords = 2,   // records written
+  kCtrTarget = 3,    // run until this many sweeps are done
+  kCtrActive = 4,    // 0: the instance is idle
+  kCtrEvery = 5,     // exchange interval (0 = never)
+  kCtrWords = 8
+};
+
+struct BatchInst {
+  DevState st;
+  Geometry geo;
+  Keys key;
+  uint32_t record_every;
+  uint32_t lg_L, lg_spr, lg_rows, lg_items; // as in the fused kernel, for span_groups(geo)
+  int32_t z2;
+  uint32_t *ctr; // [kCtrWords]
+};
+
+struct BatchItem {
+  uint32_t inst; // instance index
+  uint32_t w0;   // first walker of the workgroup (up to W walkers)
+};
+
+// One cycle of at most K sweeps: sweep launches (one per lattice-size group),
+// then the exchange launch, then the counter advance.
+hipError_t launch_batch_sweep(const BatchInst *insts, const BatchItem *items, uint32_t n_items,
+                              const Geometry &g, uint32_t W, uint32_t threads, uint32_t K,
+                              hipStream_t stream);
+hipError_t launch_batch_exchange(const BatchInst *insts, const uint2 *pairs, uint32_t n_pairs,
+                                 uint32_t K, hipStream_t stream);
+hipError_t launch_batch_advance(const BatchInst *insts, uint32_t n_insts, uint32_t K,
+                                hipStream_t stream);
+size_t batch_lds_bytes(const Geometry &g, uint32_t W);
+// Start a run: every instance's target = done + add, active if add > 0, interval = every.
+hipError_t launch_batch_target(const BatchInst *insts, uint32_t n, uint32_t add, uint32_t every,
+                               hipStream_t stream);
+
 hipError_t launch_init_spins(const DevState &st, const Geometry &g, const Keys &k, bool upload,
                              hipStream_t stream);
 hipError_t launch_init_bonds(const DevState &st, const Geometry &g, const Keys &k, bool upload,
@@ -79,6 +124,11 @@ hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, ui
                         const Schedule &sch, hipStream_t stream);
 hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
                         uint32_t threads, const Schedule &sch, hipStream_t stream);
+// One co-resident workgroup per walker for the whole launch; exchange decisions
+// are taken pairwise through per-slot mailboxes (cooperative launch).
+hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
+                          uint32_t threads, const Schedule &sch, uint32_t spin_limit,
+                          hipStream_t stream);
 
 // Groups of 8 sites one lane updates per item (V): 2D min(4, L/8), 3D min(2, L/8).
 uint32_t span_groups(const Geometry &g);
@@ -86,6 +136,9 @@ uint32_t span_groups(const Geometry &g);
 // LDS bytes needed by the kernels (host-side planning).
 size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo);
 size_t fused_lds_bytes(const Geometry &g);
+size_t persist_lds_bytes(const Geometry &g);
+// Workgroups of the persistent kernel that can be co-resident (0 if unknown).
+uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads);
 size_t max_lds_bytes();
 
 }  // namespace ptmi

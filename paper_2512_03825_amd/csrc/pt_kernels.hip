@@ -234,33 +234,58 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
+// Swap threshold of pair k for E_a - E_b (E_int at slots k, k+1).
+__device__ __forceinline__ uint64_t swap_T(const DevState &st, uint32_t k, int32_t dEint) {
+  const int32_t d = dEint / 4; // E_int differences are multiples of 4
+  const int32_t D = (int32_t)st.swap_D[k];
+  if (d < -D) return st.swap_sat[2u * k];
+  if (d > D) return st.swap_sat[2u * k + 1u];
+  const uint32_t idx = st.swap_off[k] + (uint32_t)(d + D);
+  return idx < st.swap_n ? st.swap_tab[idx] : 0u; // a valid table always passes
+}
+
+// Field factor of a swap (2D, h != 0): with y = (beta_k - beta_k+1)(-h) dM < 0,
+// one Metropolis test per set binary digit j of |dM|/2, each with its own draw
+// (word j mod 4 of block (k, e, 1 + j/4, swap purpose)).
+__device__ __forceinline__ bool field_factor(const DevState &st, uint32_t k, uint32_t e,
+                                             int32_t dM, uint32_t k0, uint32_t k1) {
+  const int32_t sg = st.field_sign[k];
+  if (sg == 0 || dM == 0 || (sg > 0) == (dM > 0)) return true; // y >= 0
+  const uint32_t n = (uint32_t)(dM < 0 ? -dM : dM) >> 1;
+  for (uint32_t j = 0; j < kFieldDigits && (n >> j); ++j) {
+    if (!((n >> j) & 1u)) continue;
+    const Words w = philox(k, e, 1u + (j >> 2), kPurposeSwap, k0, k1);
+    const uint32_t r = (j & 3u) == 0 ? w.x : (j & 3u) == 1 ? w.y : (j & 3u) == 2 ? w.z : w.w;
+    if ((uint64_t)r >= st.field_thr[(size_t)k * kFieldDigits + j]) return false;
+  }
+  return true;
+}
+
+// Exchange decision for the pair of slots (k, k+1) at step e; on acceptance the
+// two walkers trade slots.  Counts the attempt and the acceptance.
+__device__ __forceinline__ void exchange_pair(const DevState &st, uint32_t k, uint32_t k0,
+                                              uint32_t k1, uint32_t e, const int32_t *E,
+                                              const int32_t *M, uint32_t *walker_at,
+                                              uint32_t *slot_of) {
+  const uint32_t a = walker_at[k], b = walker_at[k + 1u];
+  const uint64_t T = swap_T(st, k, E[a] - E[b]);
+  const uint32_t r = philox(k, e, 0u, kPurposeSwap, k0, k1).x;
+  st.att[k] += 1u;
+  if ((uint64_t)r < T && field_factor(st, k, e, M[a] - M[b], k0, k1)) {
+    walker_at[k] = b;
+    walker_at[k + 1u] = a;
+    slot_of[a] = k + 1u;
+    slot_of[b] = k;
+    st.acc[k] += 1u;
+  }
+}
+
 // One exchange step with parity e & 1 on the given walker/slot maps.
 __device__ void exchange_step(const DevState &st, uint32_t R, uint32_t k0, uint32_t k1,
-                              uint32_t e, const int32_t *E, uint32_t *walker_at,
-                              uint32_t *slot_of, uint32_t tid, uint32_t nt) {
-  for (uint32_t k = (e & 1u) + 2u * tid; k + 1u < R; k += 2u * nt) {
-    const uint32_t a = walker_at[k], b = walker_at[k + 1u];
-    const int32_t d = (E[a] - E[b]) / 4; // E_int differences are multiples of 4
-    const int32_t D = (int32_t)st.swap_D[k];
-    uint64_t T;
-    if (d < -D)
-      T = st.swap_sat[2u * k];
-    else if (d > D)
-      T = st.swap_sat[2u * k + 1u];
-    else {
-      const uint32_t idx = st.swap_off[k] + (uint32_t)(d + D);
-      T = idx < st.swap_n ? st.swap_tab[idx] : 0u; // a valid table always passes
-    }
-    const uint32_t r = philox(k, e, 0u, kPurposeSwap, k0, k1).x;
-    st.att[k] += 1u;
-    if ((uint64_t)r < T) {
-      walker_at[k] = b;
-      walker_at[k + 1u] = a;
-      slot_of[a] = k + 1u;
-      slot_of[b] = k;
-      st.acc[k] += 1u;
-    }
-  }
+                              uint32_t e, const int32_t *E, const int32_t *M,
+                              uint32_t *walker_at, uint32_t *slot_of, uint32_t tid, uint32_t nt) {
+  for (uint32_t k = (e & 1u) + 2u * tid; k + 1u < R; k += 2u * nt)
+    exchange_pair(st, k, k0, k1, e, E, M, walker_at, slot_of);
 }
 
 struct TiledArgs {
@@ -467,7 +492,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
   }
   if (a.sch.do_exchange) {
     __syncthreads();
-    exchange_step(a.st, R, a.key.k0, a.key.k1, a.sch.ex_step, a.st.E, a.st.walker_at,
+    exchange_step(a.st, R, a.key.k0, a.key.k1, a.sch.ex_step, a.st.E, a.st.M, a.st.walker_at,
                   a.st.slot_of, tid, nt);
   }
   __syncthreads();
@@ -593,7 +618,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
     }
     __syncthreads(); // records read the maps before the exchange rewrites them
     if (a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u) {
-      exchange_step(a.st, R, a.key.k0, a.key.k1, e, E, wat, sof, tid, nt);
+      exchange_step(a.st, R, a.key.k0, a.key.k1, e, E, M, wat, sof, tid, nt);
       ++e;
     }
     __syncthreads();
@@ -608,8 +633,321 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   }
 }
 
+struct PersistArgs {
+  DevState st;
+  Geometry geo;
+  Keys key;
+  Schedule sch;
+  uint32_t *spins; // bit-packed, updated in place
+  uint32_t lg_L, lg_spr, lg_rows, lg_items;
+  int32_t z2;
+  uint32_t spin_limit; // polls of a partner's mailbox before the launch gives up
+};
+
+// Persistent replica workgroups: walker w = blockIdx.x keeps its lattice in
+// LDS for the whole launch.  After each sweep it folds its own E and M, writes
+// its slot's record, and at an exchange step posts (step, E) in the mailbox of
+// its slot, waits for the partner slot's post, and takes the same decision as
+// the partner (same draw, same table entry) -- there is no global barrier.
+// A partner is at most a few steps apart, so four mailbox generations suffice.
+template <int DIM, int V>
+__global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ uint32_t s_thr[kClasses];
+  __shared__ int s_red[kMaxThreads / 64][2];
+  __shared__ uint32_t s_slot, s_stop;
+  const Geometry &G = a.geo;
+  const uint32_t R = G.R, N = G.N, L = G.L, lgL = a.lg_L;
+  const uint32_t lgP = (DIM == 3 ? 2u : 1u) * lgL;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x, w = blockIdx.x;
+  uint8_t *sp = smem;
+  uint8_t *bx = smem + N, *by = bx + N, *bz = by + N;
+
+  uint32_t slot = a.st.slot_of[w];
+  int32_t E = a.st.E[w], M = a.st.M[w];
+  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+  unpack_tile(sp, a.spins + (size_t)w * (N >> 5), 0u, N >> 5, 0xFFFFFFFFu, tid, nt);
+  if (DIM == 3) unpack_tile(bx, a.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
+  __syncthreads();
+
+  const uint32_t smask = (1u << a.lg_spr) - 1u, rmask = G.rows - 1u;
+  const uint32_t shp = a.lg_spr + a.lg_rows;
+  const uint32_t items = 1u << a.lg_items;
+  uint32_t rec = a.sch.rec_base, e = a.sch.ex_step;
+  for (uint32_t j = 0; j < a.sch.nsw; ++j) {
+    const uint32_t s = a.sch.s0 + j;
+    Tally t = {0, 0, 0};
+    for (uint32_t c = 0; c < 2u; ++c) {
+      for (uint32_t q = tid; q < items; q += nt) {
+        const uint32_t g0 = (q & smask) * V;
+        const uint32_t y = (q >> a.lg_spr) & rmask;
+        const uint32_t pl = q >> shp;
+        const uint32_t pu = (pl + L - 1u) & (L - 1u);
+        const uint32_t pd = (pl + 1u) & (L - 1u);
+        const uint32_t off = (c + pl + (DIM == 3 ? y : 0u)) & 1u;
+        const uint32_t ctr0 = (((pl << a.lg_rows) + y) << (lgL - 3u)) + g0;
+        Words r[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+        if (DIM == 2)
+          span2d<V>(sp + (pl << lgP), sp + (pu << lgP), sp + (pd << lgP), g0, L, off, r, s_thr, t);
+        else
+          span3d<V>(sp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, s_thr, t);
+      }
+      __syncthreads();
+    }
+    // this walker's energy and magnetisation change over the sweep
+    int dE = a.z2 * t.n - (t.sc - 32 * t.sb), dM = 4 * t.sb - 2 * t.n;
+    dE = wave_sum(dE);
+    dM = wave_sum(dM);
+    if ((tid & 63u) == 0u) {
+      s_red[tid >> 6][0] = dE;
+      s_red[tid >> 6][1] = dM;
+    }
+    __syncthreads();
+    for (uint32_t v = 0; v < (nt >> 6); ++v) {
+      E += s_red[v][0];
+      M += s_red[v][1];
+    }
+    if (a.sch.record_every && (s + 1u) % a.sch.record_every == 0u) {
+      if (tid == 0u) {
+        a.st.E_series[(size_t)rec * R + slot] = E;
+        a.st.M_series[(size_t)rec * R + slot] = M;
+      }
+      ++rec;
+    }
+    if (a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u) {
+      if (tid == 0u) {
+        uint32_t stop = 0u, nslot = slot;
+        uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * R;
+        const uint64_t tag = (uint64_t)(e + 1u) << 32;
+        __hip_atomic_store(&mb[slot], tag | (uint32_t)E, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t par = e & 1u;
+        uint32_t partner = 0xFFFFFFFFu;
+        if ((slot & 1u) == par && slot + 1u < R) partner = slot + 1u;
+        else if ((slot & 1u) != par && slot >= 1u) partner = slot - 1u;
+        if (partner != 0xFFFFFFFFu) {
+          uint64_t v = 0;
+          for (uint32_t n = 0;; ++n) {
+            v = __hip_atomic_load(&mb[partner], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            if ((v & 0xFFFFFFFF00000000ull) == tag) break;
+            if (n >= a.spin_limit ||
+                __hip_atomic_load(&a.st.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+              __hip_atomic_store(&a.st.counter[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              stop = 1u;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+          }
+          if (!stop) {
+            const uint32_t lo = min(slot, partner);
+            const int32_t Ep = (int32_t)(uint32_t)v;
+            const int32_t Elo = (slot == lo) ? E : Ep, Ehi = (slot == lo) ? Ep : E;
+            const uint32_t r = philox(lo, e, 0u, kPurposeSwap, a.key.k0, a.key.k1).x;
+            const bool accept = (uint64_t)r < swap_T(a.st, lo, Elo - Ehi);
+            if (slot == lo) {
+              atomicAdd(&a.st.att[lo], 1u);
+              if (accept) atomicAdd(&a.st.acc[lo], 1u);
+            }
+            if (accept) nslot = partner;
+          }
+        }
+        s_slot = nslot;
+        s_stop = stop;
+      }
+      ++e;
+      __syncthreads();
+      if (s_stop) break;
+      if (s_slot != slot) {
+        slot = s_slot;
+        if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+      }
+      __syncthreads();
+    }
+  }
+  pack_tile(a.spins + (size_t)w * (N >> 5), sp, N >> 5, tid, nt);
+  if (tid == 0u) {
+    a.st.E[w] = E;
+    a.st.M[w] = M;
+    a.st.slot_of[w] = slot;
+    a.st.walker_at[slot] = w;
+  }
+}
+
+// ---- batched form ----------------------------------------------------------
+// LDS layout of a batched-sweep workgroup holding W walkers of one instance.
+struct BatchLayout {
+  uint32_t thr, slot, E, M, acc, spins, bonds, total;
+};
+__host__ __device__ inline BatchLayout batch_layout(uint32_t W, uint32_t N, uint32_t dim) {
+  BatchLayout b;
+  b.thr = 0;
+  b.slot = b.thr + W * kClasses * 4u;
+  b.E = b.slot + W * 4u;
+  b.M = b.E + W * 4u;
+  b.acc = b.M + W * 4u;
+  b.spins = (b.acc + W * 8u + 15u) & ~15u;
+  b.bonds = b.spins + W * N;
+  b.total = b.bonds + (dim == 3 ? 3u * N : 0u);
+  return b;
+}
+
+// Sweeps of this cycle for an instance: at most K, never past the target, and
+// never past the next exchange point (a cycle always ends on one).
+__device__ __forceinline__ uint32_t cycle_sweeps(const uint32_t *ctr, uint32_t K) {
+  if (!ctr[kCtrActive]) return 0u;
+  const uint32_t s = ctr[kCtrSweeps], every = ctr[kCtrEvery];
+  uint32_t n = min(K, ctr[kCtrTarget] - s);
+  if (every) n = min(n, every - s % every);
+  return n;
+}
+
+// One workgroup: walkers [w0, w0 + W) of one instance, whole lattices in LDS,
+// the cycle's sweeps in place, per-walker E and M, records by slot.
+template <int DIM, int V>
+__global__ __launch_bounds__(kMaxThreads) void k_batch_sweep(const BatchInst *insts,
+                                                             const BatchItem *items, uint32_t W,
+                                                             uint32_t K) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const BatchItem it = items[blockIdx.x];
+  const BatchInst &I = insts[it.inst];
+  const uint32_t nsw = cycle_sweeps(I.ctr, K);
+  if (nsw == 0u) return;
+  const uint32_t s0 = I.ctr[kCtrSweeps];
+  const Geometry &G = I.geo;
+  const uint32_t R = G.R, N = G.N, L = G.L, lgL = I.lg_L;
+  const uint32_t lgP = (DIM == 3 ? 2u : 1u) * lgL;
+  const uint32_t nw = min(W, R - it.w0);
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const BatchLayout B = batch_layout(W, N, DIM);
+  uint32_t *thr = reinterpret_cast<uint32_t *>(smem + B.thr);
+  uint32_t *slot = reinterpret_cast<uint32_t *>(smem + B.slot);
+  int32_t *E = reinterpret_cast<int32_t *>(smem + B.E);
+  int32_t *M = reinterpret_cast<int32_t *>(smem + B.M);
+  int32_t *acc = reinterpret_cast<int32_t *>(smem + B.acc);
+  uint8_t *sp = smem + B.spins;
+  uint8_t *bx = smem + B.bonds, *by = bx + N, *bz = by + N;
+
+  for (uint32_t v = tid; v < nw; v += nt) {
+    slot[v] = I.st.slot_of[it.w0 + v];
+    E[v] = I.st.E[it.w0 + v];
+    M[v] = I.st.M[it.w0 + v];
+    acc[2u * v] = 0;
+    acc[2u * v + 1u] = 0;
+  }
+  __syncthreads();
+  for (uint32_t q = tid; q < nw * kClasses; q += nt)
+    thr[q] = I.st.flip_thr[slot[q / kClasses] * kClasses + (q % kClasses)];
+  unpack_tile(sp, I.st.spins[0] + (size_t)it.w0 * (N >> 5), 0u, (nw * N) >> 5, 0xFFFFFFFFu, tid, nt);
+  if (DIM == 3) unpack_tile(bx, I.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
+  __syncthreads();
+
+  const uint32_t smask = (1u << I.lg_spr) - 1u, rmask = G.rows - 1u, imask = (1u << I.lg_items) - 1u;
+  const uint32_t shp = I.lg_spr + I.lg_rows;
+  const uint32_t items_n = nw << I.lg_items;
+  uint32_t rec = I.ctr[kCtrRecords];
+  for (uint32_t j = 0; j < nsw; ++j) {
+    const uint32_t s = s0 + j;
+    for (uint32_t c = 0; c < 2u; ++c) {
+      uint32_t cur = 0xFFFFFFFFu;
+      Tally t = {0, 0, 0};
+      for (uint32_t q = tid; q < items_n; q += nt) {
+        const uint32_t v = q >> I.lg_items;
+        const uint32_t li = q & imask;
+        if (v != cur) {
+          if (cur != 0xFFFFFFFFu) {
+            atomicAdd(&acc[2u * cur], I.z2 * t.n - (t.sc - 32 * t.sb));
+            atomicAdd(&acc[2u * cur + 1u], 4 * t.sb - 2 * t.n);
+          }
+          cur = v;
+          t = {0, 0, 0};
+        }
+        const uint32_t g0 = (li & smask) * V;
+        const uint32_t y = (li >> I.lg_spr) & rmask;
+        const uint32_t pl = li >> shp;
+        const uint32_t pu = (pl + L - 1u) & (L - 1u);
+        const uint32_t pd = (pl + 1u) & (L - 1u);
+        const uint32_t off = (c + pl + (DIM == 3 ? y : 0u)) & 1u;
+        const uint32_t ctr0 = (((pl << I.lg_rows) + y) << (lgL - 3u)) + g0;
+        Words r[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+          r[u] = philox(ctr0 + u, s, slot[v], c | kPurposeFlip, I.key.k0, I.key.k1);
+        uint8_t *wsp = sp + (size_t)v * N;
+        if (DIM == 2)
+          span2d<V>(wsp + (pl << lgP), wsp + (pu << lgP), wsp + (pd << lgP), g0, L, off, r,
+                    thr + v * kClasses, t);
+        else
+          span3d<V>(wsp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, thr + v * kClasses, t);
+      }
+      if (cur != 0xFFFFFFFFu) {
+        atomicAdd(&acc[2u * cur], I.z2 * t.n - (t.sc - 32 * t.sb));
+        atomicAdd(&acc[2u * cur + 1u], 4 * t.sb - 2 * t.n);
+      }
+      __syncthreads();
+    }
+    for (uint32_t v = tid; v < nw; v += nt) {
+      E[v] += acc[2u * v];
+      M[v] += acc[2u * v + 1u];
+      acc[2u * v] = 0;
+      acc[2u * v + 1u] = 0;
+      if (I.record_every && (s + 1u) % I.record_every == 0u) {
+        I.st.E_series[(size_t)rec * R + slot[v]] = E[v];
+        I.st.M_series[(size_t)rec * R + slot[v]] = M[v];
+      }
+    }
+    if (I.record_every && (s + 1u) % I.record_every == 0u) ++rec;
+    __syncthreads();
+  }
+  pack_tile(I.st.spins[0] + (size_t)it.w0 * (N >> 5), sp, (nw * N) >> 5, tid, nt);
+  for (uint32_t v = tid; v < nw; v += nt) {
+    I.st.E[it.w0 + v] = E[v];
+    I.st.M[it.w0 + v] = M[v];
+  }
+}
+
+// One thread per (instance, pair k): the pair's decision when the instance's
+// cycle ends on an exchange step and k has the step's parity.
+__global__ void k_batch_exchange(const BatchInst *insts, const uint2 *pairs, uint32_t n_pairs,
+                                 uint32_t K) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n_pairs) return;
+  const uint2 p = pairs[q];
+  const BatchInst &I = insts[p.x];
+  const uint32_t nsw = cycle_sweeps(I.ctr, K);
+  const uint32_t every = I.ctr[kCtrEvery], e = I.ctr[kCtrExchanges];
+  if (nsw == 0u || every == 0u || (I.ctr[kCtrSweeps] + nsw) % every != 0u) return;
+  if ((p.y & 1u) != (e & 1u)) return;
+  exchange_pair(I.st, p.y, I.key.k0, I.key.k1, e, I.st.E, I.st.M, I.st.walker_at, I.st.slot_of);
+}
+
+__global__ void k_batch_target(const BatchInst *insts, uint32_t n, uint32_t add, uint32_t every) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t *ctr = insts[i].ctr;
+  ctr[kCtrTarget] = ctr[kCtrSweeps] + add;
+  ctr[kCtrActive] = add ? 1u : 0u;
+  ctr[kCtrEvery] = every;
+}
+
+// One thread per instance: advance the schedule by this cycle's sweeps.
+__global__ void k_batch_advance(const BatchInst *insts, uint32_t n, uint32_t K) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const BatchInst &I = insts[i];
+  uint32_t *ctr = I.ctr;
+  const uint32_t nsw = cycle_sweeps(ctr, K);
+  if (nsw == 0u) return;
+  const uint32_t s0 = ctr[kCtrSweeps], every = ctr[kCtrEvery];
+  if (I.record_every) ctr[kCtrRecords] += (s0 + nsw) / I.record_every - s0 / I.record_every;
+  if (every && (s0 + nsw) % every == 0u) ctr[kCtrExchanges] += 1u;
+  ctr[kCtrSweeps] = s0 + nsw;
+  if (s0 + nsw >= ctr[kCtrTarget]) ctr[kCtrActive] = 0u;
+}
+
 __global__ void k_exchange(DevState st, uint32_t R, Keys key, uint32_t e) {
-  exchange_step(st, R, key.k0, key.k1, e, st.E, st.walker_at, st.slot_of, threadIdx.x,
+  exchange_step(st, R, key.k0, key.k1, e, st.E, st.M, st.walker_at, st.slot_of, threadIdx.x,
                 blockDim.x);
 }
 
@@ -674,6 +1012,7 @@ __global__ void k_reset(DevState st, Geometry G) {
       st.acc[q] = 0;
     }
     if (q < 4u) st.counter[q] = 0;
+    if (q < 4u * R) st.mailbox[q] = 0;
   }
 }
 
@@ -737,6 +1076,27 @@ hipError_t launch_tiled_v(const TiledArgs &a, uint32_t tiles, uint32_t R, uint32
 }
 
 template <int DIM, int V>
+hipError_t launch_batch_sweep_v(const BatchInst *insts, const BatchItem *items, uint32_t n_items,
+                                uint32_t W, uint32_t threads, uint32_t K, size_t lds,
+                                hipStream_t stream) {
+  hipError_t err = allow_lds(k_batch_sweep<DIM, V>, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_batch_sweep<DIM, V>), dim3(n_items), dim3(threads), lds, stream, insts,
+                     items, W, K);
+  return hipGetLastError();
+}
+
+template <int DIM, int V>
+hipError_t launch_persist_v(PersistArgs &a, uint32_t R, uint32_t threads, size_t lds,
+                            hipStream_t stream) {
+  hipError_t err = allow_lds(k_persist<DIM, V>, lds);
+  if (err != hipSuccess) return err;
+  void *args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_persist<DIM, V>), dim3(R),
+                                    dim3(threads), args, (unsigned int)lds, stream);
+}
+
+template <int DIM, int V>
 hipError_t launch_fused_v(const FusedArgs &a, uint32_t threads, size_t lds, hipStream_t stream) {
   hipError_t err = allow_lds(k_fused<DIM, V>, lds);
   if (err != hipSuccess) return err;
@@ -754,6 +1114,25 @@ size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo) {
 }
 
 size_t fused_lds_bytes(const Geometry &g) { return fused_layout(g.R, g.N, g.dim).total; }
+
+size_t persist_lds_bytes(const Geometry &g) { return (size_t)g.N * (g.dim == 3 ? 4u : 1u); }
+
+uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads) {
+  const uint32_t V = span_groups(g);
+  const void *fn = g.dim == 3 ? (V == 2 ? reinterpret_cast<const void *>(k_persist<3, 2>)
+                                        : reinterpret_cast<const void *>(k_persist<3, 1>))
+                 : V == 4 ? reinterpret_cast<const void *>(k_persist<2, 4>)
+                 : V == 2 ? reinterpret_cast<const void *>(k_persist<2, 2>)
+                          : reinterpret_cast<const void *>(k_persist<2, 1>);
+  const size_t lds = persist_lds_bytes(g);
+  if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  int per_cu = 0, dev = 0, cus = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, (int)threads, lds) != hipSuccess) return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return (uint32_t)(per_cu * cus);
+}
 
 hipError_t launch_init_spins(const DevState &st, const Geometry &g, const Keys &k, bool upload,
                              hipStream_t stream) {
@@ -846,6 +1225,69 @@ hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, ui
   return V == 4 ? launch_fused_v<2, 4>(a, threads, lds, stream)
        : V == 2 ? launch_fused_v<2, 2>(a, threads, lds, stream)
                 : launch_fused_v<2, 1>(a, threads, lds, stream);
+}
+
+hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
+                          uint32_t threads, const Schedule &sch, uint32_t spin_limit,
+                          hipStream_t stream) {
+  PersistArgs a;
+  a.st = st;
+  a.geo = g;
+  a.key = k;
+  a.sch = sch;
+  a.spins = st.spins[cur];
+  const uint32_t V = span_groups(g);
+  a.lg_L = ilog2(g.L);
+  a.lg_spr = ilog2(g.gpr / V);
+  a.lg_rows = ilog2(g.rows);
+  a.lg_items = ilog2(g.N / (8u * V));
+  a.z2 = g.dim == 3 ? 12 : 8;
+  a.spin_limit = spin_limit;
+  const size_t lds = persist_lds_bytes(g);
+  if (g.dim == 3)
+    return V == 2 ? launch_persist_v<3, 2>(a, g.R, threads, lds, stream)
+                  : launch_persist_v<3, 1>(a, g.R, threads, lds, stream);
+  return V == 4 ? launch_persist_v<2, 4>(a, g.R, threads, lds, stream)
+       : V == 2 ? launch_persist_v<2, 2>(a, g.R, threads, lds, stream)
+                : launch_persist_v<2, 1>(a, g.R, threads, lds, stream);
+}
+
+size_t batch_lds_bytes(const Geometry &g, uint32_t W) { return batch_layout(W, g.N, g.dim).total; }
+
+hipError_t launch_batch_sweep(const BatchInst *insts, const BatchItem *items, uint32_t n_items,
+                              const Geometry &g, uint32_t W, uint32_t threads, uint32_t K,
+                              hipStream_t stream) {
+  if (n_items == 0) return hipSuccess;
+  const uint32_t V = span_groups(g);
+  const size_t lds = batch_lds_bytes(g, W);
+  if (g.dim == 3)
+    return V == 2 ? launch_batch_sweep_v<3, 2>(insts, items, n_items, W, threads, K, lds, stream)
+                  : launch_batch_sweep_v<3, 1>(insts, items, n_items, W, threads, K, lds, stream);
+  return V == 4 ? launch_batch_sweep_v<2, 4>(insts, items, n_items, W, threads, K, lds, stream)
+       : V == 2 ? launch_batch_sweep_v<2, 2>(insts, items, n_items, W, threads, K, lds, stream)
+                : launch_batch_sweep_v<2, 1>(insts, items, n_items, W, threads, K, lds, stream);
+}
+
+hipError_t launch_batch_exchange(const BatchInst *insts, const uint2 *pairs, uint32_t n_pairs,
+                                 uint32_t K, hipStream_t stream) {
+  if (n_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_exchange, dim3((n_pairs + 255u) / 256u), dim3(256), 0, stream, insts,
+                     pairs, n_pairs, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(const BatchInst *insts, uint32_t n, uint32_t K, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_advance, dim3((n + 255u) / 256u), dim3(256), 0, stream, insts, n, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_target(const BatchInst *insts, uint32_t n, uint32_t add, uint32_t every,
+                               hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_batch_target, dim3((n + 255u) / 256u), dim3(256), 0, stream, insts, n, add,
+                     every);
+  return hipGetLastError();
 }
 
 }  // namespace ptmi

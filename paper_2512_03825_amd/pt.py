@@ -18,14 +18,15 @@ PT_ABI_VERSION = 1
 PT_ALL_SLOTS = 0xFFFFFFFF
 PT_MAX_SWEEPS_PER_LAUNCH = 8
 PT_ISING2D, PT_EA3D = 0, 1
-PT_PLAN_AUTO, PT_PLAN_FUSED, PT_PLAN_TILED = 0, 1, 2
+PT_PLAN_AUTO, PT_PLAN_FUSED, PT_PLAN_TILED, PT_PLAN_PERSISTENT = 0, 1, 2, 3
 STATUS = {0: "PT_OK", -1: "PT_EINVAL", -2: "PT_ENOMEM", -3: "PT_EDEVICE", -4: "PT_ESTATE",
           -5: "PT_EUNSUPPORTED"}
 
 # Every symbol include/pt.h declares.
 EXPORTS = ("pt_workspace_bytes", "pt_create", "pt_set_plan", "pt_get_plan", "pt_sweep",
            "pt_exchange", "pt_run", "pt_observables", "pt_flip_thresholds", "pt_swap_threshold",
-           "pt_destroy", "pt_last_error")
+           "pt_destroy", "pt_last_error", "pt_batch_workspace_bytes", "pt_batch_create",
+           "pt_batch_run", "pt_batch_observables", "pt_batch_group_plan", "pt_batch_destroy")
 
 
 class PTError(RuntimeError):
@@ -80,6 +81,12 @@ def _load():
         "pt_swap_threshold": (st, [vp, C.c_uint32, C.c_int64, P(C.c_uint64)]),
         "pt_destroy": (None, [vp]),
         "pt_last_error": (C.c_char_p, []),
+        "pt_batch_workspace_bytes": (C.c_size_t, [P(pt_config), C.c_uint32]),
+        "pt_batch_create": (st, [P(pt_config), C.c_uint32, vp, vp, C.c_size_t, P(vp)]),
+        "pt_batch_run": (st, [vp, C.c_uint32, C.c_uint32]),
+        "pt_batch_observables": (st, [vp, C.c_uint32, P(pt_obs)]),
+        "pt_batch_group_plan": (st, [vp, C.c_uint32, P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]),
+        "pt_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -172,6 +179,10 @@ def pt_run(ctx, n_sweeps: int, exchange_every: int):
 
 def pt_observables(ctx, R: int, N: int, max_records: int, spins=None, series=True) -> dict:
     """spins: None, a slot index, or "all" (slot order)."""
+    return _observe(lambda o: _lib.pt_observables(ctx, C.byref(o)), R, N, max_records, spins, series)
+
+
+def _observe(call, R, N, max_records, spins, series):
     o = pt_obs()
     E_slot = np.zeros(R, np.int32)
     M_slot = np.zeros(R, np.int32)
@@ -195,7 +206,7 @@ def pt_observables(ctx, R: int, N: int, max_records: int, spins=None, series=Tru
             sp = np.zeros(N, np.int8)
             o.spins_slot = int(spins)
         o.spins = _p(sp, C.c_int8)
-    _check(_lib.pt_observables(ctx, C.byref(o)))
+    _check(call(o))
     n = int(o.n_records)
     return {"E_slot": E_slot, "M_slot": M_slot, "swap_att": att, "swap_acc": acc,
             "walker_at": wat, "spins": sp,
@@ -264,6 +275,59 @@ class Simulation:
             except TypeError:  # interpreter shutdown already tore down ctypes
                 pass
             self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+
+def pt_batch_workspace_bytes(cfgs) -> int:
+    arr = (pt_config * len(cfgs))(*[c.c for c in cfgs])
+    n = _lib.pt_batch_workspace_bytes(arr, len(cfgs))
+    if n == 0:
+        raise PTError(-1, _lib.pt_last_error().decode())
+    return int(n)
+
+
+class Batch:
+    """Many instances advanced together (pt_batch_*), torch-owned workspace."""
+
+    def __init__(self, cfgs, device="cuda", stream=None):
+        import torch
+        self.cfgs = list(cfgs)
+        self._arr = (pt_config * len(self.cfgs))(*[c.c for c in self.cfgs])
+        self.nbytes = pt_batch_workspace_bytes(self.cfgs)
+        self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        out = C.c_void_p()
+        _check(_lib.pt_batch_create(self._arr, len(self.cfgs), C.c_void_p(self.stream.cuda_stream),
+                                    C.c_void_p(ptr), C.c_size_t(self.nbytes), C.byref(out)))
+        self.b = out
+
+    def run(self, n_sweeps, exchange_every):
+        _check(_lib.pt_batch_run(self.b, int(n_sweeps), int(exchange_every)))
+
+    def observables(self, i, spins=None, series=True):
+        c = self.cfgs[i]
+        return _observe(lambda o: _lib.pt_batch_observables(self.b, int(i), C.byref(o)), c.R, c.N,
+                        c.c.max_records, spins, series)
+
+    def group_plans(self):
+        out, g = [], 0
+        while True:
+            L, W, T = C.c_uint32(), C.c_uint32(), C.c_uint32()
+            if _lib.pt_batch_group_plan(self.b, g, C.byref(L), C.byref(W), C.byref(T)) != 0:
+                return out
+            out.append({"L": L.value, "walkers_per_wg": W.value, "block_threads": T.value})
+            g += 1
+
+    def close(self):
+        if getattr(self, "b", None):
+            try:
+                _lib.pt_batch_destroy(self.b)
+            except TypeError:
+                pass
+            self.b = None
 
     def __del__(self):
         self.close()

@@ -1,0 +1,109 @@
+"""Full-size workloads on the GPU, in the launch configuration bench.py times.
+
+- A prefix of each full-size schedule is compared bit for bit with values the
+  CPU oracle wrote (tests/golden/*.json, made by tests/golden/make_golden.py):
+  record series, walker map, swap counts and a SHA-256 of every final spin.
+- Longer runs are checked through properties that hold at any size: the
+  incrementally tracked E and M equal a recount of the final lattices, the
+  walker map stays a permutation, swap counts follow the alternating pairing,
+  the hottest slot's energy per site matches Onsager's closed form (2D Ising),
+  and the mean energy falls as beta grows (d<E>/d beta = -Var E < 0), which
+  holds at any size for the +-J EA model too.
+"""
+import hashlib
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from gpu_common import requires_gpu, say
+from paper_2512_03825_amd.workloads import HOT_PATH
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def pt():
+    from paper_2512_03825_amd import pt as _pt
+    return _pt
+
+
+def make_sim(pt, w, max_records):
+    cfg = pt.Config(w.model, w.L, w.R, w.beta, J=w.J, seed=w.seed, coupling_seed=w.coupling_seed,
+                    record_every=w.record_every, max_records=max_records)
+    return pt.Simulation(cfg)
+
+
+@pytest.mark.parametrize("name", ["ising2d_L1024_R64", "ea3d_L32_R128"])
+def test_fullsize_prefix_matches_oracle(pt, name):
+    g = json.load(open(os.path.join(GOLDEN, name + ".json")))
+    w = HOT_PATH[name]
+    assert g["L"] == w.L and g["R"] == w.R and g["seed"] == w.seed
+    assert np.array_equal(np.array(g["beta"]), w.beta)
+    say("full-size prefix", name, "sweeps", g["sweeps"])
+    sim = make_sim(pt, w, g["sweeps"])
+    sim.run(g["sweeps"], w.exchange_every)
+    obs = sim.observables(spins="all")
+    np.testing.assert_array_equal(obs["E_series"], np.array(g["E_series"], np.int32))
+    np.testing.assert_array_equal(obs["M_series"], np.array(g["M_series"], np.int32))
+    np.testing.assert_array_equal(obs["walker_at"], np.array(g["labels"], np.uint32))
+    for k in range(w.R - 1):
+        assert obs["swap_att"][k, k + 1] == g["swap_att"][k]
+        assert obs["swap_acc"][k, k + 1] == g["swap_acc"][k]
+    assert hashlib.sha256(obs["spins"].tobytes()).hexdigest() == g["spins_sha256"]
+
+
+def recount(spins, L, dim, bonds=None):
+    """E_int and M of +-1 lattices [R][N] (numpy, each bond once)."""
+    s = spins.astype(np.int64).reshape((spins.shape[0],) + (L,) * dim)
+    E = np.zeros(spins.shape[0], np.int64)
+    for ax in range(1, dim + 1):
+        prod = s * np.roll(s, -1, axis=ax)
+        if bonds is not None:
+            prod = prod * bonds[dim - ax]  # axis 1 = z (3D) ... last axis = x
+        E -= prod.reshape(spins.shape[0], -1).sum(1)
+    return E, s.reshape(spins.shape[0], -1).sum(1)
+
+
+def onsager_u(beta):
+    from scipy.special import ellipk
+    k = 2.0 * math.sinh(2 * beta) / math.cosh(2 * beta) ** 2
+    return -1.0 / math.tanh(2 * beta) * (1 + 2 / math.pi * (2 * math.tanh(2 * beta) ** 2 - 1) * ellipk(k * k))
+
+
+@pytest.mark.parametrize("name, sweeps", [("ising2d_L1024_R64", 1000), ("ea3d_L32_R128", 2000)])
+def test_fullsize_long_run_properties(pt, oracle_mod, name, sweeps):
+    w = HOT_PATH[name]
+    say("full-size run", name, "sweeps", sweeps)
+    sim = make_sim(pt, w, sweeps)
+    sim.run(sweeps, w.exchange_every)
+    obs = sim.observables(spins="all")
+    N = w.sites
+    bonds = None
+    if w.dim == 3:
+        # the couplings the library drew: the oracle draws the same stream, and the
+        # EA gauge-independent checks below only need them for the recount
+        o = oracle_mod.Oracle(w.model, w.L, 1, w.beta[:1], seed=w.seed, coupling_seed=w.coupling_seed)
+        J = o.couplings().astype(np.int64)  # [3][N], bond (i, i+e_d), d = x, y, z
+        bonds = [J[d].reshape((w.L,) * 3) for d in range(3)]  # indexed [z][y][x]
+    E, M = recount(obs["spins"], w.L, w.dim, bonds)
+    np.testing.assert_array_equal(obs["E_slot"], E)
+    np.testing.assert_array_equal(obs["M_slot"], M)
+    # the last record precedes the final exchange step: same energies, maybe permuted
+    np.testing.assert_array_equal(np.sort(obs["E_series"][-1]), np.sort(E))
+    assert sorted(obs["walker_at"].tolist()) == list(range(w.R))
+    steps = sweeps // w.exchange_every
+    for k in range(w.R - 1):
+        # pair (k, k+1) is attempted on the steps with parity k mod 2
+        assert obs["swap_att"][k, k + 1] == (steps + 1 - (k % 2)) // 2
+        assert obs["swap_acc"][k, k + 1] <= obs["swap_att"][k, k + 1]
+    half = obs["E_series"][sweeps // 2:] / N  # second half of the run, per slot
+    if w.dim == 2:
+        assert abs(half[:, 0].mean() - onsager_u(w.beta[0])) < 0.005, half[:, 0].mean()
+    means = half.mean(0)
+    picks = [0, w.R // 4, w.R // 2, 3 * w.R // 4, w.R - 1]
+    assert all(means[a] > means[b] for a, b in zip(picks, picks[1:])), means[picks]
+    assert np.all(np.abs(obs["E_series"]) <= w.dim * N)

@@ -14,7 +14,7 @@ from paper_2512_03825_amd.workloads import beta_geometric, beta_linear, ising16
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
-FUSED, TILED = 1, 2
+FUSED, TILED, PERSISTENT = 1, 2, 3
 
 
 @pytest.fixture(scope="module")
@@ -117,6 +117,46 @@ def test_ea8(pt, oracle_mod, plan):
 def test_ea16(pt, oracle_mod, plan):
     beta = beta_geometric(0.5, 3.0, 4)
     run_case(pt, oracle_mod, 1, 16, 4, beta, 3, 20, 1, plan=plan, coupling_seed=5, tag="ea16")
+
+
+@pytest.mark.parametrize("model, L, R, every, threads", [
+    (0, 16, 8, 10, 256),    # the 16x16 workload's shape
+    (0, 32, 7, 1, 128),     # odd R, exchange every sweep
+    (0, 64, 12, 3, 512),
+    (1, 8, 6, 1, 256),
+    (1, 16, 5, 2, 1024),
+    (1, 32, 4, 1, 1024),    # the EA workload's lattice
+])
+def test_persistent_plan(pt, oracle_mod, model, L, R, every, threads):
+    """One workgroup per walker for the whole run; pairwise exchange decisions."""
+    beta = beta_geometric(0.5, 3.0, R) if model == 1 else beta_geometric(0.2, 0.6, R)
+    plan = dict(mode=PERSISTENT, block_threads=threads)
+    run_case(pt, oracle_mod, model, L, R, beta, 17, 40, every, plan=plan, coupling_seed=4,
+             tag="persist")
+    run_case(pt, oracle_mod, model, L, R, beta, 17, 24, every, plan=plan, coupling_seed=4,
+             split=True, tag="persist-split")
+
+
+@pytest.mark.parametrize("h, plan", [
+    (0.05, None),
+    (-0.08, dict(mode=TILED, tile_planes=8, sweeps_per_launch=2, block_threads=256)),
+    (0.1, dict(mode=FUSED, block_threads=256)),
+    (0.3, dict(mode=TILED, tile_planes=32, sweeps_per_launch=5, block_threads=256)),
+])
+def test_field(pt, oracle_mod, h, plan):
+    """h != 0: ten flip classes and the factorised field swap rule."""
+    beta = beta_linear(0.30, 0.55, 6)
+    rec = 60
+    cfg_kw = dict(seed=19, record_every=1, max_records=rec)
+    sim = pt.Simulation(pt.Config(0, 32, 6, beta, h=h, **cfg_kw))
+    if plan is not None:
+        sim.set_plan(**plan)
+    orc = oracle_mod.Oracle(0, 32, 6, beta, h=h, **cfg_kw)
+    say("case field h", h, "plan", plan)
+    sim.run(rec, 1)
+    orc.run(rec, 1)
+    compare(sim, orc, "field")
+    assert orc.swaps()[1].sum() > 0
 
 
 def test_primitive_calls_equal_run(pt, oracle_mod):

@@ -66,11 +66,10 @@ def test_invalid_configs(pt, kw, msg):
     assert e.value.status == -1
 
 
-def test_field_is_reported_unsupported(pt):
-    cfg = pt.Config(0, 16, 2, np.array([0.3, 0.4]), h=0.05)
-    with pytest.raises(pt.PTError) as e:
-        pt.pt_create(cfg, 0, 256, 1 << 30)
-    assert e.value.status == -5
+def test_field_is_accepted_and_must_be_finite(pt):
+    assert pt.pt_workspace_bytes(pt.Config(0, 16, 2, np.array([0.3, 0.4]), h=0.05)) > 0
+    with pytest.raises(pt.PTError, match="h is not finite"):
+        pt.pt_workspace_bytes(pt.Config(0, 16, 2, np.array([0.3, 0.4]), h=float("inf")))
 
 
 def test_create_checks_buffers_before_device_work(pt):

@@ -47,10 +47,51 @@ def parse():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
+    ap.add_argument("--form", choices=["plain", "batched"], default="plain",
+                    help="plain: one PT instance (the default workload); batched: 2048 "
+                         "independent instances advanced together, against the per-instance path")
+    ap.add_argument("--batch-instances", type=int, default=2048)
+    ap.add_argument("--batch-sweeps", type=int, default=2000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 64 MiB device-to-device copy (a kernel of known "
                          "traffic, to scale HBM counters)")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ("paper_2512_03825_amd/csrc/pt_kernels.hip", "paper_2512_03825_amd/csrc/pt_internal.h")
+
+
+def kernel_source_hash():
+    """sha256 over the device-kernel sources (ties an HBM counter reading to the code it measured)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, plan, per_launch):
+    """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE passes
+    summarised under profiles/ (each counter scaled by what it reads for a plain
+    copy of known size).  None when there is no such summary, or when it was
+    taken on other kernel sources, another plan or another launch length."""
+    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload))
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                fields[k] = v.strip("` ")
+    want = {"kernel_source_sha256": kernel_source_hash(),
+            "plan": "mode=%d tile_planes=%d sweeps_per_launch=%d block_threads=%d" % (
+                plan["mode"], plan["tile_planes"], plan["sweeps_per_launch"], plan["block_threads"]),
+            "sweeps_per_launch_measured": str(per_launch)}
+    if any(fields.get(k) != v for k, v in want.items()) or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(w, sweeps):
@@ -66,8 +107,64 @@ def cpu_baseline(w, sweeps):
                       "single thread)" % (w.name, sweeps, attempts, dt)}
 
 
+def bench_batched(args):
+    """Batched form: every instance advanced by the same schedule in one batch,
+    timed against running the same instances one after another."""
+    import torch
+
+    from paper_2512_03825_amd import pt
+    from paper_2512_03825_amd.workloads import batched2048
+
+    ws = batched2048(n=args.batch_instances)
+    every, sweeps = ws[0].exchange_every, args.batch_sweeps
+    cfgs = [pt.Config(w.model, w.L, w.R, w.beta, h=w.h, seed=w.seed, stream_id=w.stream_id)
+            for w in ws]
+    torch.cuda.set_device(0)
+    batch = pt.Batch(cfgs, device="cuda:0")
+    # warm-up: the tuning cycles of the first run pick each group's decomposition
+    batch.run(10 * every, every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.run(sweeps, every)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    attempts = sweeps * sum(w.attempts_per_sweep for w in ws)
+    plans = batch.group_plans()
+    batch.close()
+    del batch
+    # the plain per-instance path on the same instances (a prefix of the schedule each)
+    per_sweeps = 4 * every
+    sims = [pt.Simulation(c, device="cuda:0") for c in cfgs]
+    for s in sims:
+        s.run(every, every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in sims:
+        s.run(per_sweeps, every)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t0
+    single = per_sweeps * sum(w.attempts_per_sweep for w in ws) / dt1
+    for s in sims:
+        s.close()
+    out = {"metric": "spin-flip attempts/s", "value": attempts / dt, "unit": "flip attempts/s",
+           "n_gpus": 1, "steps": sweeps // every, "warmup": 10, "ms_per_step": dt / (sweeps / every) * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic",
+           "config": {"workload": "batched%d" % len(ws), "instances": len(ws), "sweeps": sweeps,
+                      "exchange_every": every, "L": sorted({w.L for w in ws}),
+                      "R": sorted({w.R for w in ws}), "h": [-0.1, 0.1], "group_plans": plans,
+                      "parallelism": "single GPU"},
+           "per_instance_path": {"value": single, "unit": "flip attempts/s",
+                                 "sample": "same %d instances one after another, %d sweeps each"
+                                           % (len(ws), per_sweeps)},
+           "speedup_vs_per_instance": (attempts / dt) / single}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.form == "batched" and args.gpus == 1:
+        return bench_batched(args)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
               "(the path would shard by temperature slots, see the design notes)" % args.gpus,
@@ -82,9 +179,12 @@ def main():
     w = HOT_PATH[args.workload]
     torch.cuda.set_device(0)
     every = w.exchange_every
-    sweeps_per_step = every if every > 0 else 10
+    # a step is 10 sweeps of the workload's schedule (a whole number of
+    # exchange intervals), so one step is one launch for the fused and
+    # persistent plans and a few launches for the tiled plan
+    sweeps_per_step = every * max(1, 10 // every) if every > 0 else 10
     roof_launches = 200
-    total_sweeps = (args.warmup + args.steps) * sweeps_per_step + roof_launches * 8
+    total_sweeps = (args.warmup + args.steps + roof_launches) * sweeps_per_step
     cfg = pt.Config(w.model, w.L, w.R, w.beta, J=w.J, seed=w.seed, coupling_seed=w.coupling_seed,
                     record_every=w.record_every, max_records=total_sweeps // w.record_every)
     sim = pt.Simulation(cfg, device="cuda:0")
@@ -111,9 +211,12 @@ def main():
 
     # roofline of the sweep kernel: HIP events around single launches on the
     # library's stream (each pt_run call below is exactly one kernel launch)
-    per_launch = plan["sweeps_per_launch"] if plan["mode"] == pt.PT_PLAN_TILED else 1
-    if every:
-        per_launch = max(d for d in range(1, per_launch + 1) if every % d == 0)
+    if plan["mode"] == pt.PT_PLAN_TILED:
+        per_launch = plan["sweeps_per_launch"]
+        if every:
+            per_launch = max(d for d in range(1, per_launch + 1) if every % d == 0)
+    else:
+        per_launch = sweeps_per_step  # the whole step runs inside one launch
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(roof_launches)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(roof_launches)]
     with torch.cuda.stream(stream):
@@ -132,9 +235,13 @@ def main():
     halo_planes = 2 * 2 * per_launch * tiles if tiles > 1 else 0
     plane_bits = w.L ** (w.dim - 1)
     hbm_bytes = w.R * ((w.L + halo_planes) * plane_bits + w.L * plane_bits) / 8
+    if w.dim == 3:
+        hbm_bytes += 3 * w.sites / 8 * (tiles if tiles > 1 else 1)  # packed couplings, read once per tile
+    kernel = {pt.PT_PLAN_TILED: "k_tiled", pt.PT_PLAN_FUSED: "k_fused",
+              pt.PT_PLAN_PERSISTENT: "k_persist"}[plan["mode"]]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 VALU lane slots)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": None, "kernel": "k_tiled" if plan["mode"] == pt.PT_PLAN_TILED else "k_fused",
+                "traffic": measured_traffic(kernel, w.name, plan, per_launch), "kernel": kernel,
                 "slots_per_attempt": SLOTS_PER_ATTEMPT[w.dim],
                 "avg_launch_ms": round(avg_ms, 5), "median_launch_ms": round(durs[len(durs) // 2], 5),
                 "sweeps_per_launch": per_launch,
@@ -151,7 +258,7 @@ def main():
         del a, b
 
     obs = sim.observables(series=False)
-    assert obs["sweeps_done"] == total_sweeps - roof_launches * 8 + roof_launches * per_launch
+    assert obs["sweeps_done"] == (args.warmup + args.steps) * sweeps_per_step + roof_launches * per_launch
 
     out = {
         "metric": "spin-flip attempts/s", "value": value, "unit": "flip attempts/s",

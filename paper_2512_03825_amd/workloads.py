@@ -86,3 +86,18 @@ def ea32() -> Workload:
 
 
 HOT_PATH = {w.name: w for w in (ising16(), ising1024(), ea32())}
+
+
+def batched2048(seed: int = 4, n: int = 2048):
+    """Independent 2D Ising PT instances run together: L uniform in {32, 64, 128,
+    256}, R uniform in {16, 32, 64}, beta linear over [0.30, 0.55], field h
+    uniform in [-0.1, 0.1]; 2000 sweeps with an exchange step every 5.  Instance
+    i uses Philox stream_id i under the common seed."""
+    rng = np.random.default_rng(seed)
+    Ls = rng.choice([32, 64, 128, 256], size=n)
+    Rs = rng.choice([16, 32, 64], size=n)
+    hs = rng.uniform(-0.1, 0.1, size=n)
+    return [Workload("batched_%d" % i, ISING2D, int(Ls[i]), int(Rs[i]),
+                     beta_linear(0.30, 0.55, int(Rs[i])), sweeps=2000, exchange_every=5,
+                     record_every=0, seed=seed, h=float(hs[i]), stream_id=i)
+            for i in range(n)]

@@ -47,11 +47,15 @@ def parse():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
-    ap.add_argument("--form", choices=["plain", "batched"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batched", "served"], default="plain",
                     help="plain: one PT instance (the default workload); batched: 2048 "
-                         "independent instances advanced together, against the per-instance path")
+                         "independent instances advanced together, against the per-instance path; "
+                         "served: a Poisson stream of jobs through the request loop")
     ap.add_argument("--batch-instances", type=int, default=2048)
     ap.add_argument("--batch-sweeps", type=int, default=2000)
+    ap.add_argument("--jobs", type=int, default=400, help="served form: jobs in the stream")
+    ap.add_argument("--rho", type=float, default=0.8, help="served form: offered load / capacity")
+    ap.add_argument("--arena-gib", type=float, default=8.0, help="served form: job arena (GiB)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 64 MiB device-to-device copy (a kernel of known "
                          "traffic, to scale HBM counters)")
@@ -161,10 +165,121 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def _serve(pt, srv, cfgs, ws, arrivals, t_label):
+    """Submit job i at arrivals[i] seconds (server clock) and run the request
+    loop until every job has finished; returns the finished-job records."""
+    n = len(cfgs)
+    t0 = srv.clock()
+    nxt, out, last_note = 0, [], time.time()
+    while len(out) < n:
+        now = srv.clock() - t0
+        while nxt < n and arrivals[nxt] <= now:
+            srv.submit(cfgs[nxt], ws[nxt].sweeps, ws[nxt].exchange_every, arrival=t0 + arrivals[nxt])
+            nxt += 1
+        wait = 2000 if nxt >= n else int(max(0.0, min(2e-3, arrivals[nxt] - now)) * 1e6)
+        srv.step(wait_us=wait)
+        for f in srv.done():
+            f["arrival"] -= t0
+            f["finished"] -= t0
+            f["admitted"] -= t0
+            out.append(f)
+            srv.release(f["job_id"])
+        if time.time() - last_note > 10:
+            st = srv.stats()
+            print("[%s] t=%.1fs submitted %d finished %d resident %d pending %d" % (
+                t_label, now, nxt, len(out), st["resident"], st["pending"]), file=sys.stderr, flush=True)
+            last_note = time.time()
+    return out
+
+
+def bench_served(args):
+    """Served form: a Poisson stream of PT jobs through the request loop at
+    offered load rho of the server's measured capacity; p50/p99 latency and
+    aggregate flips/s, beside the plain per-instance path serving the same
+    stream one job at a time (first come, first served)."""
+    import numpy as np
+    import torch
+
+    from paper_2512_03825_amd import pt
+    from paper_2512_03825_amd.workloads import poisson_arrivals, served_jobs
+
+    torch.cuda.set_device(0)
+    ws = served_jobs(n=args.jobs)
+    cfgs = [pt.Config(w.model, w.L, w.R, w.beta, J=w.J, h=w.h, seed=w.seed, stream_id=w.stream_id,
+                      coupling_seed=w.coupling_seed, record_every=w.record_every,
+                      max_records=w.sweeps // w.record_every) for w in ws]
+    att = np.array([w.attempts_per_sweep * w.sweeps for w in ws], dtype=np.float64)
+    opts = dict(max_jobs=4096, max_walkers=1 << 20, tiled_lanes=2, depth=2, cycle_sweeps=10,
+                tiled_sweeps=10)
+    srv = pt.Server(int(args.arena_gib * (1 << 30)), device="cuda:0", **opts)
+    # capacity: the same jobs cut to 500 sweeps, all submitted at once
+    cap_ws = [w for w in ws[:200]]
+    cap_cfgs = cfgs[:200]
+    import copy
+    cut = []
+    for w in cap_ws:
+        w2 = copy.copy(w)
+        w2.sweeps = min(w.sweeps, 500)
+        cut.append(w2)
+    t = time.perf_counter()
+    _serve(pt, srv, cap_cfgs, cut, np.zeros(len(cut)), "capacity")
+    cap_dt = time.perf_counter() - t
+    C = sum(w.attempts_per_sweep * w.sweeps for w in cut) / cap_dt
+    lam = args.rho * C / att.mean()
+    arrivals = poisson_arrivals(lam, len(ws))
+    t = time.perf_counter()
+    fin = _serve(pt, srv, cfgs, ws, arrivals, "served rho=%.2f" % args.rho)
+    dt = time.perf_counter() - t
+    srv.close()
+    lat = np.array([f["finished"] - f["arrival"] for f in fin])
+    span = max(f["finished"] for f in fin) - min(f["arrival"] for f in fin)
+    value = att.sum() / span
+
+    # the plain per-instance path: each job's service time from a short timed
+    # run of the same configuration (100 sweeps, after creation), then the
+    # same arrivals served first come, first served
+    svc = np.zeros(len(ws))
+    for i, (w, c) in enumerate(zip(ws, cfgs)):
+        sim = pt.Simulation(c, device="cuda:0")
+        n = min(w.sweeps, 100)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sim.run(n, w.exchange_every)
+        torch.cuda.synchronize()
+        svc[i] = (time.perf_counter() - t1) * w.sweeps / n
+        sim.close()
+        del sim
+    free_at, plain_lat = 0.0, np.zeros(len(ws))
+    for i in range(len(ws)):
+        start = max(free_at, arrivals[i])
+        free_at = start + svc[i]
+        plain_lat[i] = free_at - arrivals[i]
+    plain_capacity = att.sum() / svc.sum()
+    out = {"metric": "served-job latency p50/p99 + flip attempts/s", "value": value,
+           "unit": "flip attempts/s", "n_gpus": 1, "steps": len(ws), "warmup": 0,
+           "ms_per_step": dt / len(ws) * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": "served%d" % len(ws), "jobs": len(ws), "rho": args.rho,
+                      "arrival_rate_per_s": lam, "mean_attempts_per_job": float(att.mean()),
+                      "server": opts, "arena_bytes": int(args.arena_gib * (1 << 30)),
+                      "parallelism": "single GPU"},
+           "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                         "max": float(lat.max())},
+           "capacity": {"served": C, "plain_per_instance": plain_capacity,
+                        "sample": "served: first %d jobs cut to 500 sweeps, all at t=0 (%.1f s); "
+                                  "plain: every job's 100-sweep run scaled to its length" % (len(cut), cap_dt)},
+           "plain_fifo_latency_s": {"p50": float(np.percentile(plain_lat, 50)),
+                                    "p99": float(np.percentile(plain_lat, 99))},
+           "speedup_vs_per_instance": C / plain_capacity}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.form == "batched" and args.gpus == 1:
         return bench_batched(args)
+    if args.form == "served" and args.gpus == 1:
+        return bench_served(args)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
               "(the path would shard by temperature slots, see the design notes)" % args.gpus,

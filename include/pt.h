@@ -221,6 +221,89 @@ pt_status pt_batch_group_plan(const pt_batch *b, uint32_t g, uint32_t *L, uint32
                               uint32_t *block_threads);
 void pt_batch_destroy(pt_batch *b);
 
+/* ---- served form: a request loop over jobs that arrive at any time ----------
+ * A server owns one device arena (the caller's memory) and admits submitted
+ * jobs in arrival order while their footprint (pt_workspace_bytes) fits the
+ * free arena, the resident-job limit and the resident-walker limit.  An admitted
+ * job's lattices, tables, random-stream position and counters stay on the
+ * device until it finishes.  Jobs whose replicas fit one workgroup's LDS
+ * (2D L <= 256, EA L <= 32) join the batched lane: one stream whose cycles run
+ * up to cycle_sweeps sweeps of every resident job in one launch per lattice-size
+ * group, then their exchange steps (the batched form's kernels, membership
+ * changing between cycles as jobs arrive and finish).  Larger lattices run on
+ * tiled lanes: further streams on which each resident job advances by
+ * tiled_sweeps sweeps per step, so their kernels overlap with the batched lane.
+ * A job's results depend only on its own pt_config (seed, stream_id, ...) and
+ * schedule, never on what else is resident: they are bit-identical to running
+ * it alone with pt_run(ctx, n_sweeps, exchange_every).  When a job finishes its
+ * observables are copied to host memory and its arena slice is freed at once.
+ * All work runs on streams the server creates (default priority, non-blocking).
+ * One server must not be used from two threads at once. */
+typedef struct pt_server pt_server;
+
+typedef struct {
+  uint32_t max_jobs;       /* resident jobs at once, 1 .. 65536 */
+  uint32_t max_walkers;    /* resident replicas of batched-lane jobs at once (sum of R) */
+  uint32_t tiled_lanes;    /* streams for jobs too large for the batched lane, 1 .. 8 */
+  uint32_t depth;          /* steps in flight per lane, 1 .. 8 */
+  uint32_t cycle_sweeps;   /* batched lane: at most this many sweeps per cycle, 1 .. 16 */
+  uint32_t tiled_sweeps;   /* tiled lanes: sweeps per job per step, 1 .. 4096 */
+} pt_server_opts;
+
+#define PT_JOB_KEEP_SPINS 1u /* keep the final lattices of all slots with the results */
+
+typedef struct {
+  uint64_t job_id;
+  double arrival;          /* seconds on the server clock (as submitted) */
+  double admitted;         /* when its initialisation was queued */
+  double finished;         /* when the host saw its last step complete */
+  uint64_t attempts;       /* R * L^dim * n_sweeps */
+  uint32_t lane;           /* 0 batched, 1 .. tiled lanes */
+  uint32_t pad;
+} pt_job_info;
+
+typedef struct {
+  uint64_t submitted, pending, resident, finished;
+  uint64_t arena_bytes, arena_used, arena_peak;
+  uint64_t walkers_resident;
+  uint64_t batched_cycles, tiled_steps;
+  uint64_t attempts_finished;
+} pt_server_stats;
+
+/* Device bytes the server keeps for its own tables ahead of the job arena. */
+size_t pt_server_overhead_bytes(const pt_server_opts *opts);
+/* Create a server on d_workspace (caller-owned, 256-byte aligned); the arena
+ * for jobs is ws_bytes - pt_server_overhead_bytes(opts).  Uses the current HIP
+ * device.  PT_ENOMEM if the workspace cannot hold the tables. */
+pt_status pt_server_create(const pt_server_opts *opts, void *d_workspace, size_t ws_bytes,
+                           pt_server **out);
+/* Queue a job: cfg (copied; no init_spins or couplings uploads; record_every
+ * needs max_records >= n_sweeps / record_every), n_sweeps in [1, 2^32 - 1]
+ * sweeps with an exchange step after every exchange_every-th (0 = none), flags
+ * (PT_JOB_KEEP_SPINS), arrival time on the server clock (negative = now).
+ * PT_EINVAL for an invalid job, PT_ENOMEM if it could never fit the arena. */
+pt_status pt_server_submit(pt_server *sv, const pt_config *cfg, uint64_t n_sweeps,
+                           uint32_t exchange_every, uint32_t flags, double arrival,
+                           uint64_t *job_id);
+/* One turn of the request loop: retire jobs whose last step has completed
+ * (results to host, memory freed), admit queued jobs that now fit, and keep
+ * `depth` steps in flight on every lane that has work.  If nothing completed,
+ * waits up to wait_us microseconds for a step to complete.  *n_finished (may be
+ * NULL) = jobs retired by this call. */
+pt_status pt_server_step(pt_server *sv, uint32_t wait_us, uint32_t *n_finished);
+/* Pop up to cap finished jobs (in completion order) into out; *n = count. */
+pt_status pt_server_done(pt_server *sv, pt_job_info *out, uint32_t cap, uint32_t *n);
+/* Results of a finished job, as pt_observables would give them (spins only with
+ * PT_JOB_KEEP_SPINS).  PT_ESTATE if the job has not finished. */
+pt_status pt_server_result(const pt_server *sv, uint64_t job_id, pt_obs *obs);
+/* Drop a finished job's host-side results. */
+pt_status pt_server_release(pt_server *sv, uint64_t job_id);
+pt_status pt_server_stats_get(const pt_server *sv, pt_server_stats *out);
+/* Seconds since the server was created (monotonic host clock). */
+double pt_server_clock(const pt_server *sv);
+/* Wait for all queued device work, then free the host state (never the workspace). */
+void pt_server_destroy(pt_server *sv);
+
 /* Thread-local message of the last failure on this thread ("" if none). */
 const char *pt_last_error(void);
 

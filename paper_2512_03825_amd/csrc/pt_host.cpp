@@ -1,8 +1,7 @@
 // pt_host.cpp -- host side of the parallel-tempering Metropolis library: the C
 // ABI of include/pt.h, configuration checks, the FP64 threshold tables, the
 // workspace layout, plan selection and the launch schedule.
-#include "pt.h"
-#include "pt_internal.h"
+#include "pt_host.h"
 
 #include <algorithm>
 #include <cmath>
@@ -18,8 +17,10 @@
 using namespace ptmi;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace ptmi {
 
 pt_status fail(pt_status st, const char *fmt, ...) {
   char buf[512];
@@ -31,6 +32,20 @@ pt_status fail(pt_status st, const char *fmt, ...) {
   return st;
 }
 
+uint32_t records_between(uint32_t every, uint64_t s0, uint64_t s1) {
+  return every ? (uint32_t)(s1 / every - s0 / every) : 0u;
+}
+
+uint32_t lg2(uint32_t v) {
+  uint32_t r = 0;
+  while ((1u << r) < v) ++r;
+  return r;
+}
+
+}  // namespace ptmi
+
+namespace {
+
 bool is_pow2(uint32_t v) { return v && !(v & (v - 1u)); }
 
 constexpr uint32_t kMaxR = 4096;
@@ -38,13 +53,11 @@ constexpr uint32_t kFusedChunk = 4096;   // sweeps per fused or persistent launc
 // Polls of a partner's mailbox (each followed by a short sleep) before a
 // persistent launch gives up: orders of magnitude above any legitimate wait.
 constexpr uint32_t kSpinLimit = 1u << 24;
-constexpr size_t kAlign = 256;
 
 // Saturation of the logistic swap rule: beyond |x| >= 32 ln 2 the decision no
 // longer depends on the 32-bit draw.
 constexpr double kSwapSat = 0x1.62e42fefa39efp+4;
 
-size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 // ---- acceptance rules, FP64, evaluated once per table entry ---------------
 // Eq. (1) with the Boltzmann target of Eq. (2): accept a flip with energy
@@ -67,26 +80,8 @@ uint64_t swap_threshold(double dbeta, double dE) {
   return (uint64_t)std::ceil(std::ldexp(p, 32));
 }
 
-struct Tables {
-  std::vector<uint32_t> flip; // [R][16]
-  std::vector<uint64_t> swap; // concatenated pair tables
-  std::vector<uint32_t> off;  // [R]
-  std::vector<uint32_t> D;    // [R]
-  std::vector<uint64_t> sat;  // [R][2]
-  std::vector<uint64_t> field; // [R][kFieldDigits]
-  std::vector<int32_t> fsign;  // [R]
-};
 
-struct Layout {
-  size_t spins[2], bonds, staging, flip, swap_tab, swap_off, swap_D, swap_sat, wat, sof, E, M,
-      acc3, att, acc, Es, Ms, counter, mailbox, field, fsign, total;
-};
 
-struct Derived {
-  Geometry geo;
-  double jscale; // energy unit of E_int: J (2D), 1 (EA)
-  uint32_t z;    // coordination number
-};
 
 pt_status derive(const pt_config *cfg, Derived *d) {
   if (!cfg) return fail(PT_EINVAL, "config is NULL");
@@ -223,27 +218,8 @@ void build_tables(const pt_config *cfg, const Derived &d, Tables *t) {
     }
 }
 
-uint32_t records_between(uint32_t every, uint64_t s0, uint64_t s1) {
-  return every ? (uint32_t)(s1 / every - s0 / every) : 0u;
-}
-
 }  // namespace
 
-struct pt_ctx {
-  pt_config cfg;
-  std::vector<double> beta;
-  Derived d;
-  Keys keys;
-  DevState st;
-  Layout lay;
-  Tables tab;
-  hipStream_t stream;
-  pt_plan plan;
-  uint64_t sweeps = 0, exchanges = 0;
-  uint32_t n_records = 0;
-  uint32_t cur = 0;
-  bool poisoned = false;
-};
 
 namespace {
 
@@ -344,9 +320,11 @@ pt_status usable(pt_ctx *c) {
   return PT_OK;
 }
 
-// Launch n sweeps from the current sweep index; exchange after sweep s when
-// every > 0 and (s+1) % every == 0.
-pt_status advance(pt_ctx *c, uint32_t n, uint32_t every) {
+}  // namespace
+
+namespace ptmi {
+
+pt_status ctx_advance(pt_ctx *c, uint32_t n, uint32_t every) {
   const uint32_t re = c->cfg.record_every;
   const uint32_t need = records_between(re, c->sweeps, c->sweeps + n);
   if ((uint64_t)c->n_records + need > c->cfg.max_records)
@@ -391,18 +369,10 @@ pt_status advance(pt_ctx *c, uint32_t n, uint32_t every) {
   return PT_OK;
 }
 
-}  // namespace
+}  // namespace ptmi
 
-extern "C" {
-
-size_t pt_workspace_bytes(const pt_config *cfg) {
-  Derived d;
-  if (derive(cfg, &d) != PT_OK) return 0;
-  return layout(cfg, d).total;
-}
-
-pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, size_t ws_bytes,
-                    pt_ctx **out) {
+pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d_workspace,
+                           size_t ws_bytes, bool sync, pt_ctx **out) {
   if (!out) return fail(PT_EINVAL, "out is NULL");
   *out = nullptr;
   Derived d;
@@ -438,7 +408,7 @@ pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, s
     return fail(PT_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, layout(cfg, d).total);
   }
   build_tables(&c->cfg, d, &c->tab);
-  c->stream = (hipStream_t)hip_stream;
+  c->stream = hip_stream;
 
   uint8_t *base = (uint8_t *)d_workspace;
   const Layout &l = c->lay;
@@ -487,7 +457,7 @@ pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, s
   if (cfg->init_spins) H2D(st.staging, cfg->init_spins, R * N);
   if (e == hipSuccess) e = launch_init_spins(st, d.geo, c->keys, cfg->init_spins != nullptr, sm);
   if (e == hipSuccess) e = launch_recount(st, d.geo, 0, sm);
-  if (e == hipSuccess) e = hipStreamSynchronize(sm);
+  if (e == hipSuccess && sync) e = hipStreamSynchronize(sm);
   if (e != hipSuccess) {
     delete c;
     return fail(PT_EDEVICE, "initialisation: %s", hipGetErrorString(e));
@@ -495,6 +465,19 @@ pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, s
   c->plan = auto_plan(c);
   *out = c;
   return PT_OK;
+}
+
+extern "C" {
+
+size_t pt_workspace_bytes(const pt_config *cfg) {
+  Derived d;
+  if (derive(cfg, &d) != PT_OK) return 0;
+  return layout(cfg, d).total;
+}
+
+pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, size_t ws_bytes,
+                    pt_ctx **out) {
+  return ctx_create(cfg, (hipStream_t)hip_stream, d_workspace, ws_bytes, true, out);
 }
 
 pt_status pt_set_plan(pt_ctx *ctx, const pt_plan *plan) {
@@ -524,7 +507,7 @@ pt_status pt_get_plan(const pt_ctx *ctx, pt_plan *plan) {
 pt_status pt_sweep(pt_ctx *ctx, uint32_t n_sweeps) {
   pt_status s = usable(ctx);
   if (s != PT_OK) return s;
-  return advance(ctx, n_sweeps, 0);
+  return ctx_advance(ctx, n_sweeps, 0);
 }
 
 pt_status pt_exchange(pt_ctx *ctx) {
@@ -539,7 +522,7 @@ pt_status pt_exchange(pt_ctx *ctx) {
 pt_status pt_run(pt_ctx *ctx, uint32_t n_sweeps, uint32_t exchange_every) {
   pt_status s = usable(ctx);
   if (s != PT_OK) return s;
-  return advance(ctx, n_sweeps, exchange_every);
+  return ctx_advance(ctx, n_sweeps, exchange_every);
 }
 
 pt_status pt_observables(pt_ctx *ctx, pt_obs *obs) {
@@ -645,12 +628,6 @@ const char *pt_last_error(void) { return g_err.c_str(); }
 // ---- batched form -------------------------------------------------------------
 namespace {
 
-uint32_t lg2(uint32_t v) {
-  uint32_t r = 0;
-  while ((1u << r) < v) ++r;
-  return r;
-}
-
 struct BatchGroup {
   Geometry g;                 // dim, L (R varies inside the group)
   std::vector<uint32_t> inst; // instance indices
@@ -683,6 +660,38 @@ std::vector<std::pair<uint32_t, uint32_t>> batch_candidates(const Geometry &g, u
 }
 
 }  // namespace
+
+namespace ptmi {
+
+BatchInst batch_inst(const pt_ctx *c, uint32_t *ctr) {
+  const Geometry &g = c->d.geo;
+  BatchInst I;
+  I.st = c->st;
+  I.geo = g;
+  I.key = c->keys;
+  I.record_every = c->cfg.record_every;
+  const uint32_t V = span_groups(g);
+  I.lg_L = lg2(g.L);
+  I.lg_spr = lg2(g.gpr / V);
+  I.lg_rows = lg2(g.rows);
+  I.lg_items = lg2(g.N / (8u * V));
+  I.z2 = g.dim == 3 ? 12 : 8;
+  I.ctr = ctr;
+  return I;
+}
+
+bool batch_fits(const Geometry &g) { return batch_lds_bytes(g, 1) <= max_lds_bytes(); }
+
+std::pair<uint32_t, uint32_t> batch_decomposition(const Geometry &g, uint32_t max_R) {
+  {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    auto it = g_tuned.find({g.dim, g.L});
+    if (it != g_tuned.end()) return {std::min(it->second.first, max_R), it->second.second};
+  }
+  return batch_candidates(g, max_R)[0];
+}
+
+}  // namespace ptmi
 
 struct pt_batch {
   std::vector<pt_ctx *> ctx;
@@ -809,18 +818,7 @@ pt_status pt_batch_create(const pt_config *cfgs, uint32_t n, void *hip_stream, v
   for (uint32_t i = 0; i < n; ++i) {
     const pt_ctx *c = b->ctx[i];
     const Geometry &g = c->d.geo;
-    BatchInst &I = hi[i];
-    I.st = c->st;
-    I.geo = g;
-    I.key = c->keys;
-    I.record_every = c->cfg.record_every;
-    const uint32_t V = span_groups(g);
-    I.lg_L = lg2(g.L);
-    I.lg_spr = lg2(g.gpr / V);
-    I.lg_rows = lg2(g.rows);
-    I.lg_items = lg2(g.N / (8u * V));
-    I.z2 = g.dim == 3 ? 12 : 8;
-    I.ctr = b->d_ctr + (size_t)i * kCtrWords;
+    hi[i] = batch_inst(c, b->d_ctr + (size_t)i * kCtrWords);
     for (uint32_t k = 0; k + 1 < g.R; ++k) b->pairs.push_back(make_uint2(i, k));
     const auto key = std::make_pair(g.dim, g.L);
     if (!gidx.count(key)) {

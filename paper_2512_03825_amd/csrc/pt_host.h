@@ -1,0 +1,85 @@
+// pt_host.h -- host-side structures shared by the library's C ABI files
+// (pt_host.cpp: plain and batched forms; pt_serve.cpp: served form).  Not part
+// of the public ABI.
+#pragma once
+
+#include "pt.h"
+#include "pt_internal.h"
+
+#include <utility>
+#include <vector>
+
+namespace ptmi {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Records the message for pt_last_error() and returns st.
+pt_status fail(pt_status st, const char *fmt, ...);
+// Multiples of `every` in (s0, s1] (0 when every = 0).
+uint32_t records_between(uint32_t every, uint64_t s0, uint64_t s1);
+uint32_t lg2(uint32_t v);
+
+struct Tables {
+  std::vector<uint32_t> flip; // [R][16]
+  std::vector<uint64_t> swap; // concatenated pair tables
+  std::vector<uint32_t> off;  // [R]
+  std::vector<uint32_t> D;    // [R]
+  std::vector<uint64_t> sat;  // [R][2]
+  std::vector<uint64_t> field; // [R][kFieldDigits]
+  std::vector<int32_t> fsign;  // [R]
+};
+
+struct Layout {
+  size_t spins[2], bonds, staging, flip, swap_tab, swap_off, swap_D, swap_sat, wat, sof, E, M,
+      acc3, att, acc, Es, Ms, counter, mailbox, field, fsign, total;
+};
+
+struct Derived {
+  Geometry geo;
+  double jscale; // energy unit of E_int: J (2D), 1 (EA)
+  uint32_t z;    // coordination number
+};
+
+}  // namespace ptmi
+
+using ptmi::Derived;
+using ptmi::DevState;
+using ptmi::Keys;
+using ptmi::Layout;
+using ptmi::Tables;
+
+struct pt_ctx {
+  pt_config cfg;
+  std::vector<double> beta;
+  Derived d;
+  Keys keys;
+  DevState st;
+  Layout lay;
+  Tables tab;
+  hipStream_t stream;
+  pt_plan plan;
+  uint64_t sweeps = 0, exchanges = 0;
+  uint32_t n_records = 0;
+  uint32_t cur = 0;
+  bool poisoned = false;
+};
+
+namespace ptmi {
+
+// pt_create with a choice: sync = false leaves the initialisation kernels
+// queued on the stream (errors then surface at the next synchronisation).
+pt_status ctx_create(const pt_config *cfg, hipStream_t stream, void *d_workspace, size_t ws_bytes,
+                     bool sync, pt_ctx **out);
+// Queue n sweeps of the context's plan; exchange after sweep s when every > 0
+// and (s+1) % every == 0.
+pt_status ctx_advance(pt_ctx *c, uint32_t n, uint32_t every);
+// Device descriptor of a context for the batched kernels; ctr = its counters.
+BatchInst batch_inst(const pt_ctx *c, uint32_t *ctr);
+// Whole replicas of this geometry fit one workgroup's LDS (batched kernels).
+bool batch_fits(const Geometry &g);
+// Walkers per workgroup and threads for a batched group of this geometry: the
+// decomposition tuned earlier in this process if there is one, else a default.
+std::pair<uint32_t, uint32_t> batch_decomposition(const Geometry &g, uint32_t max_R);
+
+}  // namespace ptmi

@@ -26,7 +26,11 @@ STATUS = {0: "PT_OK", -1: "PT_EINVAL", -2: "PT_ENOMEM", -3: "PT_EDEVICE", -4: "P
 EXPORTS = ("pt_workspace_bytes", "pt_create", "pt_set_plan", "pt_get_plan", "pt_sweep",
            "pt_exchange", "pt_run", "pt_observables", "pt_flip_thresholds", "pt_swap_threshold",
            "pt_destroy", "pt_last_error", "pt_batch_workspace_bytes", "pt_batch_create",
-           "pt_batch_run", "pt_batch_observables", "pt_batch_group_plan", "pt_batch_destroy")
+           "pt_batch_run", "pt_batch_observables", "pt_batch_group_plan", "pt_batch_destroy",
+           "pt_server_overhead_bytes", "pt_server_create", "pt_server_submit", "pt_server_step",
+           "pt_server_done", "pt_server_result", "pt_server_release", "pt_server_stats_get",
+           "pt_server_clock", "pt_server_destroy")
+PT_JOB_KEEP_SPINS = 1
 
 
 class PTError(RuntimeError):
@@ -61,6 +65,23 @@ class pt_obs(C.Structure):
     ]
 
 
+class pt_server_opts(C.Structure):
+    _fields_ = [("max_jobs", C.c_uint32), ("max_walkers", C.c_uint32), ("tiled_lanes", C.c_uint32),
+                ("depth", C.c_uint32), ("cycle_sweeps", C.c_uint32), ("tiled_sweeps", C.c_uint32)]
+
+
+class pt_job_info(C.Structure):
+    _fields_ = [("job_id", C.c_uint64), ("arrival", C.c_double), ("admitted", C.c_double),
+                ("finished", C.c_double), ("attempts", C.c_uint64), ("lane", C.c_uint32),
+                ("pad", C.c_uint32)]
+
+
+class pt_server_stats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in (
+        "submitted", "pending", "resident", "finished", "arena_bytes", "arena_used", "arena_peak",
+        "walkers_resident", "batched_cycles", "tiled_steps", "attempts_finished")]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libptmi.so is not built (%s); run __graft_entry__.build() or "
@@ -87,6 +108,17 @@ def _load():
         "pt_batch_observables": (st, [vp, C.c_uint32, P(pt_obs)]),
         "pt_batch_group_plan": (st, [vp, C.c_uint32, P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]),
         "pt_batch_destroy": (None, [vp]),
+        "pt_server_overhead_bytes": (C.c_size_t, [P(pt_server_opts)]),
+        "pt_server_create": (st, [P(pt_server_opts), vp, C.c_size_t, P(vp)]),
+        "pt_server_submit": (st, [vp, P(pt_config), C.c_uint64, C.c_uint32, C.c_uint32, C.c_double,
+                                  P(C.c_uint64)]),
+        "pt_server_step": (st, [vp, C.c_uint32, P(C.c_uint32)]),
+        "pt_server_done": (st, [vp, P(pt_job_info), C.c_uint32, P(C.c_uint32)]),
+        "pt_server_result": (st, [vp, C.c_uint64, P(pt_obs)]),
+        "pt_server_release": (st, [vp, C.c_uint64]),
+        "pt_server_stats_get": (st, [vp, P(pt_server_stats)]),
+        "pt_server_clock": (C.c_double, [vp]),
+        "pt_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -328,6 +360,86 @@ class Batch:
             except TypeError:
                 pass
             self.b = None
+
+    def __del__(self):
+        self.close()
+
+
+def server_opts(max_jobs=1024, max_walkers=32768, tiled_lanes=2, depth=2, cycle_sweeps=10,
+                tiled_sweeps=10) -> pt_server_opts:
+    return pt_server_opts(int(max_jobs), int(max_walkers), int(tiled_lanes), int(depth),
+                          int(cycle_sweeps), int(tiled_sweeps))
+
+
+def pt_server_overhead_bytes(opts: pt_server_opts) -> int:
+    n = _lib.pt_server_overhead_bytes(C.byref(opts))
+    if n == 0:
+        raise PTError(-1, _lib.pt_last_error().decode())
+    return int(n)
+
+
+class Server:
+    """Served form (pt_server_*): jobs admitted by device-memory budget into a
+    torch-owned arena of arena_bytes, advanced together as they arrive."""
+
+    def __init__(self, arena_bytes, device="cuda", **opts):
+        import torch
+        self.opts = server_opts(**opts)
+        self.nbytes = pt_server_overhead_bytes(self.opts) + int(arena_bytes)
+        self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        torch.cuda.synchronize(device)
+        out = C.c_void_p()
+        _check(_lib.pt_server_create(C.byref(self.opts), C.c_void_p(ptr), C.c_size_t(self.nbytes),
+                                     C.byref(out)))
+        self.sv = out
+        self.jobs = {}
+
+    def submit(self, cfg: Config, n_sweeps, exchange_every, keep_spins=False, arrival=-1.0) -> int:
+        jid = C.c_uint64()
+        _check(_lib.pt_server_submit(self.sv, C.byref(cfg.c), int(n_sweeps), int(exchange_every),
+                                     PT_JOB_KEEP_SPINS if keep_spins else 0, float(arrival),
+                                     C.byref(jid)))
+        self.jobs[jid.value] = cfg
+        return jid.value
+
+    def step(self, wait_us=0) -> int:
+        n = C.c_uint32()
+        _check(_lib.pt_server_step(self.sv, int(wait_us), C.byref(n)))
+        return n.value
+
+    def done(self, cap=256):
+        arr = (pt_job_info * cap)()
+        n = C.c_uint32()
+        _check(_lib.pt_server_done(self.sv, arr, cap, C.byref(n)))
+        return [{"job_id": a.job_id, "arrival": a.arrival, "admitted": a.admitted,
+                 "finished": a.finished, "attempts": a.attempts, "lane": a.lane}
+                for a in arr[:n.value]]
+
+    def result(self, job_id, spins=None, series=True):
+        c = self.jobs[job_id]
+        return _observe(lambda o: _lib.pt_server_result(self.sv, int(job_id), C.byref(o)), c.R, c.N,
+                        c.c.max_records, spins, series)
+
+    def release(self, job_id):
+        _check(_lib.pt_server_release(self.sv, int(job_id)))
+        self.jobs.pop(job_id, None)
+
+    def stats(self) -> dict:
+        s = pt_server_stats()
+        _check(_lib.pt_server_stats_get(self.sv, C.byref(s)))
+        return {n: int(getattr(s, n)) for n, _ in pt_server_stats._fields_}
+
+    def clock(self) -> float:
+        return float(_lib.pt_server_clock(self.sv))
+
+    def close(self):
+        if getattr(self, "sv", None):
+            try:
+                _lib.pt_server_destroy(self.sv)
+            except TypeError:
+                pass
+            self.sv = None
 
     def __del__(self):
         self.close()

@@ -101,3 +101,38 @@ def batched2048(seed: int = 4, n: int = 2048):
                      beta_linear(0.30, 0.55, int(Rs[i])), sweeps=2000, exchange_every=5,
                      record_every=0, seed=seed, h=float(hs[i]), stream_id=i)
             for i in range(n)]
+
+
+def served_jobs(seed: int = 5, n: int = 10_000):
+    """A stream of independent PT jobs for the served form.  With probability
+    0.2 a job is a 3D +-J EA instance with L uniform in {8, 16, 32} and beta
+    geometric over [0.5, 3.0]; otherwise a 2D Ising instance with L = 2^k, k the
+    rounded value of U[4, 10] (L from 16 to 1024), beta linear over [0.30, 0.55],
+    J = 1, h = 0.  R is uniform in [8, 128] and the sweep count log-uniform in
+    [10^3, 10^5]; every job exchanges every 10 sweeps and records E, M every 100.
+    Job i uses Philox stream_id i under the common seed (EA couplings from
+    coupling_seed = seed + i)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        ea = rng.random() < 0.2
+        R = int(rng.integers(8, 129))
+        sweeps = int(round(10 ** rng.uniform(3.0, 5.0)))
+        if ea:
+            L = int(rng.choice([8, 16, 32]))
+            w = Workload("served_%d" % i, EA3D, L, R, beta_geometric(0.5, 3.0, R), sweeps=sweeps,
+                         exchange_every=10, record_every=100, seed=seed, coupling_seed=seed + i,
+                         stream_id=i)
+        else:
+            L = 2 ** int(round(rng.uniform(4.0, 10.0)))
+            w = Workload("served_%d" % i, ISING2D, L, R, beta_linear(0.30, 0.55, R), sweeps=sweeps,
+                         exchange_every=10, record_every=100, seed=seed, stream_id=i)
+        out.append(w)
+    return out
+
+
+def poisson_arrivals(rate: float, n: int, seed: int = 5) -> np.ndarray:
+    """Arrival times (seconds from the start) of a Poisson process of the given
+    rate: cumulative sums of exponential gaps, from their own generator."""
+    rng = np.random.default_rng([seed, 1])
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))

@@ -47,10 +47,11 @@ def parse():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
-    ap.add_argument("--form", choices=["plain", "batched", "served"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batched", "served", "physics"], default="plain",
                     help="plain: one PT instance (the default workload); batched: 2048 "
                          "independent instances advanced together, against the per-instance path; "
-                         "served: a Poisson stream of jobs through the request loop")
+                         "served: a Poisson stream of jobs through the request loop; physics: "
+                         "|M|/N and E/N against T and sweeps-to-equilibrium against L")
     ap.add_argument("--batch-instances", type=int, default=2048)
     ap.add_argument("--batch-sweeps", type=int, default=2000)
     ap.add_argument("--jobs", type=int, default=400, help="served form: jobs in the stream")
@@ -274,8 +275,106 @@ def bench_served(args):
     print(json.dumps(out), flush=True)
 
 
+def onsager_energy(beta):
+    """Energy per site of the infinite 2D Ising model (J = 1, h = 0), Onsager 1944."""
+    import math
+
+    from scipy.special import ellipk
+    t = math.tanh(2 * beta)
+    k = 2 * math.sinh(2 * beta) / math.cosh(2 * beta) ** 2
+    return -(1 / t) * (1 + (2 / math.pi) * (2 * t * t - 1) * ellipk(k * k))
+
+
+def yang_magnetisation(beta):
+    """Spontaneous magnetisation per site (Yang 1952); 0 above the critical temperature."""
+    import math
+    x = math.sinh(2 * beta) ** -4
+    return (1 - x) ** 0.125 if x < 1 else 0.0
+
+
+def _blocked(x, blocks=20):
+    """Mean and its standard error from `blocks` contiguous block means."""
+    import numpy as np
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x) // blocks * blocks
+    b = x[len(x) - n:].reshape(blocks, -1).mean(axis=1)
+    return float(b.mean()), float(b.std(ddof=1) / np.sqrt(blocks))
+
+
+def bench_physics(args):
+    """The paper's validation figures, computed with the GPU path: |M|/N and E/N
+    against T across [1, 4] beside Onsager and Yang (Fig. 3a), and the sweeps a
+    random start needs to reach equilibrium at T = 2 against L (Fig. 3b)."""
+    import numpy as np
+    import torch
+
+    from paper_2512_03825_amd import pt
+    torch.cuda.set_device(0)
+    t_start = time.perf_counter()
+    # Fig. 3a analogue: L = 64, 32 temperatures linear in [1, 4], PT every 10 sweeps
+    L, R, sweeps, rec = 64, 32, 100_000, 10
+    T = np.array([1.0 + 3.0 * k / (R - 1) for k in range(R)])
+    beta = 1.0 / T
+    cfg = pt.Config(pt.PT_ISING2D, L, R, beta, seed=7, record_every=rec, max_records=sweeps // rec)
+    sim = pt.Simulation(cfg, device="cuda:0")
+    sim.run(sweeps, 10)
+    obs = sim.observables()
+    sim.close()
+    N = L * L
+    keep = obs["n_records"] // 2  # second half of the run
+    fig_a = []
+    for k in range(R):
+        e, de = _blocked(obs["E_series"][keep:, k] / N)  # E_int = -sum over bonds of s s (J = 1)
+        m, dm = _blocked(np.abs(obs["M_series"][keep:, k]) / N)
+        fig_a.append({"T": round(float(T[k]), 4), "E_per_site": e, "E_err": de,
+                      "onsager": onsager_energy(beta[k]), "absM_per_site": m, "M_err": dm,
+                      "yang": yang_magnetisation(beta[k])})
+    # Fig. 3b analogue: T = 2.0 slot of an 8-slot ladder over T in [2.0, 2.7],
+    # random start; first sweep after which the mean E/N over the next 200
+    # sweeps is within 0.5% of Onsager's value; 4 seeds per L
+    target = onsager_energy(0.5)
+    fig_b = []
+    for L in (16, 32, 64, 128, 256):
+        R, cap = 8, 200_000
+        Tl = np.array([2.0 + 0.7 * k / (R - 1) for k in range(R)])
+        found = []
+        for seed in range(4):
+            cfg = pt.Config(pt.PT_ISING2D, L, R, 1.0 / Tl, seed=100 + seed, record_every=1,
+                            max_records=cap)
+            sim = pt.Simulation(cfg, device="cuda:0")
+            s_eq, done = None, 0
+            while done < cap and s_eq is None:
+                n = min(cap - done, max(2000, done))
+                sim.run(n, 10)
+                done += n
+                e = sim.observables()["E_series"][:, 0].astype(np.float64) / (L * L)
+                if len(e) >= 200:
+                    w = np.convolve(e, np.ones(200) / 200, mode="valid")
+                    hit = np.nonzero(np.abs(w - target) < 0.005 * abs(target))[0]
+                    if len(hit):
+                        s_eq = int(hit[0])
+            sim.close()
+            found.append(s_eq)
+        ok = [f for f in found if f is not None]
+        fig_b.append({"L": L, "sweeps_to_equilibrium": found,
+                      "median": float(np.median(ok)) if ok else None,
+                      "not_reached": len(found) - len(ok)})
+    out = {"metric": "physics checks (Fig. 3a/3b analogues)", "value": None, "unit": None,
+           "n_gpus": 1, "data": "synthetic", "seconds": time.perf_counter() - t_start,
+           "config": {"workload": "physics", "fig3a": {"L": 64, "R": 32, "T": [1.0, 4.0],
+                                                       "sweeps": 100_000, "exchange_every": 10,
+                                                       "record_every": 10, "seed": 7},
+                      "fig3b": {"T": 2.0, "ladder": [2.0, 2.7], "R": 8, "exchange_every": 10,
+                                "criterion": "mean E/N over the next 200 sweeps within 0.5% of "
+                                             "Onsager", "cap_sweeps": 200_000}},
+           "fig3a": fig_a, "fig3b": fig_b}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.form == "physics" and args.gpus == 1:
+        return bench_physics(args)
     if args.form == "batched" and args.gpus == 1:
         return bench_batched(args)
     if args.form == "served" and args.gpus == 1:

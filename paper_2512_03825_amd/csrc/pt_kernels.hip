@@ -32,6 +32,7 @@
 #include "pt_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace ptmi {
 namespace {
@@ -401,29 +402,49 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
     const uint32_t s = a.sch.s0 + (hs >> 1);
     const uint32_t ext = halo ? (halo - 1u - hs) : 0u;
     const uint32_t plo = halo - ext;                 // computed LDS planes [plo, plo+Ht+2ext)
-    const uint32_t items = (Ht + 2u * ext) << shp;
-    for (uint32_t q = tid; q < items; q += nt) {
-      const uint32_t g0 = (q & smask) * V;
-      const uint32_t y = (q >> a.lg_spr) & rmask;
-      const uint32_t pl = plo + (q >> shp);
+    // One item: VV consecutive groups of row y of LDS plane pl.
+    auto item = [&](auto vtag, uint32_t pl, uint32_t y, uint32_t g0, bool interior) {
+      constexpr int VV = decltype(vtag)::value;
       const uint32_t pu = (pl == 0u) ? np - 1u : pl - 1u;
       const uint32_t pd = (pl + 1u == np) ? 0u : pl + 1u;
       const uint32_t gp = (base + pl) & (L - 1u);   // global plane coordinate
       const uint32_t off = (c + gp + (DIM == 3 ? y : 0u)) & 1u;
       const uint32_t ctr0 = (((gp << a.lg_rows) + y) << (lgL - 3u)) + g0;
-      Words r[V];
+      Words r[VV];
 #pragma unroll
-      for (int v = 0; v < V; ++v)
+      for (int v = 0; v < VV; ++v)
         r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
       Tally tg = {0, 0, 0};
-      if (DIM == 2)
-        span2d<V>(sp + (pl << lgP), sp + (pu << lgP), sp + (pd << lgP), g0, L, off, r, s_thr, tg);
+      if constexpr (DIM == 2)
+        span2d<VV>(sp + (pl << lgP), sp + (pu << lgP), sp + (pd << lgP), g0, L, off, r, s_thr, tg);
       else
-        span3d<V>(sp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, s_thr, tg);
-      if (pl >= halo && pl < halo + Ht) {
+        span3d<VV>(sp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, s_thr, tg);
+      if (interior) {
         t.n += tg.n;
         t.sb += tg.sb;
         t.sc += tg.sc;
+      }
+    };
+    if (DIM == 2 && halo) {
+      // Interior rows as V-group spans (a whole number of rounds when the
+      // tile's spans fill the workgroup evenly), the 2 ext recomputed halo
+      // rows as single groups spread over every lane.
+      const uint32_t items = Ht << a.lg_spr;
+      for (uint32_t q = tid; q < items; q += nt)
+        item(std::integral_constant<int, V>{}, halo + (q >> a.lg_spr), 0u, (q & smask) * V, true);
+      const uint32_t lgG = lgL - 3u;
+      const uint32_t hitems = (2u * ext) << lgG;
+      for (uint32_t q = tid; q < hitems; q += nt) {
+        const uint32_t r = q >> lgG;
+        const uint32_t pl = r < ext ? plo + r : halo + Ht + (r - ext);
+        item(std::integral_constant<int, 1>{}, pl, 0u, q & ((1u << lgG) - 1u), false);
+      }
+    } else {
+      const uint32_t items = (Ht + 2u * ext) << shp;
+      for (uint32_t q = tid; q < items; q += nt) {
+        const uint32_t pl = plo + (q >> shp);
+        item(std::integral_constant<int, V>{}, pl, (q >> a.lg_spr) & rmask, (q & smask) * V,
+             pl >= halo && pl < halo + Ht);
       }
     }
     if (c == 1u) {

@@ -1,0 +1,65 @@
+"""Physics at GPU scale: a 64x64 parallel-tempering run across T in [1.5, 3.5]
+must reproduce the infinite-lattice closed forms away from the critical
+temperature (Onsager's energy, Yang's spontaneous magnetisation), and a random
+start at T = 1.8 must reach the ordered energy.  Independent of the oracle: the
+references are the exact solutions."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import requires_gpu, say
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+T_C = 2.0 / math.log(1.0 + math.sqrt(2.0))
+
+
+def onsager_energy(beta):
+    from scipy.special import ellipk
+    t = math.tanh(2 * beta)
+    k = 2 * math.sinh(2 * beta) / math.cosh(2 * beta) ** 2
+    return -(1 / t) * (1 + (2 / math.pi) * (2 * t * t - 1) * ellipk(k * k))
+
+
+def yang_magnetisation(beta):
+    x = math.sinh(2 * beta) ** -4
+    return (1 - x) ** 0.125 if x < 1 else 0.0
+
+
+def test_energy_and_magnetisation_match_closed_forms():
+    from paper_2512_03825_amd import pt
+    L, R, sweeps, rec = 64, 16, 20_000, 5
+    T = np.array([1.5 + 2.0 * k / (R - 1) for k in range(R)])
+    cfg = pt.Config(pt.PT_ISING2D, L, R, 1.0 / T, seed=9, record_every=rec,
+                    max_records=sweeps // rec)
+    say("physics L=64 R=16 sweeps", sweeps)
+    sim = pt.Simulation(cfg)
+    sim.run(sweeps, 10)
+    obs = sim.observables()
+    sim.close()
+    N = L * L
+    keep = obs["n_records"] // 2
+    checked = 0
+    for k in range(R):
+        if abs(T[k] - T_C) < 0.45:
+            continue  # finite-size and critical slowing down near T_c
+        e = obs["E_series"][keep:, k].mean() / N
+        assert abs(e - onsager_energy(1 / T[k])) < 0.01, (T[k], e)
+        if T[k] < T_C:
+            m = np.abs(obs["M_series"][keep:, k]).mean() / N
+            assert abs(m - yang_magnetisation(1 / T[k])) < 0.01, (T[k], m)
+        checked += 1
+    assert checked >= 8
+
+
+def test_random_start_orders_below_t_c():
+    from paper_2512_03825_amd import pt
+    L, R = 32, 8
+    T = np.array([1.8 + 0.8 * k / (R - 1) for k in range(R)])
+    cfg = pt.Config(pt.PT_ISING2D, L, R, 1.0 / T, seed=11, record_every=1, max_records=20_000)
+    sim = pt.Simulation(cfg)
+    sim.run(20_000, 10)
+    e = sim.observables()["E_series"][-2000:, 0].mean() / (L * L)
+    sim.close()
+    assert abs(e - onsager_energy(1 / 1.8)) < 0.02, e

@@ -43,6 +43,13 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }
 
+// (a ^ b) + c in one VALU instruction.
+__device__ __forceinline__ uint32_t xad(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t d;
+  asm("v_xad_u32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+  return d;
+}
+
 struct Words {
   uint32_t x, y, z, w;
 };
@@ -168,8 +175,11 @@ __device__ __forceinline__ void span2d(uint8_t *row, const uint8_t *up, const ui
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int j = 2 * v + h;
-      cnt[h] = ((a[j] ^ w[j]) + (b[j] ^ w[j])) +
-               ((left_of<V>(w, j, e0) ^ w[j]) + (right_of<V>(w, j, e1) ^ w[j]));
+      // a chain of fused XOR+ADDs: one XOR and three v_xad_u32
+      uint32_t u = right_of<V>(w, j, e1) ^ w[j];
+      u = xad(left_of<V>(w, j, e0), w[j], u);
+      u = xad(b[j], w[j], u);
+      cnt[h] = xad(a[j], w[j], u);
     }
     decide(w[2 * v], w[2 * v + 1], cnt[0], cnt[1], sh, b0, b1, r[v], thr, t, nw[2 * v],
            nw[2 * v + 1]);
@@ -356,6 +366,55 @@ __device__ __forceinline__ void pack_tile(uint32_t *dst, const uint8_t *lds, uin
   }
 }
 
+// The last workgroup of a tiled launch to arrive folds the per-sweep energy
+// and magnetisation changes into E and M, writes the records, and runs the
+// exchange step; it then re-arms the arrival counter.
+__device__ void tiled_epilogue(const TiledArgs &a, uint32_t tid, uint32_t nt, uint32_t *s_last) {
+  __syncthreads();
+  if (tid == 0u) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); // publish this workgroup's tallies
+    const uint32_t total = gridDim.x * gridDim.y;
+    const uint32_t prev =
+        __hip_atomic_fetch_add(a.st.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    *s_last = (prev + 1u == total) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!*s_last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+
+  const uint32_t R = a.geo.R;
+  uint32_t rec = a.sch.rec_base;
+  for (uint32_t j = 0; j < a.sch.nsw; ++j) {
+    for (uint32_t v = tid; v < R; v += nt) {
+      int32_t *acc = a.st.acc3 + ((size_t)j * R + v) * 4u;
+      const int32_t dE = __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const int32_t dM = __hip_atomic_load(acc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(acc, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(acc + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a.st.E[v] += dE;
+      a.st.M[v] += dM;
+    }
+    __syncthreads();
+    const uint32_t s = a.sch.s0 + j;
+    if (a.sch.record_every && (s + 1u) % a.sch.record_every == 0u) {
+      for (uint32_t k = tid; k < R; k += nt) {
+        const uint32_t v = a.st.walker_at[k];
+        a.st.E_series[(size_t)rec * R + k] = a.st.E[v];
+        a.st.M_series[(size_t)rec * R + k] = a.st.M[v];
+      }
+      ++rec;
+    }
+  }
+  if (a.sch.do_exchange) {
+    __syncthreads();
+    exchange_step(a.st, R, a.key.k0, a.key.k1, a.sch.ex_step, a.st.E, a.st.M, a.st.walker_at,
+                  a.st.slot_of, tid, nt);
+  }
+  __syncthreads();
+  if (tid == 0u) __hip_atomic_store(a.st.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+
 template <int DIM, int V>
 __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -475,49 +534,232 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
   pack_tile(a.dst + (size_t)w * (G.N >> 5) + ((y0 << lgP) >> 5), sp + ((size_t)halo << lgP),
             (Ht << lgP) >> 5, tid, nt);
 
-  // The last workgroup to arrive folds the sweep results, records, exchanges.
-  __syncthreads();
-  if (tid == 0u) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); // publish this workgroup's tallies
-    const uint32_t total = gridDim.x * gridDim.y;
-    const uint32_t prev =
-        __hip_atomic_fetch_add(a.st.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (prev + 1u == total) ? 1u : 0u;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  tiled_epilogue(a, tid, nt, &s_last);
+}
 
-  const uint32_t R = G.R;
-  uint32_t rec = a.sch.rec_base;
-  for (uint32_t j = 0; j < a.sch.nsw; ++j) {
-    for (uint32_t v = tid; v < R; v += nt) {
-      int32_t *acc = a.st.acc3 + ((size_t)j * R + v) * 4u;
-      const int32_t dE = __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int32_t dM = __hip_atomic_load(acc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(acc, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(acc + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      a.st.E[v] += dE;
-      a.st.M[v] += dM;
+// ---- 2D tiled sweep at four bits per site ----------------------------------
+// The 2D tiled kernel keeps its tile at four bits per site: row y of the tile
+// is L/8 dwords, site 8g + j of the row at bits 4j .. 4j+3 of dword g (0 up, 1
+// down).  A dword is exactly one Philox group: its four colour sites sit at
+// nibbles off, off+2, off+4, off+6.  Neighbour counts are nibble-wise sums of
+// XORs (at most 4, so no carries), a site's class 8b + u fits its nibble, and
+// the tallies are v_dot8 products over nibbles.  Half the LDS of the byte
+// layout and half the SWAR instructions per site.
+
+// 8 bits -> 8 nibbles (bit j -> bit 4j), and back.
+__device__ __forceinline__ uint32_t spread8(uint32_t x) {
+  x = (x | (x << 12)) & 0x000F000Fu;
+  x = (x | (x << 6)) & 0x03030303u;
+  return (x | (x << 3)) & 0x11111111u;
+}
+__device__ __forceinline__ uint32_t gather8(uint32_t x) {
+  x &= 0x11111111u;
+  x = (x | (x >> 3)) & 0x03030303u;
+  x = (x | (x >> 6)) & 0x000F000Fu;
+  return (x | (x >> 12)) & 0x000000FFu;
+}
+
+// LDS dwords [4q, 4q + 4) <- nibbles of packed words src[(f + q) & m], q < cnt.
+__device__ __forceinline__ void unpack_tile_n(uint32_t *lds, const uint32_t *src, uint32_t f,
+                                              uint32_t cnt, uint32_t m, uint32_t tid, uint32_t nt) {
+  constexpr uint32_t kBatch = 4;
+  for (uint32_t q0 = tid; q0 < cnt; q0 += kBatch * nt) {
+    uint32_t w[kBatch];
+#pragma unroll
+    for (uint32_t j = 0; j < kBatch; ++j) {
+      const uint32_t q = q0 + j * nt;
+      w[j] = (q < cnt) ? src[(f + q) & m] : 0u;
     }
-    __syncthreads();
-    const uint32_t s = a.sch.s0 + j;
-    if (a.sch.record_every && (s + 1u) % a.sch.record_every == 0u) {
-      for (uint32_t k = tid; k < R; k += nt) {
-        const uint32_t v = a.st.walker_at[k];
-        a.st.E_series[(size_t)rec * R + k] = a.st.E[v];
-        a.st.M_series[(size_t)rec * R + k] = a.st.M[v];
-      }
-      ++rec;
+#pragma unroll
+    for (uint32_t j = 0; j < kBatch; ++j) {
+      const uint32_t q = q0 + j * nt;
+      if (q < cnt)
+        reinterpret_cast<uint4 *>(lds)[q] =
+            make_uint4(spread8(w[j] & 0xFFu), spread8(__builtin_amdgcn_ubfe(w[j], 8u, 8u)),
+                       spread8(__builtin_amdgcn_ubfe(w[j], 16u, 8u)), spread8(w[j] >> 24));
     }
   }
-  if (a.sch.do_exchange) {
-    __syncthreads();
-    exchange_step(a.st, R, a.key.k0, a.key.k1, a.sch.ex_step, a.st.E, a.st.M, a.st.walker_at,
-                  a.st.slot_of, tid, nt);
+}
+
+// dst[q] <- packed nibbles of LDS dwords [4q, 4q + 4), q < cnt.
+__device__ __forceinline__ void pack_tile_n(uint32_t *dst, const uint32_t *lds, uint32_t cnt,
+                                            uint32_t tid, uint32_t nt) {
+  for (uint32_t q = tid; q < cnt; q += nt) {
+    const uint4 x = reinterpret_cast<const uint4 *>(lds)[q];
+    dst[q] = gather8(x.x) | (gather8(x.y) << 8) | (gather8(x.z) << 16) | (gather8(x.w) << 24);
   }
+}
+
+template <int V>
+__device__ __forceinline__ void lds_load_n(uint32_t (&d)[V], const uint32_t *p) {
+  if constexpr (V == 4) {
+    const uint4 a = *reinterpret_cast<const uint4 *>(p);
+    d[0] = a.x;
+    d[1] = a.y;
+    d[2] = a.z;
+    d[3] = a.w;
+  } else if constexpr (V == 2) {
+    const uint2 a = *reinterpret_cast<const uint2 *>(p);
+    d[0] = a.x;
+    d[1] = a.y;
+  } else {
+    d[0] = p[0];
+  }
+}
+template <int V>
+__device__ __forceinline__ void lds_store_n(uint32_t *p, const uint32_t (&d)[V]) {
+  if constexpr (V == 4)
+    *reinterpret_cast<uint4 *>(p) = make_uint4(d[0], d[1], d[2], d[3]);
+  else if constexpr (V == 2)
+    *reinterpret_cast<uint2 *>(p) = make_uint2(d[0], d[1]);
+  else
+    p[0] = d[0];
+}
+
+// Tallies of the nibble layout: n flips, sb = down spins flipped, sc = sum of
+// the flipped sites' classes 8b + u.
+struct TallyN {
+  uint32_t n, sb, sc;
+};
+
+// 2D Ising, nibble layout: update the colour sites of the V groups (dwords)
+// g0 .. g0+V-1 of one row.
+template <int V>
+__device__ __forceinline__ void span2d_n(uint32_t *row, const uint32_t *up, const uint32_t *dn,
+                                         uint32_t g0, uint32_t gmask, uint32_t off,
+                                         const Words (&r)[V], const uint32_t *thr, TallyN &t) {
+  uint32_t w[V], a[V], b[V], nw[V];
+  lds_load_n<V>(w, row + g0);
+  lds_load_n<V>(a, up + g0);
+  lds_load_n<V>(b, dn + g0);
+  // the neighbouring dword on the side the colour sites need: left for off = 0
+  // (nibble 0's left neighbour), right for off = 1 (nibble 7's right neighbour)
+  const uint32_t e = row[off ? ((g0 + V) & gmask) : ((g0 + gmask) & gmask)];
+  const uint32_t M = off ? 0xF0F0F0F0u : 0x0F0F0F0Fu;   // colour nibbles
+  const uint32_t rot = off ? 2u : 30u;                  // class * 4 to bits 8m .. 8m+5
+  const uint32_t b0 = 1u << (4u * off);
+  const uint8_t *tb = reinterpret_cast<const uint8_t *>(thr);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const uint32_t l = __builtin_amdgcn_alignbit(w[v], v ? w[v - 1] : e, 28u);
+    const uint32_t rr = __builtin_amdgcn_alignbit(v < V - 1 ? w[v + 1] : e, w[v], 4u);
+    uint32_t u = rr ^ w[v];
+    u = xad(l, w[v], u);
+    u = xad(b[v], w[v], u);
+    u = xad(a[v], w[v], u);
+    const uint32_t cls = ((w[v] << 3) | u) & M;         // 8b + u in each colour nibble
+    const uint32_t c4 = __builtin_amdgcn_alignbit(cls, cls, rot);
+    const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tb + (c4 & 63u));
+    const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 8u, 6u));
+    const uint32_t t2 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 16u, 6u));
+    const uint32_t t3 = *reinterpret_cast<const uint32_t *>(tb + (c4 >> 24));
+    const uint32_t f = (r[v].x <= t0 ? b0 : 0u) | (r[v].y <= t1 ? (b0 << 8) : 0u) |
+                       (r[v].z <= t2 ? (b0 << 16) : 0u) | (r[v].w <= t3 ? (b0 << 24) : 0u);
+    t.n += __builtin_popcount(f);
+    t.sb = __builtin_amdgcn_udot8(w[v], f, t.sb, false);
+    t.sc = __builtin_amdgcn_udot8(cls, f, t.sc, false);
+    nw[v] = w[v] ^ f;
+  }
+  lds_store_n<V>(row + g0, nw);
+}
+
+template <int V>
+__global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ uint32_t s_thr[kClasses];
+  __shared__ int s_red[kMaxThreads / 64][2];
+  __shared__ uint32_t s_last;
+
+  const Geometry &G = a.geo;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t tile = blockIdx.x, w = blockIdx.y;
+  const uint32_t L = G.L, lgL = a.lg_L, lgG = lgL - 3u, gmask = (1u << lgG) - 1u;
+  const uint32_t y0 = tile * a.H;
+  const uint32_t Ht = min(a.H, L - y0);
+  const uint32_t halo = a.halo;
+  const uint32_t np = Ht + 2u * halo;                  // LDS rows
+  const uint32_t base = (y0 + L - halo) & (L - 1u);   // global row of LDS row 0
+  const uint32_t slot = a.st.slot_of[w];
+  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+  uint32_t *sp = reinterpret_cast<uint32_t *>(smem);
+
+  // rows [base, base+np) mod L of this walker, four bits per site; a packed
+  // word (32 sites) becomes four LDS dwords
+  const uint32_t nwr = G.N >> 5, wpr = L >> 5;
+  unpack_tile_n(sp, a.src + (size_t)w * nwr, base * wpr, np * wpr, nwr - 1u, tid, nt);
   __syncthreads();
-  if (tid == 0u) __hip_atomic_store(a.st.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+
+  const uint32_t smask = (1u << a.lg_spr) - 1u;
+  TallyN t = {0u, 0u, 0u};
+  for (uint32_t hs = 0; hs < 2u * a.sch.nsw; ++hs) {
+    const uint32_t c = hs & 1u;
+    const uint32_t s = a.sch.s0 + (hs >> 1);
+    const uint32_t ext = halo ? (halo - 1u - hs) : 0u;
+    const uint32_t plo = halo - ext;                 // computed LDS rows [plo, plo+Ht+2ext)
+    auto item = [&](auto vtag, uint32_t pl, uint32_t g0, bool interior) {
+      constexpr int VV = decltype(vtag)::value;
+      const uint32_t pu = (pl == 0u) ? np - 1u : pl - 1u;
+      const uint32_t pd = (pl + 1u == np) ? 0u : pl + 1u;
+      const uint32_t gp = (base + pl) & (L - 1u);   // global row
+      const uint32_t off = (c + gp) & 1u;
+      const uint32_t ctr0 = (gp << lgG) + g0;
+      Words r[VV];
+#pragma unroll
+      for (int v = 0; v < VV; ++v)
+        r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+      TallyN tg = {0u, 0u, 0u};
+      span2d_n<VV>(sp + (pl << lgG), sp + (pu << lgG), sp + (pd << lgG), g0, gmask, off, r, s_thr, tg);
+      if (interior) {
+        t.n += tg.n;
+        t.sb += tg.sb;
+        t.sc += tg.sc;
+      }
+    };
+    if (halo) {
+      // interior rows as V-dword spans, the 2 ext recomputed halo rows as
+      // single dwords spread over every lane
+      const uint32_t items = Ht << a.lg_spr;
+      for (uint32_t q = tid; q < items; q += nt)
+        item(std::integral_constant<int, V>{}, halo + (q >> a.lg_spr), (q & smask) * V, true);
+      const uint32_t hitems = (2u * ext) << lgG;
+      for (uint32_t q = tid; q < hitems; q += nt) {
+        const uint32_t r = q >> lgG;
+        const uint32_t pl = r < ext ? plo + r : halo + Ht + (r - ext);
+        item(std::integral_constant<int, 1>{}, pl, q & gmask, false);
+      }
+    } else {
+      const uint32_t items = Ht << a.lg_spr;
+      for (uint32_t q = tid; q < items; q += nt)
+        item(std::integral_constant<int, V>{}, q >> a.lg_spr, (q & smask) * V, true);
+    }
+    if (c == 1u) {
+      // per flip: dE_int = 2z - 4u, dM = 4b - 2
+      int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb);
+      int dM = 4 * (int)t.sb - 2 * (int)t.n;
+      t = {0u, 0u, 0u};
+      dE = wave_sum(dE);
+      dM = wave_sum(dM);
+      if ((tid & 63u) == 0u) {
+        s_red[tid >> 6][0] = dE;
+        s_red[tid >> 6][1] = dM;
+      }
+    }
+    __syncthreads();
+    if (c == 1u && tid == 0u) {
+      int sE = 0, sM = 0;
+      for (uint32_t v = 0; v < (nt >> 6); ++v) {
+        sE += s_red[v][0];
+        sM += s_red[v][1];
+      }
+      int32_t *acc = a.st.acc3 + ((size_t)(hs >> 1) * G.R + w) * 4u;
+      __hip_atomic_fetch_add(acc, sE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(acc + 1, sM, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+
+  // interior rows back to HBM, packed (contiguous)
+  pack_tile_n(a.dst + (size_t)w * nwr + y0 * wpr, sp + ((size_t)halo << lgG), Ht * wpr, tid, nt);
+  tiled_epilogue(a, tid, nt, &s_last);
 }
 
 struct FusedArgs {
@@ -683,6 +925,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
   const uint32_t tid = threadIdx.x, nt = blockDim.x, w = blockIdx.x;
   uint8_t *sp = smem;
   uint8_t *bx = smem + N, *by = bx + N, *bz = by + N;
+  // every slot's thresholds stay in LDS, so a slot change never waits on memory;
+  // the current slot's row is copied to a fixed LDS address for the lookups
+  uint32_t *thr = reinterpret_cast<uint32_t *>(smem + (size_t)N * (DIM == 3 ? 4u : 1u));
+  for (uint32_t q = tid; q < R * kClasses; q += nt) thr[q] = a.st.flip_thr[q];
 
   uint32_t slot = a.st.slot_of[w];
   int32_t E = a.st.E[w], M = a.st.M[w];
@@ -782,7 +1028,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
       if (s_stop) break;
       if (s_slot != slot) {
         slot = s_slot;
-        if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+        if (tid < kClasses) s_thr[tid] = thr[slot * kClasses + tid];
       }
       __syncthreads();
     }
@@ -1096,6 +1342,15 @@ hipError_t launch_tiled_v(const TiledArgs &a, uint32_t tiles, uint32_t R, uint32
   return hipGetLastError();
 }
 
+template <int V>
+hipError_t launch_tiled_n_v(const TiledArgs &a, uint32_t tiles, uint32_t R, uint32_t threads,
+                            size_t lds, hipStream_t stream) {
+  hipError_t err = allow_lds(k_tiled_n<V>, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_tiled_n<V>), dim3(tiles, R), dim3(threads), lds, stream, a);
+  return hipGetLastError();
+}
+
 template <int DIM, int V>
 hipError_t launch_batch_sweep_v(const BatchInst *insts, const BatchItem *items, uint32_t n_items,
                                 uint32_t W, uint32_t threads, uint32_t K, size_t lds,
@@ -1131,12 +1386,14 @@ size_t max_lds_bytes() { return 160u * 1024u - 1024u; }
 
 size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo) {
   const size_t np = (size_t)std::min(tile_planes, g.L) + 2u * halo;
-  return np * g.plane * (g.dim == 3 ? 4u : 1u);
+  return g.dim == 3 ? np * g.plane * 4u : np * g.plane / 2u; // 3D: spins + 3 bond planes, bytes; 2D: nibbles
 }
 
 size_t fused_lds_bytes(const Geometry &g) { return fused_layout(g.R, g.N, g.dim).total; }
 
-size_t persist_lds_bytes(const Geometry &g) { return (size_t)g.N * (g.dim == 3 ? 4u : 1u); }
+size_t persist_lds_bytes(const Geometry &g) {
+  return (size_t)g.N * (g.dim == 3 ? 4u : 1u) + (size_t)g.R * kClasses * 4u;
+}
 
 uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads) {
   const uint32_t V = span_groups(g);
@@ -1220,9 +1477,9 @@ hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, ui
   if (g.dim == 3)
     return V == 2 ? launch_tiled_v<3, 2>(a, tiles, g.R, threads, lds, stream)
                   : launch_tiled_v<3, 1>(a, tiles, g.R, threads, lds, stream);
-  return V == 4 ? launch_tiled_v<2, 4>(a, tiles, g.R, threads, lds, stream)
-       : V == 2 ? launch_tiled_v<2, 2>(a, tiles, g.R, threads, lds, stream)
-                : launch_tiled_v<2, 1>(a, tiles, g.R, threads, lds, stream);
+  return V == 4 ? launch_tiled_n_v<4>(a, tiles, g.R, threads, lds, stream)
+       : V == 2 ? launch_tiled_n_v<2>(a, tiles, g.R, threads, lds, stream)
+                : launch_tiled_n_v<1>(a, tiles, g.R, threads, lds, stream);
 }
 
 hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,

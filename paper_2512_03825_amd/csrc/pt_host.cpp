@@ -697,6 +697,7 @@ struct pt_batch {
   std::vector<pt_ctx *> ctx;
   hipStream_t user = nullptr, own = nullptr;
   hipEvent_t ev_sync = nullptr;
+  std::vector<hipEvent_t> tune_ev; // [groups][2] start / end of a timed sweep launch
   BatchInst *d_insts = nullptr;
   BatchItem *d_items = nullptr;
   uint2 *d_pairs = nullptr;
@@ -865,6 +866,9 @@ pt_status pt_batch_create(const pt_config *cfgs, uint32_t n, void *hip_stream, v
   if (e == hipSuccess) e = hipStreamSynchronize(b->user);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_sync, hipEventDisableTiming);
+  b->tune_ev.assign(2 * b->groups.size(), nullptr);
+  for (hipEvent_t &ev : b->tune_ev)
+    if (e == hipSuccess) e = hipEventCreate(&ev);
   if (e != hipSuccess) {
     pt_batch_destroy(b);
     return fail(PT_EDEVICE, "batch initialisation: %s", hipGetErrorString(e));
@@ -907,41 +911,43 @@ pt_status pt_batch_run(pt_batch *b, uint32_t n_sweeps, uint32_t exchange_every) 
   bool tuning = false;
   for (auto &G : b->groups) tuning |= !G.tuned;
   while (tuning && cycles > 0) {
-    struct Pending { BatchGroup *G; size_t c; hipEvent_t a, z; };
-    std::vector<Pending> pend;
-    for (auto &G : b->groups) {
+    // groups timing a candidate this cycle: their index and event pair
+    std::vector<size_t> timed_groups;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      BatchGroup &G = b->groups[gi];
       if (G.tuned || G.cand_ms.size() >= G.cand.size()) continue;
       const size_t ci = G.cand_ms.size();
       G.W = G.cand[ci].first;
       G.threads = G.cand[ci].second;
       build_items(b, G);
       if ((e = upload_items(b, G, b->own)) != hipSuccess) return batch_fail(b, e, "batch items");
-      pend.push_back({&G, ci, nullptr, nullptr});
+      timed_groups.push_back(gi);
     }
-    for (auto &p : pend) {
-      hipEventCreate(&p.a);
-      hipEventCreate(&p.z);
-    }
-    size_t pi = 0;
-    for (auto &G : b->groups) {
-      const bool timed = pi < pend.size() && pend[pi].G == &G;
-      if (timed) hipEventRecord(pend[pi].a, b->own);
+    size_t ti = 0;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+      BatchGroup &G = b->groups[gi];
+      const bool timed = ti < timed_groups.size() && timed_groups[ti] == gi;
+      if (timed && (e = hipEventRecord(b->tune_ev[2 * gi], b->own)) != hipSuccess)
+        return batch_fail(b, e, "batch tuning event");
       e = launch_batch_sweep(b->d_insts, b->d_items + G.item_off, (uint32_t)G.items.size(), G.g,
                              G.W, G.threads, K, b->own);
       if (e != hipSuccess) return batch_fail(b, e, "batch sweep launch");
-      if (timed) hipEventRecord(pend[pi++].z, b->own);
+      if (timed) {
+        if ((e = hipEventRecord(b->tune_ev[2 * gi + 1], b->own)) != hipSuccess)
+          return batch_fail(b, e, "batch tuning event");
+        ++ti;
+      }
     }
     if ((e = launch_batch_exchange(b->d_insts, b->d_pairs, b->n_pairs, K, b->own)) != hipSuccess ||
         (e = launch_batch_advance(b->d_insts, n, K, b->own)) != hipSuccess)
       return batch_fail(b, e, "batch cycle launch");
     --cycles;
     if ((e = hipStreamSynchronize(b->own)) != hipSuccess) return batch_fail(b, e, "batch tuning");
-    for (auto &p : pend) {
+    for (size_t gi : timed_groups) {
       float ms = 0.f;
-      hipEventElapsedTime(&ms, p.a, p.z);
-      p.G->cand_ms.push_back(ms);
-      hipEventDestroy(p.a);
-      hipEventDestroy(p.z);
+      if ((e = hipEventElapsedTime(&ms, b->tune_ev[2 * gi], b->tune_ev[2 * gi + 1])) != hipSuccess)
+        return batch_fail(b, e, "batch tuning timing");
+      b->groups[gi].cand_ms.push_back(ms);
     }
     tuning = false;
     for (auto &G : b->groups) {
@@ -961,8 +967,8 @@ pt_status pt_batch_run(pt_batch *b, uint32_t n_sweeps, uint32_t exchange_every) 
   }
   if (cycles > 0) {
     if (b->graph_dirty || b->graph_K != K) {
-      if (b->exec) hipGraphExecDestroy(b->exec);
-      if (b->graph) hipGraphDestroy(b->graph);
+      if (b->exec) (void)hipGraphExecDestroy(b->exec);
+      if (b->graph) (void)hipGraphDestroy(b->graph);
       b->exec = nullptr;
       b->graph = nullptr;
       e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal);
@@ -1020,11 +1026,13 @@ pt_status pt_batch_group_plan(const pt_batch *b, uint32_t g, uint32_t *L, uint32
 
 void pt_batch_destroy(pt_batch *b) {
   if (!b) return;
-  if (b->own) hipStreamSynchronize(b->own);
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  if (b->ev_sync) hipEventDestroy(b->ev_sync);
-  if (b->own) hipStreamDestroy(b->own);
+  if (b->own) (void)hipStreamSynchronize(b->own);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->ev_sync) (void)hipEventDestroy(b->ev_sync);
+  for (hipEvent_t ev : b->tune_ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (b->own) (void)hipStreamDestroy(b->own);
   for (pt_ctx *c : b->ctx) pt_destroy(c);
   delete b;
 }

@@ -38,6 +38,11 @@ namespace ptmi {
 namespace {
 
 constexpr int kMaxThreads = 1024;
+#ifndef PT_NIBBLE_SPAN
+#define PT_NIBBLE_SPAN 8
+#endif
+// Groups (dwords) one lane updates per item in the 2D nibble-layout kernel.
+constexpr uint32_t kNibbleSpan = PT_NIBBLE_SPAN;
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -592,7 +597,17 @@ __device__ __forceinline__ void pack_tile_n(uint32_t *dst, const uint32_t *lds, 
 
 template <int V>
 __device__ __forceinline__ void lds_load_n(uint32_t (&d)[V], const uint32_t *p) {
-  if constexpr (V == 4) {
+  if constexpr (V == 8) {
+    const uint4 a = reinterpret_cast<const uint4 *>(p)[0], b = reinterpret_cast<const uint4 *>(p)[1];
+    d[0] = a.x;
+    d[1] = a.y;
+    d[2] = a.z;
+    d[3] = a.w;
+    d[4] = b.x;
+    d[5] = b.y;
+    d[6] = b.z;
+    d[7] = b.w;
+  } else if constexpr (V == 4) {
     const uint4 a = *reinterpret_cast<const uint4 *>(p);
     d[0] = a.x;
     d[1] = a.y;
@@ -608,7 +623,10 @@ __device__ __forceinline__ void lds_load_n(uint32_t (&d)[V], const uint32_t *p) 
 }
 template <int V>
 __device__ __forceinline__ void lds_store_n(uint32_t *p, const uint32_t (&d)[V]) {
-  if constexpr (V == 4)
+  if constexpr (V == 8) {
+    reinterpret_cast<uint4 *>(p)[0] = make_uint4(d[0], d[1], d[2], d[3]);
+    reinterpret_cast<uint4 *>(p)[1] = make_uint4(d[4], d[5], d[6], d[7]);
+  } else if constexpr (V == 4)
     *reinterpret_cast<uint4 *>(p) = make_uint4(d[0], d[1], d[2], d[3]);
   else if constexpr (V == 2)
     *reinterpret_cast<uint2 *>(p) = make_uint2(d[0], d[1]);
@@ -696,10 +714,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
     const uint32_t s = a.sch.s0 + (hs >> 1);
     const uint32_t ext = halo ? (halo - 1u - hs) : 0u;
     const uint32_t plo = halo - ext;                 // computed LDS rows [plo, plo+Ht+2ext)
-    auto item = [&](auto vtag, uint32_t pl, uint32_t g0, bool interior) {
+    // wrap: rows 0 and np-1 have their neighbours across the tile (whole-replica tiles only)
+    auto item = [&](auto vtag, auto wrap, uint32_t pl, uint32_t g0, bool interior) {
       constexpr int VV = decltype(vtag)::value;
-      const uint32_t pu = (pl == 0u) ? np - 1u : pl - 1u;
-      const uint32_t pd = (pl + 1u == np) ? 0u : pl + 1u;
+      const uint32_t pu = (decltype(wrap)::value && pl == 0u) ? np - 1u : pl - 1u;
+      const uint32_t pd = (decltype(wrap)::value && pl + 1u == np) ? 0u : pl + 1u;
       const uint32_t gp = (base + pl) & (L - 1u);   // global row
       const uint32_t off = (c + gp) & 1u;
       const uint32_t ctr0 = (gp << lgG) + g0;
@@ -720,17 +739,19 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
       // single dwords spread over every lane
       const uint32_t items = Ht << a.lg_spr;
       for (uint32_t q = tid; q < items; q += nt)
-        item(std::integral_constant<int, V>{}, halo + (q >> a.lg_spr), (q & smask) * V, true);
+        item(std::integral_constant<int, V>{}, std::false_type{}, halo + (q >> a.lg_spr),
+             (q & smask) * V, true);
       const uint32_t hitems = (2u * ext) << lgG;
       for (uint32_t q = tid; q < hitems; q += nt) {
         const uint32_t r = q >> lgG;
         const uint32_t pl = r < ext ? plo + r : halo + Ht + (r - ext);
-        item(std::integral_constant<int, 1>{}, pl, q & gmask, false);
+        item(std::integral_constant<int, 1>{}, std::false_type{}, pl, q & gmask, false);
       }
     } else {
       const uint32_t items = Ht << a.lg_spr;
       for (uint32_t q = tid; q < items; q += nt)
-        item(std::integral_constant<int, V>{}, q >> a.lg_spr, (q & smask) * V, true);
+        item(std::integral_constant<int, V>{}, std::true_type{}, q >> a.lg_spr, (q & smask) * V,
+             true);
     }
     if (c == 1u) {
       // per flip: dE_int = 2z - 4u, dM = 4b - 2
@@ -1477,9 +1498,13 @@ hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, ui
   if (g.dim == 3)
     return V == 2 ? launch_tiled_v<3, 2>(a, tiles, g.R, threads, lds, stream)
                   : launch_tiled_v<3, 1>(a, tiles, g.R, threads, lds, stream);
-  return V == 4 ? launch_tiled_n_v<4>(a, tiles, g.R, threads, lds, stream)
-       : V == 2 ? launch_tiled_n_v<2>(a, tiles, g.R, threads, lds, stream)
-                : launch_tiled_n_v<1>(a, tiles, g.R, threads, lds, stream);
+  // the nibble layout holds a group in one dword: up to kNibbleSpan groups per lane
+  const uint32_t Vn = std::min<uint32_t>(kNibbleSpan, g.gpr);
+  a.lg_spr = ilog2(g.gpr / Vn);
+  return Vn == 8 ? launch_tiled_n_v<8>(a, tiles, g.R, threads, lds, stream)
+       : Vn == 4 ? launch_tiled_n_v<4>(a, tiles, g.R, threads, lds, stream)
+       : Vn == 2 ? launch_tiled_n_v<2>(a, tiles, g.R, threads, lds, stream)
+                 : launch_tiled_n_v<1>(a, tiles, g.R, threads, lds, stream);
 }
 
 hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,

@@ -678,15 +678,15 @@ double pt_server_clock(const pt_server *sv) { return sv ? now_s(sv->t0) : 0.0; }
 void pt_server_destroy(pt_server *sv) {
   if (!sv) return;
   for (Lane &ln : sv->lanes)
-    if (ln.s) hipStreamSynchronize(ln.s);
-  if (sv->copy) hipStreamSynchronize(sv->copy);
+    if (ln.s) (void)hipStreamSynchronize(ln.s);
+  if (sv->copy) (void)hipStreamSynchronize(sv->copy);
   for (Lane &ln : sv->lanes) {
     for (Step &st : ln.q)
-      if (st.ev) hipEventDestroy(st.ev);
-    if (ln.s) hipStreamDestroy(ln.s);
+      if (st.ev) (void)hipEventDestroy(st.ev);
+    if (ln.s) (void)hipStreamDestroy(ln.s);
   }
-  for (hipEvent_t e : sv->event_pool) hipEventDestroy(e);
-  if (sv->copy) hipStreamDestroy(sv->copy);
+  for (hipEvent_t e : sv->event_pool) (void)hipEventDestroy(e);
+  if (sv->copy) (void)hipStreamDestroy(sv->copy);
   sv->jobs.clear();
   delete sv;
 }

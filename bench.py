@@ -162,8 +162,41 @@ def bench_batched(args):
            "per_instance_path": {"value": single, "unit": "flip attempts/s",
                                  "sample": "same %d instances one after another, %d sweeps each"
                                            % (len(ws), per_sweeps)},
-           "speedup_vs_per_instance": (attempts / dt) / single}
+           "speedup_vs_per_instance": (attempts / dt) / single,
+           "roofline": batched_roofline(attempts / dt, SLOTS_PER_ATTEMPT[2])}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_instances(ws[:16], 20)
     print(json.dumps(out), flush=True)
+
+
+def batched_roofline(rate, slots):
+    """Whole-cycle VALU roofline of a batched or served run: attempts/s times
+    the algorithmic lane slots per attempt (attempt-weighted over the mix),
+    against the VALU peak (exchange and counter launches are inside the time)."""
+    achieved = rate * slots / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "Tops/s (int32 VALU lane slots)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
+            "traffic": None, "kernel": "k_batch_sweep (whole cycle)",
+            "slots_per_attempt": round(slots, 3)}
+
+
+def cpu_baseline_instances(ws, sweeps):
+    """The CPU oracle on a bounded sample: the first instances of the list, a
+    prefix of each one's schedule, one after another on one core."""
+    import oracle
+    t = 0.0
+    attempts = 0
+    for w in ws:
+        o = oracle.Oracle(w.model, w.L, w.R, w.beta, J=w.J, h=w.h, seed=w.seed,
+                          stream_id=w.stream_id, coupling_seed=w.coupling_seed)
+        n = min(sweeps, w.sweeps)
+        t0 = time.perf_counter()
+        o.run(n, w.exchange_every)
+        t += time.perf_counter() - t0
+        attempts += n * w.attempts_per_sweep
+    return {"value": attempts / t, "unit": "flip attempts/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d instances, %d sweeps each (%.3g flip attempts, %.1f s, single "
+                      "thread)" % (len(ws), sweeps, attempts, t)}
 
 
 def _serve(pt, srv, cfgs, ws, arrivals, t_label):
@@ -271,7 +304,13 @@ def bench_served(args):
                                   "plain: every job's 100-sweep run scaled to its length" % (len(cut), cap_dt)},
            "plain_fifo_latency_s": {"p50": float(np.percentile(plain_lat, 50)),
                                     "p99": float(np.percentile(plain_lat, 99))},
-           "speedup_vs_per_instance": C / plain_capacity}
+           "speedup_vs_per_instance": C / plain_capacity,
+           "roofline": batched_roofline(C, sum(w.attempts_per_sweep * w.sweeps * SLOTS_PER_ATTEMPT[w.dim]
+                                               for w in cut) /
+                                           sum(w.attempts_per_sweep * w.sweeps for w in cut))}
+    out["roofline"]["kernel"] = "served capacity (batched and tiled lanes)"
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_instances(ws[:8], 20)
     print(json.dumps(out), flush=True)
 
 

@@ -227,7 +227,7 @@ void pt_batch_destroy(pt_batch *b);
  * free arena, the resident-job limit and the resident-walker limit.  An admitted
  * job's lattices, tables, random-stream position and counters stay on the
  * device until it finishes.  Jobs whose replicas fit one workgroup's LDS
- * (2D L <= 256, EA L <= 32) join the batched lane: one stream whose cycles run
+ * (2D L <= 512, EA L <= 32) join the batched lane: one stream whose cycles run
  * up to cycle_sweeps sweeps of every resident job in one launch per lattice-size
  * group, then their exchange steps (the batched form's kernels, membership
  * changing between cycles as jobs arrive and finish).  Larger lattices run on

@@ -1076,7 +1076,7 @@ __host__ __device__ inline BatchLayout batch_layout(uint32_t W, uint32_t N, uint
   b.M = b.E + W * 4u;
   b.acc = b.M + W * 4u;
   b.spins = (b.acc + W * 8u + 15u) & ~15u;
-  b.bonds = b.spins + W * N;
+  b.bonds = b.spins + W * (dim == 3 ? N : N / 2u); // 2D: four bits per site
   b.total = b.bonds + (dim == 3 ? 3u * N : 0u);
   return b;
 }
@@ -1189,6 +1189,102 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_sweep(const BatchInst *in
     __syncthreads();
   }
   pack_tile(I.st.spins[0] + (size_t)it.w0 * (N >> 5), sp, (nw * N) >> 5, tid, nt);
+  for (uint32_t v = tid; v < nw; v += nt) {
+    I.st.E[it.w0 + v] = E[v];
+    I.st.M[it.w0 + v] = M[v];
+  }
+}
+
+// 2D batched sweep at four bits per site (the layout of k_tiled_n): W walkers
+// of one instance whole in LDS, the cycle's sweeps in place.
+template <int V>
+__global__ __launch_bounds__(kMaxThreads) void k_batch_sweep_n(const BatchInst *insts,
+                                                               const BatchItem *items, uint32_t W,
+                                                               uint32_t K) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const BatchItem it = items[blockIdx.x];
+  const BatchInst &I = insts[it.inst];
+  const uint32_t nsw = cycle_sweeps(I.ctr, K);
+  if (nsw == 0u) return;
+  const uint32_t s0 = I.ctr[kCtrSweeps];
+  const Geometry &G = I.geo;
+  const uint32_t R = G.R, N = G.N, L = G.L, lgL = I.lg_L;
+  const uint32_t lgG = lgL - 3u, gmask = (1u << lgG) - 1u;   // dwords per row
+  const uint32_t nw = min(W, R - it.w0);
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const BatchLayout B = batch_layout(W, N, 2u);
+  uint32_t *thr = reinterpret_cast<uint32_t *>(smem + B.thr);
+  uint32_t *slot = reinterpret_cast<uint32_t *>(smem + B.slot);
+  int32_t *E = reinterpret_cast<int32_t *>(smem + B.E);
+  int32_t *M = reinterpret_cast<int32_t *>(smem + B.M);
+  int32_t *acc = reinterpret_cast<int32_t *>(smem + B.acc);
+  uint32_t *sp = reinterpret_cast<uint32_t *>(smem + B.spins);
+
+  for (uint32_t v = tid; v < nw; v += nt) {
+    slot[v] = I.st.slot_of[it.w0 + v];
+    E[v] = I.st.E[it.w0 + v];
+    M[v] = I.st.M[it.w0 + v];
+    acc[2u * v] = 0;
+    acc[2u * v + 1u] = 0;
+  }
+  __syncthreads();
+  for (uint32_t q = tid; q < nw * kClasses; q += nt)
+    thr[q] = I.st.flip_thr[slot[q / kClasses] * kClasses + (q % kClasses)];
+  unpack_tile_n(sp, I.st.spins[0] + (size_t)it.w0 * (N >> 5), 0u, (nw * N) >> 5, 0xFFFFFFFFu, tid, nt);
+  __syncthreads();
+
+  const uint32_t smask = (1u << I.lg_spr) - 1u, imask = (1u << I.lg_items) - 1u;
+  const uint32_t items_n = nw << I.lg_items;
+  const uint32_t wdw = N >> 3;                                  // LDS dwords per walker
+  uint32_t rec = I.ctr[kCtrRecords];
+  for (uint32_t j = 0; j < nsw; ++j) {
+    const uint32_t s = s0 + j;
+    for (uint32_t c = 0; c < 2u; ++c) {
+      uint32_t cur = 0xFFFFFFFFu;
+      TallyN t = {0u, 0u, 0u};
+      auto flush = [&]() {
+        atomicAdd(&acc[2u * cur], I.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb));
+        atomicAdd(&acc[2u * cur + 1u], 4 * (int)t.sb - 2 * (int)t.n);
+      };
+      for (uint32_t q = tid; q < items_n; q += nt) {
+        const uint32_t v = q >> I.lg_items;
+        const uint32_t li = q & imask;
+        if (v != cur) {
+          if (cur != 0xFFFFFFFFu) flush();
+          cur = v;
+          t = {0u, 0u, 0u};
+        }
+        const uint32_t g0 = (li & smask) * V;
+        const uint32_t pl = li >> I.lg_spr;
+        const uint32_t pu = (pl + L - 1u) & (L - 1u);
+        const uint32_t pd = (pl + 1u) & (L - 1u);
+        const uint32_t off = (c + pl) & 1u;
+        const uint32_t ctr0 = (pl << lgG) + g0;
+        Words r[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+          r[u] = philox(ctr0 + u, s, slot[v], c | kPurposeFlip, I.key.k0, I.key.k1);
+        uint32_t *wsp = sp + (size_t)v * wdw;
+        span2d_n<V>(wsp + (pl << lgG), wsp + (pu << lgG), wsp + (pd << lgG), g0, gmask, off, r,
+                    thr + v * kClasses, t);
+      }
+      if (cur != 0xFFFFFFFFu) flush();
+      __syncthreads();
+    }
+    for (uint32_t v = tid; v < nw; v += nt) {
+      E[v] += acc[2u * v];
+      M[v] += acc[2u * v + 1u];
+      acc[2u * v] = 0;
+      acc[2u * v + 1u] = 0;
+      if (I.record_every && (s + 1u) % I.record_every == 0u) {
+        I.st.E_series[(size_t)rec * R + slot[v]] = E[v];
+        I.st.M_series[(size_t)rec * R + slot[v]] = M[v];
+      }
+    }
+    if (I.record_every && (s + 1u) % I.record_every == 0u) ++rec;
+    __syncthreads();
+  }
+  pack_tile_n(I.st.spins[0] + (size_t)it.w0 * (N >> 5), sp, (nw * N) >> 5, tid, nt);
   for (uint32_t v = tid; v < nw; v += nt) {
     I.st.E[it.w0 + v] = E[v];
     I.st.M[it.w0 + v] = M[v];
@@ -1369,6 +1465,17 @@ hipError_t launch_tiled_n_v(const TiledArgs &a, uint32_t tiles, uint32_t R, uint
   hipError_t err = allow_lds(k_tiled_n<V>, lds);
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((k_tiled_n<V>), dim3(tiles, R), dim3(threads), lds, stream, a);
+  return hipGetLastError();
+}
+
+template <int V>
+hipError_t launch_batch_sweep_n_v(const BatchInst *insts, const BatchItem *items, uint32_t n_items,
+                                  uint32_t W, uint32_t threads, uint32_t K, size_t lds,
+                                  hipStream_t stream) {
+  hipError_t err = allow_lds(k_batch_sweep_n<V>, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_batch_sweep_n<V>), dim3(n_items), dim3(threads), lds, stream, insts, items,
+                     W, K);
   return hipGetLastError();
 }
 
@@ -1566,9 +1673,9 @@ hipError_t launch_batch_sweep(const BatchInst *insts, const BatchItem *items, ui
   if (g.dim == 3)
     return V == 2 ? launch_batch_sweep_v<3, 2>(insts, items, n_items, W, threads, K, lds, stream)
                   : launch_batch_sweep_v<3, 1>(insts, items, n_items, W, threads, K, lds, stream);
-  return V == 4 ? launch_batch_sweep_v<2, 4>(insts, items, n_items, W, threads, K, lds, stream)
-       : V == 2 ? launch_batch_sweep_v<2, 2>(insts, items, n_items, W, threads, K, lds, stream)
-                : launch_batch_sweep_v<2, 1>(insts, items, n_items, W, threads, K, lds, stream);
+  return V == 4 ? launch_batch_sweep_n_v<4>(insts, items, n_items, W, threads, K, lds, stream)
+       : V == 2 ? launch_batch_sweep_n_v<2>(insts, items, n_items, W, threads, K, lds, stream)
+                : launch_batch_sweep_n_v<1>(insts, items, n_items, W, threads, K, lds, stream);
 }
 
 hipError_t launch_batch_exchange(const BatchInst *insts, const uint2 *pairs, uint32_t n_pairs,

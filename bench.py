@@ -490,7 +490,7 @@ def main():
     hbm_bytes = w.R * ((w.L + halo_planes) * plane_bits + w.L * plane_bits) / 8
     if w.dim == 3:
         hbm_bytes += 3 * w.sites / 8 * (tiles if tiles > 1 else 1)  # packed couplings, read once per tile
-    kernel = {pt.PT_PLAN_TILED: "k_tiled", pt.PT_PLAN_FUSED: "k_fused",
+    kernel = {pt.PT_PLAN_TILED: "k_tiled_n" if w.dim == 2 else "k_tiled", pt.PT_PLAN_FUSED: "k_fused",
               pt.PT_PLAN_PERSISTENT: "k_persist"}[plan["mode"]]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 VALU lane slots)", "frac": round(achieved / VALU_PEAK_TOPS, 4),

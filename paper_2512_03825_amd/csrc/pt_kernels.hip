@@ -702,9 +702,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
   uint32_t *sp = reinterpret_cast<uint32_t *>(smem);
 
   // rows [base, base+np) mod L of this walker, four bits per site; a packed
-  // word (32 sites) becomes four LDS dwords
-  const uint32_t nwr = G.N >> 5, wpr = L >> 5;
-  unpack_tile_n(sp, a.src + (size_t)w * nwr, base * wpr, np * wpr, nwr - 1u, tid, nt);
+  // word (32 sites) becomes four LDS dwords (rows shorter than a word only
+  // occur in whole-replica tiles, which start at row 0)
+  const uint32_t nwr = G.N >> 5;
+  unpack_tile_n(sp, a.src + (size_t)w * nwr, (base * L) >> 5, (np * L) >> 5, nwr - 1u, tid, nt);
   __syncthreads();
 
   const uint32_t smask = (1u << a.lg_spr) - 1u;
@@ -779,7 +780,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
   }
 
   // interior rows back to HBM, packed (contiguous)
-  pack_tile_n(a.dst + (size_t)w * nwr + y0 * wpr, sp + ((size_t)halo << lgG), Ht * wpr, tid, nt);
+  pack_tile_n(a.dst + (size_t)w * nwr + ((y0 * L) >> 5), sp + ((size_t)halo << lgG), (Ht * L) >> 5,
+              tid, nt);
   tiled_epilogue(a, tid, nt, &s_last);
 }
 

@@ -27,7 +27,7 @@ def _instances(rng, n):
             L, R, model = int(rng.choice([8, 16])), int(rng.integers(2, 7)), 1
             beta, h = beta_geometric(0.5, 2.5, R), 0.0
         else:
-            L, R, model = int(rng.choice([16, 32, 64])), int(rng.integers(2, 9)), 0
+            L, R, model = int(rng.choice([8, 16, 32, 64])), int(rng.integers(2, 9)), 0
             beta, h = beta_linear(0.30, 0.55, R), float(rng.uniform(-0.1, 0.1))
         out.append(dict(model=model, L=L, R=R, beta=beta, h=h, seed=4, stream_id=i,
                         coupling_seed=4 + i))

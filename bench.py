@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ising2d_L1024_R64")
+    ap.add_argument("--plan", choices=["auto", "fused", "tiled", "persistent", "lanes"],
+                    default="auto", help="launch decomposition (every plan gives identical results)")
     ap.add_argument("--tile-planes", type=int, default=0)
     ap.add_argument("--sweeps-per-launch", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
@@ -441,9 +443,13 @@ def main():
     cfg = pt.Config(w.model, w.L, w.R, w.beta, J=w.J, seed=w.seed, coupling_seed=w.coupling_seed,
                     record_every=w.record_every, max_records=total_sweeps // w.record_every)
     sim = pt.Simulation(cfg, device="cuda:0")
-    if args.tile_planes or args.sweeps_per_launch or args.threads:
+    if args.plan != "auto" or args.tile_planes or args.sweeps_per_launch or args.threads:
         p = sim.plan()
-        sim.set_plan(pt.PT_PLAN_TILED, args.tile_planes or p["tile_planes"],
+        mode = {"auto": p["mode"], "fused": pt.PT_PLAN_FUSED, "tiled": pt.PT_PLAN_TILED,
+                "persistent": pt.PT_PLAN_PERSISTENT, "lanes": pt.PT_PLAN_LANES}[args.plan]
+        if args.tile_planes or args.sweeps_per_launch:
+            mode = pt.PT_PLAN_TILED
+        sim.set_plan(mode, args.tile_planes or p["tile_planes"],
                      args.sweeps_per_launch or p["sweeps_per_launch"], args.threads or p["block_threads"])
     plan = sim.plan()
     stream = sim.stream
@@ -491,7 +497,7 @@ def main():
     if w.dim == 3:
         hbm_bytes += 3 * w.sites / 8 * (tiles if tiles > 1 else 1)  # packed couplings, read once per tile
     kernel = {pt.PT_PLAN_TILED: "k_tiled_n" if w.dim == 2 else "k_tiled", pt.PT_PLAN_FUSED: "k_fused",
-              pt.PT_PLAN_PERSISTENT: "k_persist"}[plan["mode"]]
+              pt.PT_PLAN_PERSISTENT: "k_persist", pt.PT_PLAN_LANES: "k_lanes"}[plan["mode"]]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 VALU lane slots)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": measured_traffic(kernel, w.name, plan, per_launch), "kernel": kernel,

@@ -94,12 +94,18 @@ typedef struct {
  *               epilogue of the last workgroup.
  *   PERSISTENT  one co-resident workgroup per walker keeps its lattice in LDS
  *               for a whole pt_run call; exchange steps are decided pairwise
- *               between neighbouring slots without a global barrier. */
+ *               between neighbouring slots without a global barrier.
+ *   LANES       the paper's GPU decomposition (Sec. 3: one replica per thread):
+ *               each lane holds one walker's whole lattice in registers and
+ *               updates it site after site; one workgroup runs every walker and
+ *               the exchange steps.  2D, L = 8 or 16, R <= 1024 only; never
+ *               chosen automatically (a reference point for the other plans). */
 typedef enum {
   PT_PLAN_AUTO = 0,
   PT_PLAN_FUSED = 1,
   PT_PLAN_TILED = 2,
-  PT_PLAN_PERSISTENT = 3
+  PT_PLAN_PERSISTENT = 3,
+  PT_PLAN_LANES = 4
 } pt_plan_mode;
 typedef struct {
   uint32_t mode;              /* pt_plan_mode */

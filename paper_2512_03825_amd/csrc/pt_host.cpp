@@ -230,6 +230,15 @@ pt_status device_fail(pt_ctx *c, hipError_t e, const char *what) {
 
 pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
   const Geometry &g = c->d.geo;
+  if (p.mode == PT_PLAN_LANES) { // block size follows R
+    if (g.dim != 2 || (g.L != 8 && g.L != 16))
+      return fail(PT_EINVAL, "the lanes plan holds a lattice in registers: 2D with L = 8 or 16 only");
+    if (g.R > 1024) return fail(PT_EINVAL, "the lanes plan runs one workgroup: R <= 1024");
+    if (lanes_lds_bytes(g) > max_lds_bytes())
+      return fail(PT_EINVAL, "lanes plan needs %zu bytes of LDS (max %zu)", lanes_lds_bytes(g),
+                  max_lds_bytes());
+    return PT_OK;
+  }
   if (p.block_threads < 64 || p.block_threads > 1024 || p.block_threads % 64)
     return fail(PT_EINVAL, "block_threads = %u: must be a multiple of 64 in [64, 1024]", p.block_threads);
   if (p.mode == PT_PLAN_FUSED) {
@@ -302,8 +311,18 @@ pt_plan auto_plan(const pt_ctx *c) {
     p.tile_planes = g.L; // small rows: whole-replica tiles, updated in place
     p.block_threads = 256;
   } else {
-    // Tiles of full rows with about 64 KB of spins in LDS.
-    p.tile_planes = std::max<uint32_t>(8u, std::min<uint32_t>(g.L, (64u * 1024u) / g.L));
+    // Tiles of full rows at four bits per site: the tallest tile (fewest
+    // recomputed halo rows) that fits 144 KB of LDS with halos for 5 sweeps
+    // per launch while the grid still gives every compute unit a workgroup.
+    p.sweeps_per_launch = 5;
+    uint32_t H = g.L;
+    auto fits = [&](uint32_t h) {
+      const uint32_t halo = h >= g.L ? 0u : 2u * p.sweeps_per_launch;
+      return tiled_lds_bytes(g, h, halo) <= 144u * 1024u && (g.L / h) * g.R >= 256u;
+    };
+    while (H > 32u && !fits(H)) H /= 2u;
+    p.tile_planes = H;
+    p.block_threads = H >= 256u ? 1024u : 512u;
   }
   for (int tries = 0; tries < 8 && check_plan(c, p) != PT_OK; ++tries) {
     // shrink until the plan fits (LDS, halo rules); whole-replica tiles always fit
@@ -340,13 +359,16 @@ pt_status ctx_advance(pt_ctx *c, uint32_t n, uint32_t every) {
     sch.ex_step = (uint32_t)c->exchanges;
     uint32_t nsw, nex = 0;
     hipError_t err;
-    if (c->plan.mode == PT_PLAN_FUSED || c->plan.mode == PT_PLAN_PERSISTENT) {
+    if (c->plan.mode == PT_PLAN_FUSED || c->plan.mode == PT_PLAN_PERSISTENT ||
+        c->plan.mode == PT_PLAN_LANES) {
       nsw = std::min(left, kFusedChunk);
       sch.nsw = nsw;
       sch.exchange_every = every;
       nex = records_between(every, c->sweeps, c->sweeps + nsw);
       err = c->plan.mode == PT_PLAN_FUSED
                 ? launch_fused(c->st, g, c->keys, c->cur, c->plan.block_threads, sch, c->stream)
+            : c->plan.mode == PT_PLAN_LANES
+                ? launch_lanes(c->st, g, c->keys, c->cur, sch, c->stream)
                 : launch_persist(c->st, g, c->keys, c->cur, c->plan.block_threads, sch,
                                  kSpinLimit, c->stream);
     } else {
@@ -491,10 +513,12 @@ pt_status pt_set_plan(pt_ctx *ctx, const pt_plan *plan) {
   s = check_plan(ctx, *plan);
   if (s != PT_OK) return s;
   ctx->plan = *plan;
-  if (ctx->plan.mode == PT_PLAN_FUSED || ctx->plan.mode == PT_PLAN_PERSISTENT) {
+  if (ctx->plan.mode == PT_PLAN_FUSED || ctx->plan.mode == PT_PLAN_PERSISTENT ||
+      ctx->plan.mode == PT_PLAN_LANES) {
     ctx->plan.tile_planes = ctx->d.geo.L;
     ctx->plan.sweeps_per_launch = 1;
   }
+  if (ctx->plan.mode == PT_PLAN_LANES) ctx->plan.block_threads = (ctx->d.geo.R + 63u) & ~63u;
   return PT_OK;
 }
 

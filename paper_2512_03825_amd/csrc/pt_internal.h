@@ -124,6 +124,10 @@ hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, ui
                         const Schedule &sch, hipStream_t stream);
 hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
                         uint32_t threads, const Schedule &sch, hipStream_t stream);
+// One lane per walker, whole lattice in registers (2D, L = 8 or 16, R <= 1024).
+hipError_t launch_lanes(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
+                        const Schedule &sch, hipStream_t stream);
+size_t lanes_lds_bytes(const Geometry &g);
 // One co-resident workgroup per walker for the whole launch; exchange decisions
 // are taken pairwise through per-slot mailboxes (cooperative launch).
 hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,

@@ -1,32 +1,40 @@
 // pt_kernels.hip -- gfx950 kernels of the parallel-tempering Metropolis library.
 //
-// Spin storage: one byte per site, 0 = up (s = +1), 1 = down (s = -1), so
-// that the number of unsatisfied bonds of a site is a byte-wise sum of XORs.
-// A lattice row of L sites is L/8 "groups" of 8 bytes; in every group the four
-// sites of the colour being updated sit at byte positions off, off+2, off+4,
-// off+6 (off = colour parity of the row), and they consume the four words of
-// one Philox4x32-10 block whose counter is the group's index: the draw of site
-// i is word (i/2) mod 4 of block (i/2)/4, as the method's draw mapping fixes.
+// Lattices live bit-packed in HBM (bit set = down spin) and are unpacked into
+// LDS for updating.  Two LDS layouts:
+//   - four bits per site (2D tiled and batched kernels): a row of L sites is
+//     L/8 dwords, one dword per group of 8 sites;
+//   - one byte per site (3D kernels, and the fused and persistent kernels): a
+//     row is L/8 groups of 8 bytes.
+// Either way a value of 0 is an up spin (s = +1) and 1 a down spin, so the
+// number of unsatisfied bonds of a site is a nibble- or byte-wise sum of
+// XORs with its neighbours (SWAR).  In a group the four sites of the colour
+// being updated sit at positions off, off+2, off+4, off+6 (off = colour parity
+// of the row) and consume the four words of one Philox4x32-10 block whose
+// counter is the group's index: the draw of site i is word (i/2) mod 4 of
+// block (i/2)/4, as the method's draw mapping fixes.
 //
-// Work of one group (one lane): three (2D) or five (3D) 8-byte neighbour
-// words plus one edge byte from LDS, a SWAR count of unsatisfied bonds per
-// byte, one Philox block (18 64-bit multiplies + 20 three-way XORs), four
-// LDS threshold lookups and compares, one 8-byte store, and the exact integer
-// energy / magnetisation change of the accepted flips (dot4 bookkeeping).
+// Work of one group: the neighbour words from LDS, a SWAR count of unsatisfied
+// bonds, one Philox block (18 vector 64-bit multiplies + 20 three-way XORs),
+// four LDS threshold lookups and compares, one store, and the exact integer
+// energy / magnetisation change of the accepted flips (dot-product tallies).
 //
 // Kernels:
-//   k_tiled<DIM>   grid (tiles, walkers).  A workgroup stages one tile of
-//                  planes (rows in 2D, z-planes in 3D) plus halo planes of its
-//                  walker in LDS and runs up to 8 sweeps on it.  With halo
-//                  depth 2k for k sweeps the interior stays exact (every half
-//                  sweep recomputes one plane less on each side with the same
-//                  draws); tiles read one spin buffer and write the other.  A
+//   k_tiled_n      2D, grid (tiles, walkers).  A workgroup stages one tile of
+//   k_tiled<3>     rows (z-planes in 3D) plus halo rows of its walker in LDS
+//                  and runs up to 8 sweeps on it.  With halo depth 2k for k
+//                  sweeps the interior stays exact (every half sweep
+//                  recomputes one row less on each side with the same draws);
+//                  tiles read one spin buffer and write the other.  A
 //                  whole-replica tile (halo 0) updates in place.  The last
 //                  workgroup to finish folds the per-sweep energy changes into
 //                  E and M, writes the records, and runs the exchange step.
-//   k_fused<DIM>   one workgroup holds every walker of a small system in LDS
+//   k_fused        one workgroup holds every walker of a small system in LDS
 //                  and runs sweeps, records and exchange steps without leaving
 //                  the kernel.
+//   k_persist      one co-resident workgroup per walker for a whole run;
+//                  exchanges decided pairwise through mailboxes.
+//   k_batch_*      batched and served forms: many instances per launch.
 //   k_exchange     one exchange step (slot permutation, no lattice copies).
 //   k_init_*, k_reset, k_recount   initialisation.
 #include "pt_internal.h"
@@ -422,6 +430,7 @@ __device__ void tiled_epilogue(const TiledArgs &a, uint32_t tid, uint32_t nt, ui
 
 template <int DIM, int V>
 __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
+  static_assert(DIM == 3, "2D lattices use the four-bit layout of k_tiled_n");
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint32_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
@@ -479,31 +488,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
       for (int v = 0; v < VV; ++v)
         r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
       Tally tg = {0, 0, 0};
-      if constexpr (DIM == 2)
-        span2d<VV>(sp + (pl << lgP), sp + (pu << lgP), sp + (pd << lgP), g0, L, off, r, s_thr, tg);
-      else
-        span3d<VV>(sp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, s_thr, tg);
+      span3d<VV>(sp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, s_thr, tg);
       if (interior) {
         t.n += tg.n;
         t.sb += tg.sb;
         t.sc += tg.sc;
       }
     };
-    if (DIM == 2 && halo) {
-      // Interior rows as V-group spans (a whole number of rounds when the
-      // tile's spans fill the workgroup evenly), the 2 ext recomputed halo
-      // rows as single groups spread over every lane.
-      const uint32_t items = Ht << a.lg_spr;
-      for (uint32_t q = tid; q < items; q += nt)
-        item(std::integral_constant<int, V>{}, halo + (q >> a.lg_spr), 0u, (q & smask) * V, true);
-      const uint32_t lgG = lgL - 3u;
-      const uint32_t hitems = (2u * ext) << lgG;
-      for (uint32_t q = tid; q < hitems; q += nt) {
-        const uint32_t r = q >> lgG;
-        const uint32_t pl = r < ext ? plo + r : halo + Ht + (r - ext);
-        item(std::integral_constant<int, 1>{}, pl, 0u, q & ((1u << lgG) - 1u), false);
-      }
-    } else {
+    {
       const uint32_t items = (Ht + 2u * ext) << shp;
       for (uint32_t q = tid; q < items; q += nt) {
         const uint32_t pl = plo + (q >> shp);
@@ -1065,6 +1057,105 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
   }
 }
 
+// ---- one walker per lane (the paper's decomposition) -----------------------
+// Lane w holds walker w's bit-packed lattice in registers (N/32 words, bit i =
+// site i, as in HBM) and visits its colour-c sites one after another; the
+// workgroup's LDS holds every slot's thresholds, the walkers' E and M and the
+// walker/slot maps for the exchange steps.  All indexing is unrolled at
+// compile time for the lattice side L.
+template <int L>
+__device__ __forceinline__ uint32_t lane_bit(const uint32_t (&S)[L * L / 32], int x, int y) {
+  const int i = ((y + L) % L) * L + ((x + L) % L);
+  return (S[i >> 5] >> (i & 31)) & 1u;
+}
+
+template <int L>
+__global__ __launch_bounds__(kMaxThreads) void k_lanes(FusedArgs a) {
+  constexpr int NW = L * L / 32, GPR = L / 8;
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint32_t R = a.geo.R, tid = threadIdx.x, nt = blockDim.x;
+  uint32_t *thr = reinterpret_cast<uint32_t *>(smem);        // [R][16]
+  int32_t *E = reinterpret_cast<int32_t *>(thr + R * kClasses); // [R] by walker
+  int32_t *M = E + R;
+  uint32_t *wat = reinterpret_cast<uint32_t *>(M + R);
+  uint32_t *sof = wat + R;
+  for (uint32_t q = tid; q < R * kClasses; q += nt) thr[q] = a.st.flip_thr[q];
+  for (uint32_t q = tid; q < R; q += nt) {
+    E[q] = a.st.E[q];
+    M[q] = a.st.M[q];
+    wat[q] = a.st.walker_at[q];
+    sof[q] = a.st.slot_of[q];
+  }
+  const bool live = tid < R;
+  const uint32_t w = tid;
+  uint32_t S[NW];
+#pragma unroll
+  for (int j = 0; j < NW; ++j) S[j] = live ? a.spins[(size_t)w * NW + j] : 0u;
+  __syncthreads();
+  int32_t e = live ? E[w] : 0, m = live ? M[w] : 0;
+  uint32_t rec = a.sch.rec_base, ex = a.sch.ex_step;
+  for (uint32_t j = 0; j < a.sch.nsw; ++j) {
+    const uint32_t s = a.sch.s0 + j;
+    const uint32_t slot = live ? sof[w] : 0u;
+    if (live) {
+      const uint32_t *T = thr + slot * kClasses;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+#pragma unroll
+        for (int y = 0; y < L; ++y) {
+          const int off = (c + y) & 1;
+#pragma unroll
+          for (int g = 0; g < GPR; ++g) {
+            const Words r = philox((uint32_t)(y * GPR + g), s, slot, (uint32_t)c | kPurposeFlip,
+                                   a.key.k0, a.key.k1);
+            const uint32_t rw[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+            for (int mm = 0; mm < 4; ++mm) {
+              const int x = 8 * g + off + 2 * mm, i = y * L + x;
+              const uint32_t b = lane_bit<L>(S, x, y);
+              const uint32_t nb = lane_bit<L>(S, x - 1, y) + lane_bit<L>(S, x + 1, y) +
+                                  lane_bit<L>(S, x, y - 1) + lane_bit<L>(S, x, y + 1);
+              const uint32_t u = b ? 4u - nb : nb;        // neighbours unlike the site
+              if (rw[mm] <= T[8u * b + u]) {
+                S[i >> 5] ^= 1u << (i & 31);
+                e += 8 - 4 * (int32_t)u;                  // dE_int = 2z - 4u
+                m += 4 * (int32_t)b - 2;                  // dM = -2 s
+              }
+            }
+          }
+        }
+      }
+      if (a.sch.record_every && (s + 1u) % a.sch.record_every == 0u) {
+        a.st.E_series[(size_t)rec * R + slot] = e;
+        a.st.M_series[(size_t)rec * R + slot] = m;
+      }
+    }
+    if (a.sch.record_every && (s + 1u) % a.sch.record_every == 0u) ++rec;
+    if (a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u) {
+      if (live) {
+        E[w] = e;
+        M[w] = m;
+      }
+      __syncthreads();
+      exchange_step(a.st, R, a.key.k0, a.key.k1, ex, E, M, wat, sof, tid, nt);
+      ++ex;
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NW; ++j)
+    if (live) a.spins[(size_t)w * NW + j] = S[j];
+  if (live) {
+    a.st.E[w] = e;
+    a.st.M[w] = m;
+  }
+  __syncthreads();
+  for (uint32_t q = tid; q < R; q += nt) {
+    a.st.walker_at[q] = wat[q];
+    a.st.slot_of[q] = sof[q];
+  }
+}
+
 // ---- batched form ----------------------------------------------------------
 // LDS layout of a batched-sweep workgroup holding W walkers of one instance.
 struct BatchLayout {
@@ -1099,6 +1190,7 @@ template <int DIM, int V>
 __global__ __launch_bounds__(kMaxThreads) void k_batch_sweep(const BatchInst *insts,
                                                              const BatchItem *items, uint32_t W,
                                                              uint32_t K) {
+  static_assert(DIM == 3, "2D lattices use the four-bit layout of k_batch_sweep_n");
   extern __shared__ __align__(16) uint8_t smem[];
   const BatchItem it = items[blockIdx.x];
   const BatchInst &I = insts[it.inst];
@@ -1165,11 +1257,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_sweep(const BatchInst *in
         for (int u = 0; u < V; ++u)
           r[u] = philox(ctr0 + u, s, slot[v], c | kPurposeFlip, I.key.k0, I.key.k1);
         uint8_t *wsp = sp + (size_t)v * N;
-        if (DIM == 2)
-          span2d<V>(wsp + (pl << lgP), wsp + (pu << lgP), wsp + (pd << lgP), g0, L, off, r,
-                    thr + v * kClasses, t);
-        else
-          span3d<V>(wsp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, thr + v * kClasses, t);
+        span3d<V>(wsp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, thr + v * kClasses, t);
       }
       if (cur != 0xFFFFFFFFu) {
         atomicAdd(&acc[2u * cur], I.z2 * t.n - (t.sc - 32 * t.sb));
@@ -1614,6 +1702,29 @@ hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, ui
        : Vn == 4 ? launch_tiled_n_v<4>(a, tiles, g.R, threads, lds, stream)
        : Vn == 2 ? launch_tiled_n_v<2>(a, tiles, g.R, threads, lds, stream)
                  : launch_tiled_n_v<1>(a, tiles, g.R, threads, lds, stream);
+}
+
+size_t lanes_lds_bytes(const Geometry &g) { return (size_t)g.R * (kClasses + 4u) * 4u; }
+
+hipError_t launch_lanes(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
+                        const Schedule &sch, hipStream_t stream) {
+  FusedArgs a;
+  a.st = st;
+  a.geo = g;
+  a.key = k;
+  a.sch = sch;
+  a.spins = st.spins[cur];
+  const uint32_t threads = (g.R + 63u) & ~63u;
+  const size_t lds = lanes_lds_bytes(g);
+  if (g.dim != 2 || (g.L != 8 && g.L != 16) || threads > (uint32_t)kMaxThreads)
+    return hipErrorInvalidValue;
+  hipError_t err = g.L == 8 ? allow_lds(k_lanes<8>, lds) : allow_lds(k_lanes<16>, lds);
+  if (err != hipSuccess) return err;
+  if (g.L == 8)
+    hipLaunchKernelGGL(k_lanes<8>, dim3(1), dim3(threads), lds, stream, a);
+  else
+    hipLaunchKernelGGL(k_lanes<16>, dim3(1), dim3(threads), lds, stream, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,

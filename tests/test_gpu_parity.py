@@ -14,7 +14,7 @@ from paper_2512_03825_amd.workloads import beta_geometric, beta_linear, ising16
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
-FUSED, TILED, PERSISTENT = 1, 2, 3
+FUSED, TILED, PERSISTENT, LANES = 1, 2, 3, 4
 
 
 @pytest.fixture(scope="module")
@@ -64,6 +64,7 @@ def test_ising16_full_run_auto_plan(pt, oracle_mod):
     dict(mode=TILED, tile_planes=32, sweeps_per_launch=8, block_threads=1024),
     dict(mode=FUSED, block_threads=64),
     dict(mode=FUSED, block_threads=1024),
+    dict(mode=LANES),                                                           # one walker per lane
 ])
 def test_ising16_every_plan_is_identical(pt, oracle_mod, plan):
     w = ising16()
@@ -191,3 +192,42 @@ def test_beta_zero_negates_every_sweep(pt, oracle_mod):
     obs = sim.observables(spins="all")
     wat = obs["walker_at"]
     np.testing.assert_array_equal(obs["spins"], -s0[wat])
+
+
+@pytest.mark.parametrize("L, R, every, h, split", [
+    (8, 5, 3, 0.0, False),
+    (16, 70, 10, 0.0, False),     # two waves of walkers, the second partly empty
+    (16, 9, 1, 0.15, True),       # field swaps, primitive calls
+    (8, 1, 0, 0.0, False),        # one walker, no exchange
+])
+def test_lanes_plan_matches_oracle(pt, oracle_mod, L, R, every, h, split):
+    """The replica-per-lane plan (the paper's decomposition) against the oracle."""
+    beta = beta_linear(0.25, 0.7, R)
+    sweeps = 60
+    tag = "lanes L%d R%d" % (L, R)
+    say("case", tag, "every", every, "h", h)
+    cfg = pt.Config(0, L, R, beta, h=h, seed=21, stream_id=3, record_every=1, max_records=sweeps)
+    sim = pt.Simulation(cfg)
+    sim.set_plan(LANES)
+    assert sim.plan()["mode"] == LANES
+    orc = oracle_mod.Oracle(0, L, R, beta, h=h, seed=21, stream_id=3, record_every=1,
+                            max_records=sweeps)
+    if split:
+        for _ in range(sweeps // every):
+            sim.sweep(every)
+            sim.exchange()
+            orc.sweep(every)
+            orc.exchange()
+    else:
+        sim.run(sweeps, every)
+        orc.run(sweeps, every)
+    compare(sim, orc, tag)
+
+
+def test_lanes_plan_rejects_other_shapes(pt):
+    for model, L, R in ((0, 32, 4), (1, 8, 4), (0, 16, 1100)):
+        beta = beta_linear(0.3, 0.5, R)
+        sim = pt.Simulation(pt.Config(model, L, R, beta, seed=1))
+        with pytest.raises(pt.PTError):
+            sim.set_plan(LANES)
+        sim.close()

@@ -248,14 +248,14 @@ def bench_served(args):
     opts = dict(max_jobs=4096, max_walkers=1 << 20, tiled_lanes=2, depth=2, cycle_sweeps=10,
                 tiled_sweeps=10)
     srv = pt.Server(int(args.arena_gib * (1 << 30)), device="cuda:0", **opts)
-    # capacity: the same jobs cut to 500 sweeps, all submitted at once
+    # capacity: the first 200 jobs cut to 2000 sweeps, all submitted at once
     cap_ws = [w for w in ws[:200]]
     cap_cfgs = cfgs[:200]
     import copy
     cut = []
     for w in cap_ws:
         w2 = copy.copy(w)
-        w2.sweeps = min(w.sweeps, 500)
+        w2.sweeps = min(w.sweeps, 2000)
         cut.append(w2)
     t = time.perf_counter()
     _serve(pt, srv, cap_cfgs, cut, np.zeros(len(cut)), "capacity")
@@ -302,7 +302,7 @@ def bench_served(args):
            "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                          "max": float(lat.max())},
            "capacity": {"served": C, "plain_per_instance": plain_capacity,
-                        "sample": "served: first %d jobs cut to 500 sweeps, all at t=0 (%.1f s); "
+                        "sample": "served: first %d jobs cut to 2000 sweeps, all at t=0 (%.1f s); "
                                   "plain: every job's 100-sweep run scaled to its length" % (len(cut), cap_dt)},
            "plain_fifo_latency_s": {"p50": float(np.percentile(plain_lat, 50)),
                                     "p99": float(np.percentile(plain_lat, 99))},

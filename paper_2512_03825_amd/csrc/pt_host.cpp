@@ -339,6 +339,42 @@ pt_status usable(pt_ctx *c) {
   return PT_OK;
 }
 
+// Threshold tables depend only on the model, the lattice size, the ladder, J
+// and h; contexts with equal inputs (served jobs drawn from a few ladders) share
+// one immutable copy instead of rebuilding it (up to ~10^6 exp() calls).
+std::shared_ptr<const Tables> shared_tables(const pt_config *cfg, const Derived &d) {
+  static std::mutex mu;
+  static std::map<std::string, std::shared_ptr<const Tables>> cache;
+  static std::vector<std::string> order; // insertion order, oldest first
+  constexpr size_t kMaxCached = 256;
+  std::string key;
+  key.reserve(40 + 8 * (size_t)cfg->R);
+  auto put = [&](const void *p, size_t n) { key.append(reinterpret_cast<const char *>(p), n); };
+  put(&cfg->model, sizeof cfg->model);
+  put(&d.geo.L, sizeof d.geo.L);
+  put(&cfg->R, sizeof cfg->R);
+  put(&cfg->J, sizeof cfg->J);
+  put(&cfg->h, sizeof cfg->h);
+  put(cfg->beta, (size_t)cfg->R * sizeof(double));
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+  }
+  auto t = std::make_shared<Tables>();
+  build_tables(cfg, d, t.get());
+  std::lock_guard<std::mutex> lk(mu);
+  auto ins = cache.emplace(key, t);
+  if (ins.second) {
+    order.push_back(key);
+    if (order.size() > kMaxCached) {
+      cache.erase(order.front());
+      order.erase(order.begin());
+    }
+  }
+  return ins.first->second;
+}
+
 }  // namespace
 
 namespace ptmi {
@@ -429,7 +465,7 @@ pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d
     delete c;
     return fail(PT_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, layout(cfg, d).total);
   }
-  build_tables(&c->cfg, d, &c->tab);
+  c->tab = shared_tables(&c->cfg, d);
   c->stream = hip_stream;
 
   uint8_t *base = (uint8_t *)d_workspace;
@@ -443,7 +479,7 @@ pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d
   st.swap_off = (uint32_t *)(base + l.swap_off);
   st.swap_D = (uint32_t *)(base + l.swap_D);
   st.swap_sat = (uint64_t *)(base + l.swap_sat);
-  st.swap_n = (uint32_t)c->tab.swap.size();
+  st.swap_n = (uint32_t)c->tab->swap.size();
   st.field_thr = (uint64_t *)(base + l.field);
   st.field_sign = (int32_t *)(base + l.fsign);
   st.walker_at = (uint32_t *)(base + l.wat);
@@ -464,13 +500,13 @@ pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d
   auto H2D = [&](void *dst, const void *src, size_t n) {
     if (e == hipSuccess && n) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, sm);
   };
-  H2D(st.flip_thr, c->tab.flip.data(), c->tab.flip.size() * 4);
-  H2D(st.swap_tab, c->tab.swap.data(), c->tab.swap.size() * 8);
-  H2D(st.swap_off, c->tab.off.data(), R * 4);
-  H2D(st.swap_D, c->tab.D.data(), R * 4);
-  H2D(st.swap_sat, c->tab.sat.data(), R * 16);
-  H2D(st.field_thr, c->tab.field.data(), c->tab.field.size() * 8);
-  H2D(st.field_sign, c->tab.fsign.data(), R * 4);
+  H2D(st.flip_thr, c->tab->flip.data(), c->tab->flip.size() * 4);
+  H2D(st.swap_tab, c->tab->swap.data(), c->tab->swap.size() * 8);
+  H2D(st.swap_off, c->tab->off.data(), R * 4);
+  H2D(st.swap_D, c->tab->D.data(), R * 4);
+  H2D(st.swap_sat, c->tab->sat.data(), R * 16);
+  H2D(st.field_thr, c->tab->field.data(), c->tab->field.size() * 8);
+  H2D(st.field_sign, c->tab->fsign.data(), R * 4);
   if (e == hipSuccess) e = launch_reset(st, d.geo, sm);
   if (d.geo.dim == 3) {
     if (cfg->couplings) H2D(st.staging, cfg->couplings, 3 * N);
@@ -626,20 +662,20 @@ pt_status pt_observables(pt_ctx *ctx, pt_obs *obs) {
 
 pt_status pt_flip_thresholds(const pt_ctx *ctx, uint32_t *out) {
   if (!ctx || !out) return fail(PT_EINVAL, "NULL argument");
-  std::memcpy(out, ctx->tab.flip.data(), ctx->tab.flip.size() * 4);
+  std::memcpy(out, ctx->tab->flip.data(), ctx->tab->flip.size() * 4);
   return PT_OK;
 }
 
 pt_status pt_swap_threshold(const pt_ctx *ctx, uint32_t k, int64_t d, uint64_t *out_T) {
   if (!ctx || !out_T) return fail(PT_EINVAL, "NULL argument");
   if (k + 1 >= ctx->d.geo.R) return fail(PT_EINVAL, "pair %u out of range", k);
-  const int64_t D = ctx->tab.D[k];
+  const int64_t D = ctx->tab->D[k];
   if (d < -D)
-    *out_T = ctx->tab.sat[2 * (size_t)k];
+    *out_T = ctx->tab->sat[2 * (size_t)k];
   else if (d > D)
-    *out_T = ctx->tab.sat[2 * (size_t)k + 1];
+    *out_T = ctx->tab->sat[2 * (size_t)k + 1];
   else
-    *out_T = ctx->tab.swap[ctx->tab.off[k] + (size_t)(d + D)];
+    *out_T = ctx->tab->swap[ctx->tab->off[k] + (size_t)(d + D)];
   return PT_OK;
 }
 

@@ -6,6 +6,7 @@
 #include "pt.h"
 #include "pt_internal.h"
 
+#include <memory>
 #include <utility>
 #include <vector>
 
@@ -56,7 +57,7 @@ struct pt_ctx {
   Keys keys;
   DevState st;
   Layout lay;
-  Tables tab;
+  std::shared_ptr<const Tables> tab; // shared with contexts of the same ladder
   hipStream_t stream;
   pt_plan plan;
   uint64_t sweeps = 0, exchanges = 0;

@@ -294,6 +294,17 @@ pt_status admit(pt_server *sv) {
       sv->poisoned = true;
       return s;
     }
+    if (!batched && j.ctx->d.geo.dim == 2) {
+      // Tiled lanes run several jobs at once, so a job's own grid need not
+      // fill the chip: tall tiles (fewest recomputed halo rows) and 5 sweeps
+      // per launch; the context's automatic plan stays if this one is invalid.
+      pt_plan p{};
+      p.mode = PT_PLAN_TILED;
+      p.tile_planes = std::min<uint32_t>(j.ctx->d.geo.L, 256u);
+      p.sweeps_per_launch = 5;
+      p.block_threads = p.tile_planes >= 256u ? 1024u : 512u;
+      (void)pt_set_plan(j.ctx, &p);
+    }
     j.admitted = now_s(sv->t0);
     ++sv->resident;
     if (batched) {

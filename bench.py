@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--jobs", type=int, default=400, help="served form: jobs in the stream")
     ap.add_argument("--rho", type=float, default=0.8, help="served form: offered load / capacity")
     ap.add_argument("--arena-gib", type=float, default=8.0, help="served form: job arena (GiB)")
-    ap.add_argument("--tiled-lanes", type=int, default=3, help="served form: streams for large lattices")
+    ap.add_argument("--tiled-lanes", type=int, default=2, help="served form: streams for large lattices")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 64 MiB device-to-device copy (a kernel of known "
                          "traffic, to scale HBM counters)")

@@ -231,3 +231,35 @@ def test_lanes_plan_rejects_other_shapes(pt):
         with pytest.raises(pt.PTError):
             sim.set_plan(LANES)
         sim.close()
+
+
+@pytest.mark.parametrize("model, L, R, sweeps, every", [
+    (0, 2048, 3, 4, 2),    # automatic plan: 128-row tiles
+    (0, 4096, 2, 2, 1),    # 64-row tiles, exchange after every sweep
+    (1, 64, 3, 3, 1),      # largest EA lattice, tiled 3D plan
+])
+def test_large_lattices_match_oracle(pt, oracle_mod, model, L, R, sweeps, every):
+    """Larger sides than the benchmark's, through their automatic plans."""
+    beta = beta_geometric(0.5, 3.0, R) if model == 1 else beta_linear(0.35, 0.50, R)
+    run_case(pt, oracle_mod, model, L, R, beta, 17, sweeps, every, coupling_seed=9,
+             tag="large L%d" % L)
+
+
+def test_largest_2d_lattice_bookkeeping(pt):
+    """2D L = 16384 (the largest side): after a few sweeps and exchanges the
+    incrementally tracked E and M of every slot equal a recount from the
+    returned spins, and the walker map is a permutation."""
+    L, R = 16384, 2
+    beta = beta_linear(0.40, 0.45, R)
+    say("case largest 2D L", L, "R", R)
+    sim = make_gpu(pt, 0, L, R, beta, 23, record_every=0, max_records=0)
+    sim.run(3, 1)
+    obs = sim.observables(spins="all", series=False)
+    assert sorted(obs["walker_at"].tolist()) == list(range(R))
+    for k in range(R):
+        s = obs["spins"][k].reshape(L, L).astype(np.int32)
+        E = -int((s * np.roll(s, 1, axis=0)).sum() + (s * np.roll(s, 1, axis=1)).sum())
+        assert obs["E_slot"][k] == E, k
+        assert obs["M_slot"][k] == int(s.sum()), k
+    assert obs["sweeps_done"] == 3 and obs["exchanges_done"] == 3
+    sim.close()

@@ -5,7 +5,8 @@ linear in [0.30, 0.55], spins drawn from seed 2; E_int and M reduced and
 recorded after every sweep; one replica-exchange step every 10 sweeps.
 A step is one interval of that schedule (10 checkerboard sweeps of all 64
 replicas + their records + one exchange step, i.e. 6.7e8 flip attempts); the
-full run of the workload is 1000 steps (10^4 sweeps).
+full run of the workload is 1000 steps (10^4 sweeps), timed as one pt_run call
+of the whole schedule (the library splits it into launches).
 
 Prints one JSON line: flip attempts/s of the whole job, the roofline of the
 sweep kernel (integer-VALU bound; average launch duration measured live with
@@ -440,7 +441,7 @@ def main():
     # persistent plans and a few launches for the tiled plan
     sweeps_per_step = every * max(1, 10 // every) if every > 0 else 10
     roof_launches = 200
-    total_sweeps = (args.warmup + args.steps + roof_launches) * sweeps_per_step
+    total_sweeps = (args.warmup + args.steps + 10 * roof_launches) * sweeps_per_step
     cfg = pt.Config(w.model, w.L, w.R, w.beta, J=w.J, seed=w.seed, coupling_seed=w.coupling_seed,
                     record_every=w.record_every, max_records=total_sweeps // w.record_every)
     sim = pt.Simulation(cfg, device="cuda:0")
@@ -456,14 +457,14 @@ def main():
     stream = sim.stream
 
     # warmup
-    for _ in range(args.warmup):
-        sim.run(sweeps_per_step, every)
+    sim.run(args.warmup * sweeps_per_step, every)
     torch.cuda.synchronize()
 
-    # timed region: exactly K steps
+    # timed region: exactly K steps, handed to the library as one run of the
+    # schedule (as a user runs a job: the library splits it into launches;
+    # fused and persistent plans run up to 4096 sweeps per launch)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sim.run(sweeps_per_step, every)
+    sim.run(args.steps * sweeps_per_step, every)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     attempts = args.steps * sweeps_per_step * w.attempts_per_sweep
@@ -476,7 +477,7 @@ def main():
         if every:
             per_launch = max(d for d in range(1, per_launch + 1) if every % d == 0)
     else:
-        per_launch = sweeps_per_step  # the whole step runs inside one launch
+        per_launch = 10 * sweeps_per_step  # ten steps inside one launch
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(roof_launches)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(roof_launches)]
     with torch.cuda.stream(stream):

@@ -992,24 +992,33 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
       E += s_red[v][0];
       M += s_red[v][1];
     }
-    if (a.sch.record_every && (s + 1u) % a.sch.record_every == 0u) {
-      if (tid == 0u) {
+    const bool do_rec = a.sch.record_every && (s + 1u) % a.sch.record_every == 0u;
+    const bool do_ex = a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u;
+    if (tid == 0u) {
+      // post this slot's energy first, so the partner's wait does not include
+      // the record stores below
+      uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * R;
+      const uint64_t tag = (uint64_t)(e + 1u) << 32;
+      if (do_ex)
+        __hip_atomic_store(&mb[slot], tag | (uint32_t)E, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (do_rec) {
         a.st.E_series[(size_t)rec * R + slot] = E;
         a.st.M_series[(size_t)rec * R + slot] = M;
       }
-      ++rec;
-    }
-    if (a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u) {
-      if (tid == 0u) {
+      if (do_ex) {
         uint32_t stop = 0u, nslot = slot;
-        uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * R;
-        const uint64_t tag = (uint64_t)(e + 1u) << 32;
-        __hip_atomic_store(&mb[slot], tag | (uint32_t)E, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t par = e & 1u;
         uint32_t partner = 0xFFFFFFFFu;
         if ((slot & 1u) == par && slot + 1u < R) partner = slot + 1u;
         else if ((slot & 1u) != par && slot >= 1u) partner = slot - 1u;
         if (partner != 0xFFFFFFFFu) {
+          // everything that does not need the partner's energy before waiting:
+          // the pair's draw and its table row
+          const uint32_t lo = min(slot, partner);
+          const uint32_t r = philox(lo, e, 0u, kPurposeSwap, a.key.k0, a.key.k1).x;
+          const int32_t D = (int32_t)a.st.swap_D[lo];
+          const uint32_t toff = a.st.swap_off[lo];
+          const uint64_t sat_lo = a.st.swap_sat[2u * lo], sat_hi = a.st.swap_sat[2u * lo + 1u];
           uint64_t v = 0;
           for (uint32_t n = 0;; ++n) {
             v = __hip_atomic_load(&mb[partner], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
@@ -1020,32 +1029,42 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
               stop = 1u;
               break;
             }
-            __builtin_amdgcn_s_sleep(2);
+            __builtin_amdgcn_s_sleep(1);
           }
           if (!stop) {
-            const uint32_t lo = min(slot, partner);
             const int32_t Ep = (int32_t)(uint32_t)v;
             const int32_t Elo = (slot == lo) ? E : Ep, Ehi = (slot == lo) ? Ep : E;
-            const uint32_t r = philox(lo, e, 0u, kPurposeSwap, a.key.k0, a.key.k1).x;
-            const bool accept = (uint64_t)r < swap_T(a.st, lo, Elo - Ehi);
+            const int32_t d = (Elo - Ehi) / 4; // E_int differences are multiples of 4
+            uint64_t T;
+            if (d < -D) T = sat_lo;
+            else if (d > D) T = sat_hi;
+            else {
+              const uint32_t idx = toff + (uint32_t)(d + D);
+              T = idx < a.st.swap_n ? a.st.swap_tab[idx] : 0u; // a valid table always passes
+            }
+            const bool accept = (uint64_t)r < T;
             if (slot == lo) {
               atomicAdd(&a.st.att[lo], 1u);
               if (accept) atomicAdd(&a.st.acc[lo], 1u);
             }
-            if (accept) nslot = partner;
+            if (accept) {
+              nslot = partner;
+              // every lane is waiting at the barrier below: the lookup row
+              // can be replaced here, no second barrier needed
+              for (uint32_t q = 0; q < kClasses; ++q) s_thr[q] = thr[nslot * kClasses + q];
+            }
           }
         }
         s_slot = nslot;
         s_stop = stop;
       }
+    }
+    if (do_rec) ++rec;
+    if (do_ex) {
       ++e;
       __syncthreads();
       if (s_stop) break;
-      if (s_slot != slot) {
-        slot = s_slot;
-        if (tid < kClasses) s_thr[tid] = thr[slot * kClasses + tid];
-      }
-      __syncthreads();
+      slot = s_slot;
     }
   }
   pack_tile(a.spins + (size_t)w * (N >> 5), sp, N >> 5, tid, nt);

@@ -32,8 +32,9 @@
  *     slot w.
  *
  * Threading: one context must not be used from two host threads at once;
- * distinct contexts may run concurrently on distinct streams.  All calls
- * except pt_observables are asynchronous on the context's stream.
+ * distinct contexts may run concurrently on distinct streams.  pt_create and
+ * pt_observables synchronise the context's stream; the other calls only queue
+ * work on it.
  *
  * Errors: every pt_status function returns PT_OK (0) or a negative code and
  * never throws.  Configuration errors are detected synchronously (PT_EINVAL).

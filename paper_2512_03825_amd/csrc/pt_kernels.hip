@@ -2,9 +2,9 @@
 //
 // Lattices live bit-packed in HBM (bit set = down spin) and are unpacked into
 // LDS for updating.  Two LDS layouts:
-//   - four bits per site (2D tiled and batched kernels): a row of L sites is
-//     L/8 dwords, one dword per group of 8 sites;
-//   - one byte per site (3D kernels, and the fused and persistent kernels): a
+//   - four bits per site (2D tiled and batched kernels, the persistent kernel):
+//     a row of L sites is L/8 dwords, one dword per group of 8 sites;
+//   - one byte per site (3D tiled and batched kernels, the fused kernel): a
 //     row is L/8 groups of 8 bytes.
 // Either way a value of 0 is an up spin (s = +1) and 1 a down spin, so the
 // number of unsatisfied bonds of a site is a nibble- or byte-wise sum of
@@ -51,6 +51,11 @@ constexpr int kMaxThreads = 1024;
 #endif
 // Groups (dwords) one lane updates per item in the 2D nibble-layout kernel.
 constexpr uint32_t kNibbleSpan = PT_NIBBLE_SPAN;
+#ifndef PT_PERSIST_SPAN
+#define PT_PERSIST_SPAN 4
+#endif
+// Groups (dwords) per item in the persistent kernel.
+constexpr uint32_t kPersistSpan = PT_PERSIST_SPAN;
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -632,6 +637,28 @@ struct TallyN {
   uint32_t n, sb, sc;
 };
 
+// Metropolis decision for the four colour sites of one dword (nibble layout):
+// w = spins, u = unsatisfied-bond counts per nibble, r = the group's draws.
+// Returns the new spins and adds the accepted flips to the tallies.
+__device__ __forceinline__ uint32_t decide_n(uint32_t w, uint32_t u, uint32_t off, const Words &r,
+                                             const uint8_t *tb, TallyN &t) {
+  const uint32_t M = off ? 0xF0F0F0F0u : 0x0F0F0F0Fu;   // colour nibbles
+  const uint32_t rot = off ? 2u : 30u;                  // class * 4 to bits 8m .. 8m+5
+  const uint32_t b0 = 1u << (4u * off);
+  const uint32_t cls = ((w << 3) | u) & M;              // 8b + u in each colour nibble
+  const uint32_t c4 = __builtin_amdgcn_alignbit(cls, cls, rot);
+  const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tb + (c4 & 63u));
+  const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 8u, 6u));
+  const uint32_t t2 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 16u, 6u));
+  const uint32_t t3 = *reinterpret_cast<const uint32_t *>(tb + (c4 >> 24));
+  const uint32_t f = (r.x <= t0 ? b0 : 0u) | (r.y <= t1 ? (b0 << 8) : 0u) |
+                     (r.z <= t2 ? (b0 << 16) : 0u) | (r.w <= t3 ? (b0 << 24) : 0u);
+  t.n += __builtin_popcount(f);
+  t.sb = __builtin_amdgcn_udot8(w, f, t.sb, false);
+  t.sc = __builtin_amdgcn_udot8(cls, f, t.sc, false);
+  return w ^ f;
+}
+
 // 2D Ising, nibble layout: update the colour sites of the V groups (dwords)
 // g0 .. g0+V-1 of one row.
 template <int V>
@@ -645,9 +672,6 @@ __device__ __forceinline__ void span2d_n(uint32_t *row, const uint32_t *up, cons
   // the neighbouring dword on the side the colour sites need: left for off = 0
   // (nibble 0's left neighbour), right for off = 1 (nibble 7's right neighbour)
   const uint32_t e = row[off ? ((g0 + V) & gmask) : ((g0 + gmask) & gmask)];
-  const uint32_t M = off ? 0xF0F0F0F0u : 0x0F0F0F0Fu;   // colour nibbles
-  const uint32_t rot = off ? 2u : 30u;                  // class * 4 to bits 8m .. 8m+5
-  const uint32_t b0 = 1u << (4u * off);
   const uint8_t *tb = reinterpret_cast<const uint8_t *>(thr);
 #pragma unroll
   for (int v = 0; v < V; ++v) {
@@ -657,20 +681,55 @@ __device__ __forceinline__ void span2d_n(uint32_t *row, const uint32_t *up, cons
     u = xad(l, w[v], u);
     u = xad(b[v], w[v], u);
     u = xad(a[v], w[v], u);
-    const uint32_t cls = ((w[v] << 3) | u) & M;         // 8b + u in each colour nibble
-    const uint32_t c4 = __builtin_amdgcn_alignbit(cls, cls, rot);
-    const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tb + (c4 & 63u));
-    const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 8u, 6u));
-    const uint32_t t2 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 16u, 6u));
-    const uint32_t t3 = *reinterpret_cast<const uint32_t *>(tb + (c4 >> 24));
-    const uint32_t f = (r[v].x <= t0 ? b0 : 0u) | (r[v].y <= t1 ? (b0 << 8) : 0u) |
-                       (r[v].z <= t2 ? (b0 << 16) : 0u) | (r[v].w <= t3 ? (b0 << 24) : 0u);
-    t.n += __builtin_popcount(f);
-    t.sb = __builtin_amdgcn_udot8(w[v], f, t.sb, false);
-    t.sc = __builtin_amdgcn_udot8(cls, f, t.sc, false);
-    nw[v] = w[v] ^ f;
+    nw[v] = decide_n(w[v], u, off, r[v], tb, t);
   }
   lds_store_n<V>(row + g0, nw);
+}
+
+// 3D +-J EA, nibble layout: spins and the three bond planes (bond (i, i+e_d)
+// at site i, bit set = J -1) are dword arrays with plane p, row y at dword
+// (p << lgPl) + (y << lgG).  Updates the colour sites of V dwords g0.. of row
+// y of plane pl; a bond is unsatisfied iff s_i ^ s_j ^ J_ij = 1.
+template <int V>
+__device__ __forceinline__ void span3d_n(uint32_t *sp, const uint32_t *bx, const uint32_t *by,
+                                         const uint32_t *bz, uint32_t lgG, uint32_t lgPl,
+                                         uint32_t pl, uint32_t pu, uint32_t pd, uint32_t y,
+                                         uint32_t yu, uint32_t yd, uint32_t g0, uint32_t gmask,
+                                         uint32_t off, const Words (&r)[V], const uint32_t *thr,
+                                         TallyN &t) {
+  const uint32_t rowb = (pl << lgPl) + (y << lgG);
+  uint32_t w[V], jx[V], u[V], nw[V];
+  lds_load_n<V>(w, sp + rowb + g0);
+  lds_load_n<V>(jx, bx + rowb + g0);
+  const uint32_t eg = rowb + (off ? ((g0 + V) & gmask) : ((g0 + gmask) & gmask));
+  const uint32_t es = sp[eg];
+  const uint32_t ej = off ? 0u : bx[eg];   // +x bond of the left neighbour (off = 0 only)
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const uint32_t l = __builtin_amdgcn_alignbit(w[v], v ? w[v - 1] : es, 28u);
+    const uint32_t lj = __builtin_amdgcn_alignbit(jx[v], v ? jx[v - 1] : ej, 28u);
+    const uint32_t rr = __builtin_amdgcn_alignbit(v < V - 1 ? w[v + 1] : es, w[v], 4u);
+    u[v] = xor3(l, w[v], lj) + xor3(rr, w[v], jx[v]);
+  }
+  {
+    uint32_t s0[V], s1[V], j0[V], j1[V];
+    lds_load_n<V>(s0, sp + (pl << lgPl) + (yu << lgG) + g0);   // row y-1
+    lds_load_n<V>(s1, sp + (pl << lgPl) + (yd << lgG) + g0);   // row y+1
+    lds_load_n<V>(j0, by + (pl << lgPl) + (yu << lgG) + g0);   // its +y bond to us
+    lds_load_n<V>(j1, by + rowb + g0);
+#pragma unroll
+    for (int v = 0; v < V; ++v) u[v] += xor3(s0[v], w[v], j0[v]) + xor3(s1[v], w[v], j1[v]);
+    lds_load_n<V>(s0, sp + (pu << lgPl) + (y << lgG) + g0);    // plane z-1
+    lds_load_n<V>(s1, sp + (pd << lgPl) + (y << lgG) + g0);    // plane z+1
+    lds_load_n<V>(j0, bz + (pu << lgPl) + (y << lgG) + g0);
+    lds_load_n<V>(j1, bz + rowb + g0);
+#pragma unroll
+    for (int v = 0; v < V; ++v) u[v] += xor3(s0[v], w[v], j0[v]) + xor3(s1[v], w[v], j1[v]);
+  }
+  const uint8_t *tb = reinterpret_cast<const uint8_t *>(thr);
+#pragma unroll
+  for (int v = 0; v < V; ++v) nw[v] = decide_n(w[v], u[v], off, r[v], tb, t);
+  lds_store_n<V>(sp + rowb + g0, nw);
 }
 
 template <int V>
@@ -936,20 +995,22 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
   __shared__ uint32_t s_slot, s_stop;
   const Geometry &G = a.geo;
   const uint32_t R = G.R, N = G.N, L = G.L, lgL = a.lg_L;
-  const uint32_t lgP = (DIM == 3 ? 2u : 1u) * lgL;
+  const uint32_t lgG = lgL - 3u, gmask = (1u << lgG) - 1u;   // dwords per row
+  const uint32_t lgPl = (DIM == 3 ? lgL : 0u) + lgG;          // dwords per plane (3D)
   const uint32_t tid = threadIdx.x, nt = blockDim.x, w = blockIdx.x;
-  uint8_t *sp = smem;
-  uint8_t *bx = smem + N, *by = bx + N, *bz = by + N;
+  // four bits per site: spins, then (3D) the x, y, z bond planes, N/8 dwords each
+  uint32_t *sp = reinterpret_cast<uint32_t *>(smem);
+  uint32_t *bx = sp + (N >> 3), *by = bx + (N >> 3), *bz = by + (N >> 3);
   // every slot's thresholds stay in LDS, so a slot change never waits on memory;
   // the current slot's row is copied to a fixed LDS address for the lookups
-  uint32_t *thr = reinterpret_cast<uint32_t *>(smem + (size_t)N * (DIM == 3 ? 4u : 1u));
+  uint32_t *thr = sp + (N >> 3) * (DIM == 3 ? 4u : 1u);
   for (uint32_t q = tid; q < R * kClasses; q += nt) thr[q] = a.st.flip_thr[q];
 
   uint32_t slot = a.st.slot_of[w];
   int32_t E = a.st.E[w], M = a.st.M[w];
   if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
-  unpack_tile(sp, a.spins + (size_t)w * (N >> 5), 0u, N >> 5, 0xFFFFFFFFu, tid, nt);
-  if (DIM == 3) unpack_tile(bx, a.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
+  unpack_tile_n(sp, a.spins + (size_t)w * (N >> 5), 0u, N >> 5, 0xFFFFFFFFu, tid, nt);
+  if (DIM == 3) unpack_tile_n(bx, a.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
   __syncthreads();
 
   const uint32_t smask = (1u << a.lg_spr) - 1u, rmask = G.rows - 1u;
@@ -958,7 +1019,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
   uint32_t rec = a.sch.rec_base, e = a.sch.ex_step;
   for (uint32_t j = 0; j < a.sch.nsw; ++j) {
     const uint32_t s = a.sch.s0 + j;
-    Tally t = {0, 0, 0};
+    TallyN t = {0u, 0u, 0u};
     for (uint32_t c = 0; c < 2u; ++c) {
       for (uint32_t q = tid; q < items; q += nt) {
         const uint32_t g0 = (q & smask) * V;
@@ -967,20 +1028,22 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
         const uint32_t pu = (pl + L - 1u) & (L - 1u);
         const uint32_t pd = (pl + 1u) & (L - 1u);
         const uint32_t off = (c + pl + (DIM == 3 ? y : 0u)) & 1u;
-        const uint32_t ctr0 = (((pl << a.lg_rows) + y) << (lgL - 3u)) + g0;
+        const uint32_t ctr0 = (((pl << a.lg_rows) + y) << lgG) + g0;
         Words r[V];
 #pragma unroll
         for (int v = 0; v < V; ++v)
           r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
-        if (DIM == 2)
-          span2d<V>(sp + (pl << lgP), sp + (pu << lgP), sp + (pd << lgP), g0, L, off, r, s_thr, t);
+        if constexpr (DIM == 2)
+          span2d_n<V>(sp + (pl << lgG), sp + (pu << lgG), sp + (pd << lgG), g0, gmask, off, r,
+                      s_thr, t);
         else
-          span3d<V>(sp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, s_thr, t);
+          span3d_n<V>(sp, bx, by, bz, lgG, lgPl, pl, pu, pd, y, (y + L - 1u) & (L - 1u),
+                      (y + 1u) & (L - 1u), g0, gmask, off, r, s_thr, t);
       }
       __syncthreads();
     }
     // this walker's energy and magnetisation change over the sweep
-    int dE = a.z2 * t.n - (t.sc - 32 * t.sb), dM = 4 * t.sb - 2 * t.n;
+    int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb), dM = 4 * (int)t.sb - 2 * (int)t.n;
     dE = wave_sum(dE);
     dM = wave_sum(dM);
     if ((tid & 63u) == 0u) {
@@ -1067,7 +1130,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
       slot = s_slot;
     }
   }
-  pack_tile(a.spins + (size_t)w * (N >> 5), sp, N >> 5, tid, nt);
+  pack_tile_n(a.spins + (size_t)w * (N >> 5), sp, N >> 5, tid, nt);
   if (tid == 0u) {
     a.st.E[w] = E;
     a.st.M[w] = M;
@@ -1629,13 +1692,14 @@ size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo) {
 size_t fused_lds_bytes(const Geometry &g) { return fused_layout(g.R, g.N, g.dim).total; }
 
 size_t persist_lds_bytes(const Geometry &g) {
-  return (size_t)g.N * (g.dim == 3 ? 4u : 1u) + (size_t)g.R * kClasses * 4u;
+  return (size_t)g.N / 2u * (g.dim == 3 ? 4u : 1u) + (size_t)g.R * kClasses * 4u; // four bits per site
 }
 
 uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads) {
-  const uint32_t V = span_groups(g);
-  const void *fn = g.dim == 3 ? (V == 2 ? reinterpret_cast<const void *>(k_persist<3, 2>)
-                                        : reinterpret_cast<const void *>(k_persist<3, 1>))
+  const uint32_t V = std::min<uint32_t>(kPersistSpan, g.gpr);
+  const void *fn = g.dim == 3 ? (V == 4   ? reinterpret_cast<const void *>(k_persist<3, 4>)
+                                 : V == 2 ? reinterpret_cast<const void *>(k_persist<3, 2>)
+                                          : reinterpret_cast<const void *>(k_persist<3, 1>))
                  : V == 4 ? reinterpret_cast<const void *>(k_persist<2, 4>)
                  : V == 2 ? reinterpret_cast<const void *>(k_persist<2, 2>)
                           : reinterpret_cast<const void *>(k_persist<2, 1>);
@@ -1778,7 +1842,7 @@ hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, 
   a.key = k;
   a.sch = sch;
   a.spins = st.spins[cur];
-  const uint32_t V = span_groups(g);
+  const uint32_t V = std::min<uint32_t>(kPersistSpan, g.gpr);
   a.lg_L = ilog2(g.L);
   a.lg_spr = ilog2(g.gpr / V);
   a.lg_rows = ilog2(g.rows);
@@ -1787,8 +1851,9 @@ hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, 
   a.spin_limit = spin_limit;
   const size_t lds = persist_lds_bytes(g);
   if (g.dim == 3)
-    return V == 2 ? launch_persist_v<3, 2>(a, g.R, threads, lds, stream)
-                  : launch_persist_v<3, 1>(a, g.R, threads, lds, stream);
+    return V == 4   ? launch_persist_v<3, 4>(a, g.R, threads, lds, stream)
+           : V == 2 ? launch_persist_v<3, 2>(a, g.R, threads, lds, stream)
+                    : launch_persist_v<3, 1>(a, g.R, threads, lds, stream);
   return V == 4 ? launch_persist_v<2, 4>(a, g.R, threads, lds, stream)
        : V == 2 ? launch_persist_v<2, 2>(a, g.R, threads, lds, stream)
                 : launch_persist_v<2, 1>(a, g.R, threads, lds, stream);

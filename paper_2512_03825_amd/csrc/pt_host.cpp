@@ -281,8 +281,10 @@ pt_plan auto_plan(const pt_ctx *c) {
   const Geometry &g = c->d.geo;
   pt_plan p{};
   const size_t fused = fused_lds_bytes(g);
-  if (fused <= 64u * 1024u) {
-    // Everything fits one workgroup: sweeps and exchanges never leave the kernel.
+  const size_t work = (size_t)g.R * g.N * (g.dim == 3 ? 4u : 1u); // one workgroup's sites (EA: x4)
+  if (fused <= 64u * 1024u && work <= 60u * 1024u) {
+    // Small enough that one workgroup is the fastest: sweeps and exchanges
+    // never leave the kernel.
     const uint32_t items = (g.R * g.N) / (8u * span_groups(g));
     p.mode = PT_PLAN_FUSED;
     p.block_threads = std::min<uint32_t>(1024u, std::max<uint32_t>(64u, (items + 63u) & ~63u));

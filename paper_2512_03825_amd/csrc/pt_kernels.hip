@@ -1,23 +1,21 @@
 // pt_kernels.hip -- gfx950 kernels of the parallel-tempering Metropolis library.
 //
 // Lattices live bit-packed in HBM (bit set = down spin) and are unpacked into
-// LDS for updating.  Two LDS layouts:
-//   - four bits per site (2D tiled and batched kernels, the persistent kernel):
-//     a row of L sites is L/8 dwords, one dword per group of 8 sites;
-//   - one byte per site (3D tiled and batched kernels, the fused kernel): a
-//     row is L/8 groups of 8 bytes.
-// Either way a value of 0 is an up spin (s = +1) and 1 a down spin, so the
-// number of unsatisfied bonds of a site is a nibble- or byte-wise sum of
-// XORs with its neighbours (SWAR).  In a group the four sites of the colour
-// being updated sit at positions off, off+2, off+4, off+6 (off = colour parity
-// of the row) and consume the four words of one Philox4x32-10 block whose
-// counter is the group's index: the draw of site i is word (i/2) mod 4 of
-// block (i/2)/4, as the method's draw mapping fixes.
+// LDS at four bits per site: a row of L sites is L/8 dwords, one dword per
+// group of 8 sites (EA bonds: three more such arrays, bond (i, i+e_d) at site
+// i).  A value of 0 is an up spin (s = +1) and 1 a down spin, so the number of
+// unsatisfied bonds of a site is a nibble-wise sum of XORs with its neighbours
+// (at most 6, no carries between nibbles).  In a group the four sites of the
+// colour being updated sit at nibbles off, off+2, off+4, off+6 (off = colour
+// parity of the row) and consume the four words of one Philox4x32-10 block
+// whose counter is the group's index: the draw of site i is word (i/2) mod 4
+// of block (i/2)/4, as the method's draw mapping fixes.
 //
-// Work of one group: the neighbour words from LDS, a SWAR count of unsatisfied
-// bonds, one Philox block (18 vector 64-bit multiplies + 20 three-way XORs),
-// four LDS threshold lookups and compares, one store, and the exact integer
-// energy / magnetisation change of the accepted flips (dot-product tallies).
+// Work of one group: the neighbour dwords from LDS, a SWAR count of
+// unsatisfied bonds, one Philox block (18 vector 64-bit multiplies + 20
+// three-way XORs), four LDS threshold lookups and compares, one store, and the
+// exact integer energy / magnetisation change of the accepted flips (v_dot8
+// tallies over nibbles).
 //
 // Kernels:
 //   k_tiled_n      2D, grid (tiles, walkers).  A workgroup stages one tile of
@@ -46,16 +44,10 @@ namespace ptmi {
 namespace {
 
 constexpr int kMaxThreads = 1024;
-#ifndef PT_NIBBLE_SPAN
-#define PT_NIBBLE_SPAN 8
-#endif
-// Groups (dwords) one lane updates per item in the 2D nibble-layout kernel.
-constexpr uint32_t kNibbleSpan = PT_NIBBLE_SPAN;
-#ifndef PT_PERSIST_SPAN
-#define PT_PERSIST_SPAN 4
-#endif
-// Groups (dwords) per item in the persistent kernel.
-constexpr uint32_t kPersistSpan = PT_PERSIST_SPAN;
+// Groups (dwords) one lane updates per item: the 2D tiled kernel (chosen by
+// measurement among 2, 4, 8) and the persistent kernel (among 2, 4).
+constexpr uint32_t kNibbleSpan = 8;
+constexpr uint32_t kPersistSpan = 4;
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -90,171 +82,6 @@ __device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     k1 += 0xBB67AE85u;
   }
   return {c0, c1, c2, c3};
-}
-
-// LDS span of V consecutive 8-byte groups (2V dwords), 8V-byte aligned.
-template <int V>
-__device__ __forceinline__ void lds_load(uint32_t (&d)[2 * V], const uint8_t *p) {
-  if constexpr (V == 1) {
-    const uint2 a = *reinterpret_cast<const uint2 *>(p);
-    d[0] = a.x;
-    d[1] = a.y;
-  } else {
-#pragma unroll
-    for (int i = 0; i < V / 2; ++i) {
-      const uint4 a = reinterpret_cast<const uint4 *>(p)[i];
-      d[4 * i] = a.x;
-      d[4 * i + 1] = a.y;
-      d[4 * i + 2] = a.z;
-      d[4 * i + 3] = a.w;
-    }
-  }
-}
-template <int V>
-__device__ __forceinline__ void lds_store(uint8_t *p, const uint32_t (&d)[2 * V]) {
-  if constexpr (V == 1) {
-    *reinterpret_cast<uint2 *>(p) = make_uint2(d[0], d[1]);
-  } else {
-#pragma unroll
-    for (int i = 0; i < V / 2; ++i)
-      reinterpret_cast<uint4 *>(p)[i] = make_uint4(d[4 * i], d[4 * i + 1], d[4 * i + 2], d[4 * i + 3]);
-  }
-}
-
-// Per-lane tallies of accepted flips: n = count, sb = sum of b (down spins
-// flipped up), sc = 4 x sum of class index 8b+u.  Energy change of the tally:
-// dE_int = 2z n - (sc - 32 sb), magnetisation change dM = 4 sb - 2 n.
-struct Tally {
-  int n, sb, sc;
-};
-
-// Metropolis decision for the four colour sites of a group.  wlo/whi: the
-// group's 8 spin bytes; ulo/uhi: per-byte unsatisfied-bond counts (valid at
-// the colour bytes, which sit at bit offsets sh and sh+16 of each dword,
-// sh = 8*off); b0 = 1 << sh, b1 = 1 << (sh+16); r: the group's four draws.
-// Writes the new spin bytes.
-__device__ __forceinline__ void decide(uint32_t wlo, uint32_t whi, uint32_t ulo, uint32_t uhi,
-                                       uint32_t sh, uint32_t b0, uint32_t b1, const Words &r,
-                                       const uint32_t *thr, Tally &t, uint32_t &nlo,
-                                       uint32_t &nhi) {
-  // 4*(8b+u) per byte (<= 56): the byte offset of the class threshold
-  const uint32_t clo = (wlo << 5) | (ulo << 2);
-  const uint32_t chi = (whi << 5) | (uhi << 2);
-  const uint8_t *tb = reinterpret_cast<const uint8_t *>(thr);
-  const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(clo, sh, 6));
-  const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(clo, sh + 16u, 6));
-  const uint32_t t2 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(chi, sh, 6));
-  const uint32_t t3 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(chi, sh + 16u, 6));
-  const uint32_t flo = (r.x <= t0 ? b0 : 0u) | (r.y <= t1 ? b1 : 0u);
-  const uint32_t fhi = (r.z <= t2 ? b0 : 0u) | (r.w <= t3 ? b1 : 0u);
-  t.n = (int)__builtin_amdgcn_udot4(flo + fhi, 0x01010101u, (uint32_t)t.n, false);
-  t.sb = (int)__builtin_amdgcn_udot4(wlo, flo, (uint32_t)t.sb, false);
-  t.sb = (int)__builtin_amdgcn_udot4(whi, fhi, (uint32_t)t.sb, false);
-  t.sc = (int)__builtin_amdgcn_udot4(clo, flo, (uint32_t)t.sc, false);
-  t.sc = (int)__builtin_amdgcn_udot4(chi, fhi, (uint32_t)t.sc, false);
-  nlo = wlo ^ flo;
-  nhi = whi ^ fhi;
-}
-
-// Byte index within the row of the edge site a span of V groups starting at
-// group g0 needs: left of the span for off = 0, right of it for off = 1.
-template <int V>
-__device__ __forceinline__ uint32_t edge_index(uint32_t g0, uint32_t off, uint32_t L) {
-  return off ? ((8u * (g0 + V)) & (L - 1u)) : ((8u * g0 + L - 1u) & (L - 1u));
-}
-
-// Left / right neighbour words of dword j of a span (0/1 bytes), with the
-// edge byte e0 entering on the left (off = 0) or e1 on the right (off = 1).
-template <int V>
-__device__ __forceinline__ uint32_t left_of(const uint32_t (&w)[2 * V], int j, uint32_t e0) {
-  return j ? __builtin_amdgcn_alignbyte(w[j], w[j - 1], 3) : ((w[0] << 8) | e0);
-}
-template <int V>
-__device__ __forceinline__ uint32_t right_of(const uint32_t (&w)[2 * V], int j, uint32_t e1) {
-  return (j < 2 * V - 1) ? __builtin_amdgcn_alignbyte(w[j + 1], w[j], 1) : ((w[2 * V - 1] >> 8) | (e1 << 24));
-}
-
-// 2D Ising: update the colour sites of V consecutive groups of one row.
-template <int V>
-__device__ __forceinline__ void span2d(uint8_t *row, const uint8_t *up, const uint8_t *dn,
-                                       uint32_t g0, uint32_t L, uint32_t off,
-                                       const Words (&r)[V], const uint32_t *thr, Tally &t) {
-  uint32_t w[2 * V], a[2 * V], b[2 * V], nw[2 * V];
-  const uint32_t o = 8u * g0;
-  lds_load<V>(w, row + o);
-  lds_load<V>(a, up + o);
-  lds_load<V>(b, dn + o);
-  const uint32_t e = row[edge_index<V>(g0, off, L)];
-  const uint32_t e0 = off ? 0u : e, e1 = off ? e : 0u;
-  const uint32_t sh = off << 3, b0 = 1u << sh, b1 = 0x10000u << sh;
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    uint32_t cnt[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int j = 2 * v + h;
-      // a chain of fused XOR+ADDs: one XOR and three v_xad_u32
-      uint32_t u = right_of<V>(w, j, e1) ^ w[j];
-      u = xad(left_of<V>(w, j, e0), w[j], u);
-      u = xad(b[j], w[j], u);
-      cnt[h] = xad(a[j], w[j], u);
-    }
-    decide(w[2 * v], w[2 * v + 1], cnt[0], cnt[1], sh, b0, b1, r[v], thr, t, nw[2 * v],
-           nw[2 * v + 1]);
-  }
-  lds_store<V>(row + o, nw);
-}
-
-// 3D +-J EA: update the colour sites of V consecutive groups of row y of plane
-// pl.  Spin and bond planes share one LDS plane indexing: plane p of spins at
-// sp + (p << lgP), of x/y/z bonds at bx/by/bz + (p << lgP).
-template <int V>
-__device__ __forceinline__ void span3d(uint8_t *sp, const uint8_t *bx, const uint8_t *by,
-                                       const uint8_t *bz, uint32_t lgL, uint32_t pl, uint32_t pu,
-                                       uint32_t pd, uint32_t y, uint32_t g0, uint32_t L,
-                                       uint32_t off, const Words (&r)[V], const uint32_t *thr,
-                                       Tally &t) {
-  const uint32_t lgP = 2u * lgL;
-  const uint32_t yu = (y + L - 1u) & (L - 1u), yd = (y + 1u) & (L - 1u);
-  const uint32_t rowb = (pl << lgP) + (y << lgL);
-  const uint32_t o = rowb + 8u * g0;                          // this span
-  const uint32_t oyu = (pl << lgP) + (yu << lgL) + 8u * g0;   // row y-1
-  const uint32_t oyd = (pl << lgP) + (yd << lgL) + 8u * g0;   // row y+1
-  const uint32_t ozu = (pu << lgP) + (y << lgL) + 8u * g0;    // plane z-1
-  const uint32_t ozd = (pd << lgP) + (y << lgL) + 8u * g0;    // plane z+1
-  uint32_t w[2 * V], jx[2 * V], nw[2 * V];
-  lds_load<V>(w, sp + o);
-  lds_load<V>(jx, bx + o);                                    // bonds to x+1
-  const uint32_t ei = rowb + edge_index<V>(g0, off, L);
-  const uint32_t e = sp[ei];
-  const uint32_t ej = off ? 0u : (uint32_t)bx[ei];            // bond from the left edge site
-  const uint32_t e0 = off ? 0u : e, e1 = off ? e : 0u;
-  uint32_t cnt[2 * V];
-#pragma unroll
-  for (int j = 0; j < 2 * V; ++j)
-    cnt[j] = xor3(left_of<V>(w, j, e0), w[j], left_of<V>(jx, j, ej)) +
-             xor3(right_of<V>(w, j, e1), w[j], jx[j]);
-  {
-    uint32_t s0[2 * V], s1[2 * V], j0[2 * V], j1[2 * V];
-    lds_load<V>(s0, sp + oyu);
-    lds_load<V>(s1, sp + oyd);
-    lds_load<V>(j0, by + oyu);
-    lds_load<V>(j1, by + o);
-#pragma unroll
-    for (int j = 0; j < 2 * V; ++j) cnt[j] += xor3(s0[j], w[j], j0[j]) + xor3(s1[j], w[j], j1[j]);
-    lds_load<V>(s0, sp + ozu);
-    lds_load<V>(s1, sp + ozd);
-    lds_load<V>(j0, bz + ozu);
-    lds_load<V>(j1, bz + o);
-#pragma unroll
-    for (int j = 0; j < 2 * V; ++j) cnt[j] += xor3(s0[j], w[j], j0[j]) + xor3(s1[j], w[j], j1[j]);
-  }
-  const uint32_t sh = off << 3, b0 = 1u << sh, b1 = 0x10000u << sh;
-#pragma unroll
-  for (int v = 0; v < V; ++v)
-    decide(w[2 * v], w[2 * v + 1], cnt[2 * v], cnt[2 * v + 1], sh, b0, b1, r[v], thr, t,
-           nw[2 * v], nw[2 * v + 1]);
-  lds_store<V>(sp + o, nw);
 }
 
 __device__ __forceinline__ int wave_sum(int v) {
@@ -332,58 +159,6 @@ struct TiledArgs {
   int32_t z2;      // 2 * coordination number (8 in 2D, 12 in 3D)
 };
 
-// Global lattices are bit-packed (bit j of word q = site 32q + j); LDS holds
-// one byte per site.  unpack32 spreads a word to 32 bytes, pack32 gathers them.
-__device__ __forceinline__ void unpack32(uint32_t w, uint32_t (&d)[8]) {
-#pragma unroll
-  for (int j = 0; j < 8; ++j)
-    d[j] = __umul24(__builtin_amdgcn_ubfe(w, 4u * j, 4u), 0x00204081u) & 0x01010101u;
-}
-__device__ __forceinline__ uint32_t pack32(const uint32_t (&d)[8]) {
-  uint32_t b[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-    b[j] = __builtin_amdgcn_udot4(d[2 * j + 1], 0x80402010u,
-                                  __builtin_amdgcn_udot4(d[2 * j], 0x08040201u, 0u, false), false);
-  return b[0] | (b[1] << 8) | (b[2] << 16) | (b[3] << 24);
-}
-
-// LDS bytes [0, 32 cnt) <- unpacked words src[(f + q) & m], q < cnt.
-__device__ __forceinline__ void unpack_tile(uint8_t *lds, const uint32_t *src, uint32_t f,
-                                            uint32_t cnt, uint32_t m, uint32_t tid, uint32_t nt) {
-  constexpr uint32_t kBatch = 4;
-  for (uint32_t q0 = tid; q0 < cnt; q0 += kBatch * nt) {
-    uint32_t w[kBatch];
-#pragma unroll
-    for (uint32_t j = 0; j < kBatch; ++j) {
-      const uint32_t q = q0 + j * nt;
-      w[j] = (q < cnt) ? src[(f + q) & m] : 0u;
-    }
-#pragma unroll
-    for (uint32_t j = 0; j < kBatch; ++j) {
-      const uint32_t q = q0 + j * nt;
-      if (q < cnt) {
-        uint32_t d[8];
-        unpack32(w[j], d);
-        uint4 *p = reinterpret_cast<uint4 *>(lds + 32u * q);
-        p[0] = make_uint4(d[0], d[1], d[2], d[3]);
-        p[1] = make_uint4(d[4], d[5], d[6], d[7]);
-      }
-    }
-  }
-}
-
-// dst[q] <- packed LDS bytes [32q, 32q + 32), q < cnt.
-__device__ __forceinline__ void pack_tile(uint32_t *dst, const uint8_t *lds, uint32_t cnt,
-                                          uint32_t tid, uint32_t nt) {
-  for (uint32_t q = tid; q < cnt; q += nt) {
-    const uint4 *p = reinterpret_cast<const uint4 *>(lds + 32u * q);
-    const uint4 x = p[0], y = p[1];
-    const uint32_t d[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
-    dst[q] = pack32(d);
-  }
-}
-
 // The last workgroup of a tiled launch to arrive folds the per-sweep energy
 // and magnetisation changes into E and M, writes the records, and runs the
 // exchange step; it then re-arms the arrival counter.
@@ -433,120 +208,11 @@ __device__ void tiled_epilogue(const TiledArgs &a, uint32_t tid, uint32_t nt, ui
 }
 
 
-template <int DIM, int V>
-__global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
-  static_assert(DIM == 3, "2D lattices use the four-bit layout of k_tiled_n");
-  extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ uint32_t s_thr[kClasses];
-  __shared__ int s_red[kMaxThreads / 64][2];
-  __shared__ uint32_t s_last;
 
-  const Geometry &G = a.geo;
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t tile = blockIdx.x, w = blockIdx.y;
-  const uint32_t L = G.L, lgL = a.lg_L;
-  const uint32_t lgP = (DIM == 3 ? 2u : 1u) * lgL;     // bytes per plane = 2^lgP
-  const uint32_t y0 = tile * a.H;
-  const uint32_t Ht = min(a.H, L - y0);
-  const uint32_t halo = a.halo;
-  const uint32_t np = Ht + 2u * halo;                  // LDS planes
-  const uint32_t base = (y0 + L - halo) & (L - 1u);   // global plane of LDS plane 0
-  const uint32_t slot = a.st.slot_of[w];
-  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
-
-  uint8_t *sp = smem;
-  uint8_t *bx = smem + ((size_t)np << lgP);
-  uint8_t *by = bx + ((size_t)np << lgP);
-  uint8_t *bz = by + ((size_t)np << lgP);
-
-  // Stage planes [base, base+np) mod L of this walker (and the bonds) in LDS,
-  // one byte per site.  Halo tiles have planes of a multiple of 32 sites.
-  {
-    const uint32_t nwr = G.N >> 5, first = (base << lgP) >> 5, cnt = (np << lgP) >> 5;
-    unpack_tile(sp, a.src + (size_t)w * nwr, first, cnt, nwr - 1u, tid, nt);
-    if (DIM == 3) {
-      unpack_tile(bx, a.st.bonds, first, cnt, nwr - 1u, tid, nt);
-      unpack_tile(by, a.st.bonds + nwr, first, cnt, nwr - 1u, tid, nt);
-      unpack_tile(bz, a.st.bonds + 2u * nwr, first, cnt, nwr - 1u, tid, nt);
-    }
-  }
-  __syncthreads();
-
-  const uint32_t smask = (1u << a.lg_spr) - 1u, rmask = G.rows - 1u;
-  const uint32_t shp = a.lg_spr + a.lg_rows;
-  Tally t = {0, 0, 0};
-  for (uint32_t hs = 0; hs < 2u * a.sch.nsw; ++hs) {
-    const uint32_t c = hs & 1u;
-    const uint32_t s = a.sch.s0 + (hs >> 1);
-    const uint32_t ext = halo ? (halo - 1u - hs) : 0u;
-    const uint32_t plo = halo - ext;                 // computed LDS planes [plo, plo+Ht+2ext)
-    // One item: VV consecutive groups of row y of LDS plane pl.
-    auto item = [&](auto vtag, uint32_t pl, uint32_t y, uint32_t g0, bool interior) {
-      constexpr int VV = decltype(vtag)::value;
-      const uint32_t pu = (pl == 0u) ? np - 1u : pl - 1u;
-      const uint32_t pd = (pl + 1u == np) ? 0u : pl + 1u;
-      const uint32_t gp = (base + pl) & (L - 1u);   // global plane coordinate
-      const uint32_t off = (c + gp + (DIM == 3 ? y : 0u)) & 1u;
-      const uint32_t ctr0 = (((gp << a.lg_rows) + y) << (lgL - 3u)) + g0;
-      Words r[VV];
-#pragma unroll
-      for (int v = 0; v < VV; ++v)
-        r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
-      Tally tg = {0, 0, 0};
-      span3d<VV>(sp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, s_thr, tg);
-      if (interior) {
-        t.n += tg.n;
-        t.sb += tg.sb;
-        t.sc += tg.sc;
-      }
-    };
-    {
-      const uint32_t items = (Ht + 2u * ext) << shp;
-      for (uint32_t q = tid; q < items; q += nt) {
-        const uint32_t pl = plo + (q >> shp);
-        item(std::integral_constant<int, V>{}, pl, (q >> a.lg_spr) & rmask, (q & smask) * V,
-             pl >= halo && pl < halo + Ht);
-      }
-    }
-    if (c == 1u) {
-      int dE = a.z2 * t.n - (t.sc - 32 * t.sb);
-      int dM = 4 * t.sb - 2 * t.n;
-      t = {0, 0, 0};
-      dE = wave_sum(dE);
-      dM = wave_sum(dM);
-      if ((tid & 63u) == 0u) {
-        s_red[tid >> 6][0] = dE;
-        s_red[tid >> 6][1] = dM;
-      }
-    }
-    __syncthreads();
-    if (c == 1u && tid == 0u) {
-      int sE = 0, sM = 0;
-      for (uint32_t v = 0; v < (nt >> 6); ++v) {
-        sE += s_red[v][0];
-        sM += s_red[v][1];
-      }
-      int32_t *acc = a.st.acc3 + ((size_t)(hs >> 1) * G.R + w) * 4u;
-      __hip_atomic_fetch_add(acc, sE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(acc + 1, sM, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-
-  // Write the interior planes back, packed (contiguous in global memory).
-  pack_tile(a.dst + (size_t)w * (G.N >> 5) + ((y0 << lgP) >> 5), sp + ((size_t)halo << lgP),
-            (Ht << lgP) >> 5, tid, nt);
-
-  tiled_epilogue(a, tid, nt, &s_last);
-}
-
-// ---- 2D tiled sweep at four bits per site ----------------------------------
-// The 2D tiled kernel keeps its tile at four bits per site: row y of the tile
-// is L/8 dwords, site 8g + j of the row at bits 4j .. 4j+3 of dword g (0 up, 1
-// down).  A dword is exactly one Philox group: its four colour sites sit at
-// nibbles off, off+2, off+4, off+6.  Neighbour counts are nibble-wise sums of
-// XORs (at most 4, so no carries), a site's class 8b + u fits its nibble, and
-// the tallies are v_dot8 products over nibbles.  Half the LDS of the byte
-// layout and half the SWAR instructions per site.
+// ---- the four-bit LDS layout -------------------------------------------------
+// Site 8g + j of a row sits at bits 4j .. 4j+3 of the row's dword g.  A dword
+// is exactly one Philox group; a site's class 8b + u fits its nibble, and the
+// tallies are v_dot8 products over nibbles.
 
 // 8 bits -> 8 nibbles (bit j -> bit 4j), and back.
 __device__ __forceinline__ uint32_t spread8(uint32_t x) {
@@ -836,6 +502,107 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
   tiled_epilogue(a, tid, nt, &s_last);
 }
 
+// 3D +-J EA tiled sweep (nibble layout): tiles of z-planes with halo planes.
+template <int DIM, int V>
+__global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
+  static_assert(DIM == 3, "2D lattices use k_tiled_n");
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ uint32_t s_thr[kClasses];
+  __shared__ int s_red[kMaxThreads / 64][2];
+  __shared__ uint32_t s_last;
+
+  const Geometry &G = a.geo;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t tile = blockIdx.x, w = blockIdx.y;
+  const uint32_t L = G.L, lgL = a.lg_L;
+  const uint32_t lgG = lgL - 3u, gmask = (1u << lgG) - 1u;   // dwords per row
+  const uint32_t lgPl = lgL + lgG;                           // dwords per plane
+  const uint32_t y0 = tile * a.H;
+  const uint32_t Ht = min(a.H, L - y0);
+  const uint32_t halo = a.halo;
+  const uint32_t np = Ht + 2u * halo;                  // LDS planes
+  const uint32_t base = (y0 + L - halo) & (L - 1u);   // global plane of LDS plane 0
+  const uint32_t slot = a.st.slot_of[w];
+  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+
+  // four bits per site: spins, then the x, y, z bond planes of the tile
+  uint32_t *sp = reinterpret_cast<uint32_t *>(smem);
+  uint32_t *bx = sp + ((size_t)np << lgPl);
+  uint32_t *by = bx + ((size_t)np << lgPl);
+  uint32_t *bz = by + ((size_t)np << lgPl);
+
+  // Stage planes [base, base+np) mod L of this walker and of the bonds.
+  {
+    const uint32_t nwr = G.N >> 5, wpp = (L * L) >> 5;  // packed words per plane
+    const uint32_t first = base * wpp, cnt = np * wpp;
+    unpack_tile_n(sp, a.src + (size_t)w * nwr, first, cnt, nwr - 1u, tid, nt);
+    unpack_tile_n(bx, a.st.bonds, first, cnt, nwr - 1u, tid, nt);
+    unpack_tile_n(by, a.st.bonds + nwr, first, cnt, nwr - 1u, tid, nt);
+    unpack_tile_n(bz, a.st.bonds + 2u * nwr, first, cnt, nwr - 1u, tid, nt);
+  }
+  __syncthreads();
+
+  const uint32_t smask = (1u << a.lg_spr) - 1u, rmask = G.rows - 1u;
+  const uint32_t shp = a.lg_spr + a.lg_rows;
+  TallyN t = {0u, 0u, 0u};
+  for (uint32_t hs = 0; hs < 2u * a.sch.nsw; ++hs) {
+    const uint32_t c = hs & 1u;
+    const uint32_t s = a.sch.s0 + (hs >> 1);
+    const uint32_t ext = halo ? (halo - 1u - hs) : 0u;
+    const uint32_t plo = halo - ext;                 // computed LDS planes [plo, plo+Ht+2ext)
+    const uint32_t items = (Ht + 2u * ext) << shp;
+    for (uint32_t q = tid; q < items; q += nt) {
+      const uint32_t pl = plo + (q >> shp);
+      const uint32_t y = (q >> a.lg_spr) & rmask;
+      const uint32_t g0 = (q & smask) * V;
+      const uint32_t pu = (pl == 0u) ? np - 1u : pl - 1u;
+      const uint32_t pd = (pl + 1u == np) ? 0u : pl + 1u;
+      const uint32_t gp = (base + pl) & (L - 1u);   // global plane coordinate
+      const uint32_t off = (c + gp + y) & 1u;
+      const uint32_t ctr0 = (((gp << a.lg_rows) + y) << lgG) + g0;
+      Words r[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+      TallyN tg = {0u, 0u, 0u};
+      span3d_n<V>(sp, bx, by, bz, lgG, lgPl, pl, pu, pd, y, (y + L - 1u) & (L - 1u),
+                  (y + 1u) & (L - 1u), g0, gmask, off, r, s_thr, tg);
+      if (pl >= halo && pl < halo + Ht) {
+        t.n += tg.n;
+        t.sb += tg.sb;
+        t.sc += tg.sc;
+      }
+    }
+    if (c == 1u) {
+      int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb);
+      int dM = 4 * (int)t.sb - 2 * (int)t.n;
+      t = {0u, 0u, 0u};
+      dE = wave_sum(dE);
+      dM = wave_sum(dM);
+      if ((tid & 63u) == 0u) {
+        s_red[tid >> 6][0] = dE;
+        s_red[tid >> 6][1] = dM;
+      }
+    }
+    __syncthreads();
+    if (c == 1u && tid == 0u) {
+      int sE = 0, sM = 0;
+      for (uint32_t v = 0; v < (nt >> 6); ++v) {
+        sE += s_red[v][0];
+        sM += s_red[v][1];
+      }
+      int32_t *acc = a.st.acc3 + ((size_t)(hs >> 1) * G.R + w) * 4u;
+      __hip_atomic_fetch_add(acc, sE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(acc + 1, sM, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+
+  // Write the interior planes back, packed (contiguous in global memory).
+  pack_tile_n(a.dst + (size_t)w * (G.N >> 5) + y0 * ((L * L) >> 5), sp + ((size_t)halo << lgPl),
+              Ht * ((L * L) >> 5), tid, nt);
+  tiled_epilogue(a, tid, nt, &s_last);
+}
+
 struct FusedArgs {
   DevState st;
   Geometry geo;
@@ -859,8 +626,8 @@ __host__ __device__ inline FusedLayout fused_layout(uint32_t R, uint32_t N, uint
   f.M = f.E + R * 4u;
   f.acc = f.M + R * 4u;
   f.spins = (f.acc + R * 8u + 15u) & ~15u;
-  f.bonds = f.spins + R * N;
-  f.total = f.bonds + (dim == 3 ? 3u * N : 0u);
+  f.bonds = f.spins + R * N / 2u;                  // four bits per site
+  f.total = f.bonds + (dim == 3 ? 3u * N / 2u : 0u);
   return f;
 }
 
@@ -869,7 +636,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const Geometry &G = a.geo;
   const uint32_t R = G.R, N = G.N, L = G.L, lgL = a.lg_L;
-  const uint32_t lgP = (DIM == 3 ? 2u : 1u) * lgL;
+  const uint32_t lgG = lgL - 3u, gmask = (1u << lgG) - 1u;   // dwords per row
+  const uint32_t lgPl = lgL + lgG;                           // dwords per plane (3D)
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const FusedLayout F = fused_layout(R, N, DIM);
   uint32_t *thr = reinterpret_cast<uint32_t *>(smem + F.thr);
@@ -878,8 +646,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   int32_t *E = reinterpret_cast<int32_t *>(smem + F.E);
   int32_t *M = reinterpret_cast<int32_t *>(smem + F.M);
   int32_t *acc = reinterpret_cast<int32_t *>(smem + F.acc);
-  uint8_t *sp = smem + F.spins;
-  uint8_t *bx = smem + F.bonds, *by = bx + N, *bz = by + N;
+  uint32_t *sp = reinterpret_cast<uint32_t *>(smem + F.spins);   // [R][N/8] nibble dwords
+  uint32_t *bx = reinterpret_cast<uint32_t *>(smem + F.bonds), *by = bx + (N >> 3), *bz = by + (N >> 3);
 
   for (uint32_t q = tid; q < R * kClasses; q += nt) thr[q] = a.st.flip_thr[q];
   for (uint32_t q = tid; q < R; q += nt) {
@@ -890,8 +658,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
     acc[2u * q] = 0;
     acc[2u * q + 1u] = 0;
   }
-  unpack_tile(sp, a.spins, 0u, (R * N) >> 5, 0xFFFFFFFFu, tid, nt);
-  if (DIM == 3) unpack_tile(bx, a.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
+  unpack_tile_n(sp, a.spins, 0u, (R * N) >> 5, 0xFFFFFFFFu, tid, nt);
+  if (DIM == 3) unpack_tile_n(bx, a.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
   __syncthreads();
 
   const uint32_t smask = (1u << a.lg_spr) - 1u, rmask = G.rows - 1u, imask = (1u << a.lg_items) - 1u;
@@ -902,17 +670,18 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
     const uint32_t s = a.sch.s0 + j;
     for (uint32_t c = 0; c < 2u; ++c) {
       uint32_t cur = 0xFFFFFFFFu;
-      Tally t = {0, 0, 0};
+      TallyN t = {0u, 0u, 0u};
+      auto flush = [&]() {
+        atomicAdd(&acc[2u * cur], a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb));
+        atomicAdd(&acc[2u * cur + 1u], 4 * (int)t.sb - 2 * (int)t.n);
+      };
       for (uint32_t q = tid; q < items; q += nt) {
         const uint32_t w = q >> a.lg_items;
         const uint32_t li = q & imask;
         if (w != cur) {
-          if (cur != 0xFFFFFFFFu) {
-            atomicAdd(&acc[2u * cur], a.z2 * t.n - (t.sc - 32 * t.sb));
-            atomicAdd(&acc[2u * cur + 1u], 4 * t.sb - 2 * t.n);
-          }
+          if (cur != 0xFFFFFFFFu) flush();
           cur = w;
-          t = {0, 0, 0};
+          t = {0u, 0u, 0u};
         }
         const uint32_t g0 = (li & smask) * V;
         const uint32_t y = (li >> a.lg_spr) & rmask;
@@ -921,22 +690,20 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
         const uint32_t pd = (pl + 1u) & (L - 1u);
         const uint32_t off = (c + pl + (DIM == 3 ? y : 0u)) & 1u;
         const uint32_t slot = sof[w];
-        const uint32_t ctr0 = (((pl << a.lg_rows) + y) << (lgL - 3u)) + g0;
+        const uint32_t ctr0 = (((pl << a.lg_rows) + y) << lgG) + g0;
         Words r[V];
 #pragma unroll
         for (int v = 0; v < V; ++v)
           r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
-        uint8_t *wsp = sp + (size_t)w * N;
-        if (DIM == 2)
-          span2d<V>(wsp + (pl << lgP), wsp + (pu << lgP), wsp + (pd << lgP), g0, L, off, r,
-                    thr + slot * kClasses, t);
+        uint32_t *wsp = sp + (size_t)w * (N >> 3);
+        if constexpr (DIM == 2)
+          span2d_n<V>(wsp + (pl << lgG), wsp + (pu << lgG), wsp + (pd << lgG), g0, gmask, off, r,
+                      thr + slot * kClasses, t);
         else
-          span3d<V>(wsp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, thr + slot * kClasses, t);
+          span3d_n<V>(wsp, bx, by, bz, lgG, lgPl, pl, pu, pd, y, (y + L - 1u) & (L - 1u),
+                      (y + 1u) & (L - 1u), g0, gmask, off, r, thr + slot * kClasses, t);
       }
-      if (cur != 0xFFFFFFFFu) {
-        atomicAdd(&acc[2u * cur], a.z2 * t.n - (t.sc - 32 * t.sb));
-        atomicAdd(&acc[2u * cur + 1u], 4 * t.sb - 2 * t.n);
-      }
+      if (cur != 0xFFFFFFFFu) flush();
       __syncthreads();
     }
     for (uint32_t v = tid; v < R; v += nt) {
@@ -961,7 +728,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
     __syncthreads();
   }
 
-  pack_tile(a.spins, sp, (R * N) >> 5, tid, nt);
+  pack_tile_n(a.spins, sp, (R * N) >> 5, tid, nt);
   for (uint32_t q = tid; q < R; q += nt) {
     a.st.walker_at[q] = wat[q];
     a.st.slot_of[q] = sof[q];
@@ -1251,8 +1018,8 @@ __host__ __device__ inline BatchLayout batch_layout(uint32_t W, uint32_t N, uint
   b.M = b.E + W * 4u;
   b.acc = b.M + W * 4u;
   b.spins = (b.acc + W * 8u + 15u) & ~15u;
-  b.bonds = b.spins + W * (dim == 3 ? N : N / 2u); // 2D: four bits per site
-  b.total = b.bonds + (dim == 3 ? 3u * N : 0u);
+  b.bonds = b.spins + W * N / 2u;                  // four bits per site
+  b.total = b.bonds + (dim == 3 ? 3u * N / 2u : 0u);
   return b;
 }
 
@@ -1266,113 +1033,13 @@ __device__ __forceinline__ uint32_t cycle_sweeps(const uint32_t *ctr, uint32_t K
   return n;
 }
 
-// One workgroup: walkers [w0, w0 + W) of one instance, whole lattices in LDS,
-// the cycle's sweeps in place, per-walker E and M, records by slot.
+// Batched sweep, one workgroup = walkers [w0, w0 + W) of one instance whole
+// in LDS at four bits per site (EA: with the instance's bond planes), the
+// cycle's sweeps in place, per-walker E and M, records by slot.
 template <int DIM, int V>
 __global__ __launch_bounds__(kMaxThreads) void k_batch_sweep(const BatchInst *insts,
                                                              const BatchItem *items, uint32_t W,
                                                              uint32_t K) {
-  static_assert(DIM == 3, "2D lattices use the four-bit layout of k_batch_sweep_n");
-  extern __shared__ __align__(16) uint8_t smem[];
-  const BatchItem it = items[blockIdx.x];
-  const BatchInst &I = insts[it.inst];
-  const uint32_t nsw = cycle_sweeps(I.ctr, K);
-  if (nsw == 0u) return;
-  const uint32_t s0 = I.ctr[kCtrSweeps];
-  const Geometry &G = I.geo;
-  const uint32_t R = G.R, N = G.N, L = G.L, lgL = I.lg_L;
-  const uint32_t lgP = (DIM == 3 ? 2u : 1u) * lgL;
-  const uint32_t nw = min(W, R - it.w0);
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const BatchLayout B = batch_layout(W, N, DIM);
-  uint32_t *thr = reinterpret_cast<uint32_t *>(smem + B.thr);
-  uint32_t *slot = reinterpret_cast<uint32_t *>(smem + B.slot);
-  int32_t *E = reinterpret_cast<int32_t *>(smem + B.E);
-  int32_t *M = reinterpret_cast<int32_t *>(smem + B.M);
-  int32_t *acc = reinterpret_cast<int32_t *>(smem + B.acc);
-  uint8_t *sp = smem + B.spins;
-  uint8_t *bx = smem + B.bonds, *by = bx + N, *bz = by + N;
-
-  for (uint32_t v = tid; v < nw; v += nt) {
-    slot[v] = I.st.slot_of[it.w0 + v];
-    E[v] = I.st.E[it.w0 + v];
-    M[v] = I.st.M[it.w0 + v];
-    acc[2u * v] = 0;
-    acc[2u * v + 1u] = 0;
-  }
-  __syncthreads();
-  for (uint32_t q = tid; q < nw * kClasses; q += nt)
-    thr[q] = I.st.flip_thr[slot[q / kClasses] * kClasses + (q % kClasses)];
-  unpack_tile(sp, I.st.spins[0] + (size_t)it.w0 * (N >> 5), 0u, (nw * N) >> 5, 0xFFFFFFFFu, tid, nt);
-  if (DIM == 3) unpack_tile(bx, I.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
-  __syncthreads();
-
-  const uint32_t smask = (1u << I.lg_spr) - 1u, rmask = G.rows - 1u, imask = (1u << I.lg_items) - 1u;
-  const uint32_t shp = I.lg_spr + I.lg_rows;
-  const uint32_t items_n = nw << I.lg_items;
-  uint32_t rec = I.ctr[kCtrRecords];
-  for (uint32_t j = 0; j < nsw; ++j) {
-    const uint32_t s = s0 + j;
-    for (uint32_t c = 0; c < 2u; ++c) {
-      uint32_t cur = 0xFFFFFFFFu;
-      Tally t = {0, 0, 0};
-      for (uint32_t q = tid; q < items_n; q += nt) {
-        const uint32_t v = q >> I.lg_items;
-        const uint32_t li = q & imask;
-        if (v != cur) {
-          if (cur != 0xFFFFFFFFu) {
-            atomicAdd(&acc[2u * cur], I.z2 * t.n - (t.sc - 32 * t.sb));
-            atomicAdd(&acc[2u * cur + 1u], 4 * t.sb - 2 * t.n);
-          }
-          cur = v;
-          t = {0, 0, 0};
-        }
-        const uint32_t g0 = (li & smask) * V;
-        const uint32_t y = (li >> I.lg_spr) & rmask;
-        const uint32_t pl = li >> shp;
-        const uint32_t pu = (pl + L - 1u) & (L - 1u);
-        const uint32_t pd = (pl + 1u) & (L - 1u);
-        const uint32_t off = (c + pl + (DIM == 3 ? y : 0u)) & 1u;
-        const uint32_t ctr0 = (((pl << I.lg_rows) + y) << (lgL - 3u)) + g0;
-        Words r[V];
-#pragma unroll
-        for (int u = 0; u < V; ++u)
-          r[u] = philox(ctr0 + u, s, slot[v], c | kPurposeFlip, I.key.k0, I.key.k1);
-        uint8_t *wsp = sp + (size_t)v * N;
-        span3d<V>(wsp, bx, by, bz, lgL, pl, pu, pd, y, g0, L, off, r, thr + v * kClasses, t);
-      }
-      if (cur != 0xFFFFFFFFu) {
-        atomicAdd(&acc[2u * cur], I.z2 * t.n - (t.sc - 32 * t.sb));
-        atomicAdd(&acc[2u * cur + 1u], 4 * t.sb - 2 * t.n);
-      }
-      __syncthreads();
-    }
-    for (uint32_t v = tid; v < nw; v += nt) {
-      E[v] += acc[2u * v];
-      M[v] += acc[2u * v + 1u];
-      acc[2u * v] = 0;
-      acc[2u * v + 1u] = 0;
-      if (I.record_every && (s + 1u) % I.record_every == 0u) {
-        I.st.E_series[(size_t)rec * R + slot[v]] = E[v];
-        I.st.M_series[(size_t)rec * R + slot[v]] = M[v];
-      }
-    }
-    if (I.record_every && (s + 1u) % I.record_every == 0u) ++rec;
-    __syncthreads();
-  }
-  pack_tile(I.st.spins[0] + (size_t)it.w0 * (N >> 5), sp, (nw * N) >> 5, tid, nt);
-  for (uint32_t v = tid; v < nw; v += nt) {
-    I.st.E[it.w0 + v] = E[v];
-    I.st.M[it.w0 + v] = M[v];
-  }
-}
-
-// 2D batched sweep at four bits per site (the layout of k_tiled_n): W walkers
-// of one instance whole in LDS, the cycle's sweeps in place.
-template <int V>
-__global__ __launch_bounds__(kMaxThreads) void k_batch_sweep_n(const BatchInst *insts,
-                                                               const BatchItem *items, uint32_t W,
-                                                               uint32_t K) {
   extern __shared__ __align__(16) uint8_t smem[];
   const BatchItem it = items[blockIdx.x];
   const BatchInst &I = insts[it.inst];
@@ -1382,15 +1049,17 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_sweep_n(const BatchInst *
   const Geometry &G = I.geo;
   const uint32_t R = G.R, N = G.N, L = G.L, lgL = I.lg_L;
   const uint32_t lgG = lgL - 3u, gmask = (1u << lgG) - 1u;   // dwords per row
+  const uint32_t lgPl = lgL + lgG;                           // dwords per plane (3D)
   const uint32_t nw = min(W, R - it.w0);
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const BatchLayout B = batch_layout(W, N, 2u);
+  const BatchLayout B = batch_layout(W, N, DIM);
   uint32_t *thr = reinterpret_cast<uint32_t *>(smem + B.thr);
   uint32_t *slot = reinterpret_cast<uint32_t *>(smem + B.slot);
   int32_t *E = reinterpret_cast<int32_t *>(smem + B.E);
   int32_t *M = reinterpret_cast<int32_t *>(smem + B.M);
   int32_t *acc = reinterpret_cast<int32_t *>(smem + B.acc);
   uint32_t *sp = reinterpret_cast<uint32_t *>(smem + B.spins);
+  uint32_t *bx = reinterpret_cast<uint32_t *>(smem + B.bonds), *by = bx + (N >> 3), *bz = by + (N >> 3);
 
   for (uint32_t v = tid; v < nw; v += nt) {
     slot[v] = I.st.slot_of[it.w0 + v];
@@ -1403,9 +1072,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_sweep_n(const BatchInst *
   for (uint32_t q = tid; q < nw * kClasses; q += nt)
     thr[q] = I.st.flip_thr[slot[q / kClasses] * kClasses + (q % kClasses)];
   unpack_tile_n(sp, I.st.spins[0] + (size_t)it.w0 * (N >> 5), 0u, (nw * N) >> 5, 0xFFFFFFFFu, tid, nt);
+  if (DIM == 3) unpack_tile_n(bx, I.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
   __syncthreads();
 
-  const uint32_t smask = (1u << I.lg_spr) - 1u, imask = (1u << I.lg_items) - 1u;
+  const uint32_t smask = (1u << I.lg_spr) - 1u, rmask = G.rows - 1u, imask = (1u << I.lg_items) - 1u;
+  const uint32_t shp = I.lg_spr + I.lg_rows;
   const uint32_t items_n = nw << I.lg_items;
   const uint32_t wdw = N >> 3;                                  // LDS dwords per walker
   uint32_t rec = I.ctr[kCtrRecords];
@@ -1427,18 +1098,23 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_sweep_n(const BatchInst *
           t = {0u, 0u, 0u};
         }
         const uint32_t g0 = (li & smask) * V;
-        const uint32_t pl = li >> I.lg_spr;
+        const uint32_t y = (li >> I.lg_spr) & rmask;
+        const uint32_t pl = li >> shp;
         const uint32_t pu = (pl + L - 1u) & (L - 1u);
         const uint32_t pd = (pl + 1u) & (L - 1u);
-        const uint32_t off = (c + pl) & 1u;
-        const uint32_t ctr0 = (pl << lgG) + g0;
+        const uint32_t off = (c + pl + (DIM == 3 ? y : 0u)) & 1u;
+        const uint32_t ctr0 = (((pl << I.lg_rows) + y) << lgG) + g0;
         Words r[V];
 #pragma unroll
         for (int u = 0; u < V; ++u)
           r[u] = philox(ctr0 + u, s, slot[v], c | kPurposeFlip, I.key.k0, I.key.k1);
         uint32_t *wsp = sp + (size_t)v * wdw;
-        span2d_n<V>(wsp + (pl << lgG), wsp + (pu << lgG), wsp + (pd << lgG), g0, gmask, off, r,
-                    thr + v * kClasses, t);
+        if constexpr (DIM == 2)
+          span2d_n<V>(wsp + (pl << lgG), wsp + (pu << lgG), wsp + (pd << lgG), g0, gmask, off, r,
+                      thr + v * kClasses, t);
+        else
+          span3d_n<V>(wsp, bx, by, bz, lgG, lgPl, pl, pu, pd, y, (y + L - 1u) & (L - 1u),
+                      (y + 1u) & (L - 1u), g0, gmask, off, r, thr + v * kClasses, t);
       }
       if (cur != 0xFFFFFFFFu) flush();
       __syncthreads();
@@ -1640,17 +1316,6 @@ hipError_t launch_tiled_n_v(const TiledArgs &a, uint32_t tiles, uint32_t R, uint
   return hipGetLastError();
 }
 
-template <int V>
-hipError_t launch_batch_sweep_n_v(const BatchInst *insts, const BatchItem *items, uint32_t n_items,
-                                  uint32_t W, uint32_t threads, uint32_t K, size_t lds,
-                                  hipStream_t stream) {
-  hipError_t err = allow_lds(k_batch_sweep_n<V>, lds);
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((k_batch_sweep_n<V>), dim3(n_items), dim3(threads), lds, stream, insts, items,
-                     W, K);
-  return hipGetLastError();
-}
-
 template <int DIM, int V>
 hipError_t launch_batch_sweep_v(const BatchInst *insts, const BatchItem *items, uint32_t n_items,
                                 uint32_t W, uint32_t threads, uint32_t K, size_t lds,
@@ -1686,7 +1351,7 @@ size_t max_lds_bytes() { return 160u * 1024u - 1024u; }
 
 size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo) {
   const size_t np = (size_t)std::min(tile_planes, g.L) + 2u * halo;
-  return g.dim == 3 ? np * g.plane * 4u : np * g.plane / 2u; // 3D: spins + 3 bond planes, bytes; 2D: nibbles
+  return np * g.plane / 2u * (g.dim == 3 ? 4u : 1u); // four bits per site; 3D: spins + 3 bond planes
 }
 
 size_t fused_lds_bytes(const Geometry &g) { return fused_layout(g.R, g.N, g.dim).total; }
@@ -1870,9 +1535,9 @@ hipError_t launch_batch_sweep(const BatchInst *insts, const BatchItem *items, ui
   if (g.dim == 3)
     return V == 2 ? launch_batch_sweep_v<3, 2>(insts, items, n_items, W, threads, K, lds, stream)
                   : launch_batch_sweep_v<3, 1>(insts, items, n_items, W, threads, K, lds, stream);
-  return V == 4 ? launch_batch_sweep_n_v<4>(insts, items, n_items, W, threads, K, lds, stream)
-       : V == 2 ? launch_batch_sweep_n_v<2>(insts, items, n_items, W, threads, K, lds, stream)
-                : launch_batch_sweep_n_v<1>(insts, items, n_items, W, threads, K, lds, stream);
+  return V == 4 ? launch_batch_sweep_v<2, 4>(insts, items, n_items, W, threads, K, lds, stream)
+       : V == 2 ? launch_batch_sweep_v<2, 2>(insts, items, n_items, W, threads, K, lds, stream)
+                : launch_batch_sweep_v<2, 1>(insts, items, n_items, W, threads, K, lds, stream);
 }
 
 hipError_t launch_batch_exchange(const BatchInst *insts, const uint2 *pairs, uint32_t n_pairs,

@@ -237,24 +237,26 @@ void pt_batch_destroy(pt_batch *b);
  * (2D L <= 512, EA L <= 32) join the batched lane: one stream whose cycles run
  * up to cycle_sweeps sweeps of every resident job in one launch per lattice-size
  * group, then their exchange steps (the batched form's kernels, membership
- * changing between cycles as jobs arrive and finish).  Larger lattices run on
- * tiled lanes: further streams on which each resident job advances by
- * tiled_sweeps sweeps per step, so their kernels overlap with the batched lane.
- * A job's results depend only on its own pt_config (seed, stream_id, ...) and
- * schedule, never on what else is resident: they are bit-identical to running
- * it alone with pt_run(ctx, n_sweeps, exchange_every).  When a job finishes its
- * observables are copied to host memory and its arena slice is freed at once.
+ * changing between cycles as jobs arrive and finish).  Larger 2D lattices join
+ * a tiled lane: a stream whose cycles run up to tiled_sweeps sweeps of every
+ * resident job's tiles in one launch per lattice size, each job's last
+ * workgroup folding its energies, records and exchange step; tiled lanes and
+ * the batched lane run concurrently.  A job's results depend only on its own
+ * pt_config (seed, stream_id, ...) and schedule, never on what else is
+ * resident: they are bit-identical to running it alone with
+ * pt_run(ctx, n_sweeps, exchange_every).  When a job finishes its observables
+ * are copied to host memory and its arena slice is freed at once.
  * All work runs on streams the server creates (default priority, non-blocking).
  * One server must not be used from two threads at once. */
 typedef struct pt_server pt_server;
 
 typedef struct {
   uint32_t max_jobs;       /* resident jobs at once, 1 .. 65536 */
-  uint32_t max_walkers;    /* resident replicas of batched-lane jobs at once (sum of R) */
+  uint32_t max_walkers;    /* per lane: resident replicas (batched lane) or replica tiles (tiled lanes) */
   uint32_t tiled_lanes;    /* streams for jobs too large for the batched lane, 1 .. 8 */
   uint32_t depth;          /* steps in flight per lane, 1 .. 8 */
   uint32_t cycle_sweeps;   /* batched lane: at most this many sweeps per cycle, 1 .. 16 */
-  uint32_t tiled_sweeps;   /* tiled lanes: sweeps per job per step, 1 .. 4096 */
+  uint32_t tiled_sweeps;   /* tiled lanes: at most this many sweeps per cycle, 1 .. PT_MAX_SWEEPS_PER_LAUNCH */
 } pt_server_opts;
 
 #define PT_JOB_KEEP_SPINS 1u /* keep the final lattices of all slots with the results */
@@ -288,7 +290,8 @@ pt_status pt_server_create(const pt_server_opts *opts, void *d_workspace, size_t
  * needs max_records >= n_sweeps / record_every), n_sweeps in [1, 2^32 - 1]
  * sweeps with an exchange step after every exchange_every-th (0 = none), flags
  * (PT_JOB_KEEP_SPINS), arrival time on the server clock (negative = now).
- * PT_EINVAL for an invalid job, PT_ENOMEM if it could never fit the arena. */
+ * PT_EINVAL for an invalid job, PT_ENOMEM if it could never fit the arena or
+ * a lane, PT_EUNSUPPORTED if no tile of its lattice fits one workgroup. */
 pt_status pt_server_submit(pt_server *sv, const pt_config *cfg, uint64_t n_sweeps,
                            uint32_t exchange_every, uint32_t flags, double arrival,
                            uint64_t *job_id);

@@ -832,7 +832,7 @@ hipError_t launch_cycle(pt_batch *b, uint32_t K, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   if ((e = launch_batch_exchange(b->d_insts, b->d_pairs, b->n_pairs, K, s)) != hipSuccess) return e;
-  return launch_batch_advance(b->d_insts, (uint32_t)b->ctx.size(), K, s);
+  return launch_batch_advance(b->d_insts, nullptr, (uint32_t)b->ctx.size(), K, s);
 }
 
 }  // namespace
@@ -1001,7 +1001,7 @@ pt_status pt_batch_run(pt_batch *b, uint32_t n_sweeps, uint32_t exchange_every) 
       }
     }
     if ((e = launch_batch_exchange(b->d_insts, b->d_pairs, b->n_pairs, K, b->own)) != hipSuccess ||
-        (e = launch_batch_advance(b->d_insts, n, K, b->own)) != hipSuccess)
+        (e = launch_batch_advance(b->d_insts, nullptr, n, K, b->own)) != hipSuccess)
       return batch_fail(b, e, "batch cycle launch");
     --cycles;
     if ((e = hipStreamSynchronize(b->own)) != hipSuccess) return batch_fail(b, e, "batch tuning");

@@ -78,6 +78,8 @@ enum BatchCtr : uint32_t {
   kCtrTarget = 3,    // run until this many sweeps are done
   kCtrActive = 4,    // 0: the instance is idle
   kCtrEvery = 5,     // exchange interval (0 = never)
+  kCtrCur = 6,       // tiled instances: spin buffer holding the lattices
+  kCtrTiles = 7,     // tiled instances: tiles per walker (0: whole replicas in LDS)
   kCtrWords = 8
 };
 
@@ -96,6 +98,11 @@ struct BatchItem {
   uint32_t w0;   // first walker of the workgroup (up to W walkers)
 };
 
+// Work item of the batched tiled sweep: one tile of one walker of an instance.
+struct BatchTileItem {
+  uint32_t inst, w, tile, pad;
+};
+
 // One cycle of at most K sweeps: sweep launches (one per lattice-size group),
 // then the exchange launch, then the counter advance.
 hipError_t launch_batch_sweep(const BatchInst *insts, const BatchItem *items, uint32_t n_items,
@@ -103,8 +110,15 @@ hipError_t launch_batch_sweep(const BatchInst *insts, const BatchItem *items, ui
                               hipStream_t stream);
 hipError_t launch_batch_exchange(const BatchInst *insts, const uint2 *pairs, uint32_t n_pairs,
                                  uint32_t K, hipStream_t stream);
-hipError_t launch_batch_advance(const BatchInst *insts, uint32_t n_insts, uint32_t K,
-                                hipStream_t stream);
+// Advance the schedule counters of instances list[0 .. n) (list = NULL: 0 .. n).
+hipError_t launch_batch_advance(const BatchInst *insts, const uint32_t *list, uint32_t n_insts,
+                                uint32_t K, hipStream_t stream);
+// Batched 2D tiled sweep: items of instances of one lattice size L, tiles of H
+// rows, up to K sweeps per instance (to its next exchange point); each
+// instance's last workgroup folds E and M, records and exchanges.
+hipError_t launch_batch_tiled(const BatchInst *insts, const BatchTileItem *items, uint32_t n_items,
+                              const Geometry &g, uint32_t H, uint32_t threads, uint32_t K,
+                              hipStream_t stream);
 size_t batch_lds_bytes(const Geometry &g, uint32_t W);
 // Start a run: every instance's target = done + add, active if add > 0, interval = every.
 hipError_t launch_batch_target(const BatchInst *insts, uint32_t n, uint32_t add, uint32_t every,

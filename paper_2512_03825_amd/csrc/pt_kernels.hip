@@ -84,6 +84,16 @@ __device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, u
   return {c0, c1, c2, c3};
 }
 
+// Sweeps of this cycle for an instance: at most K, never past the target, and
+// never past the next exchange point (a cycle always ends on one).
+__device__ __forceinline__ uint32_t cycle_sweeps(const uint32_t *ctr, uint32_t K) {
+  if (!ctr[kCtrActive]) return 0u;
+  const uint32_t s = ctr[kCtrSweeps], every = ctr[kCtrEvery];
+  uint32_t n = min(K, ctr[kCtrTarget] - s);
+  if (every) n = min(n, every - s % every);
+  return n;
+}
+
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
   for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -162,11 +172,12 @@ struct TiledArgs {
 // The last workgroup of a tiled launch to arrive folds the per-sweep energy
 // and magnetisation changes into E and M, writes the records, and runs the
 // exchange step; it then re-arms the arrival counter.
-__device__ void tiled_epilogue(const TiledArgs &a, uint32_t tid, uint32_t nt, uint32_t *s_last) {
+// total = workgroups of the launch working on this walker set.
+__device__ __forceinline__ void tiled_epilogue(const TiledArgs &a, uint32_t tid, uint32_t nt,
+                                               uint32_t *s_last, uint32_t total) {
   __syncthreads();
   if (tid == 0u) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); // publish this workgroup's tallies
-    const uint32_t total = gridDim.x * gridDim.y;
     const uint32_t prev =
         __hip_atomic_fetch_add(a.st.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
     *s_last = (prev + 1u == total) ? 1u : 0u;
@@ -398,16 +409,14 @@ __device__ __forceinline__ void span3d_n(uint32_t *sp, const uint32_t *bx, const
   lds_store_n<V>(sp + rowb + g0, nw);
 }
 
+// One workgroup of the 2D tiled sweep: tile `tile` of walker `w`, staged in
+// sp (LDS), k sweeps, interior written back; per-sweep tallies to acc3.
 template <int V>
-__global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ uint32_t s_thr[kClasses];
-  __shared__ int s_red[kMaxThreads / 64][2];
-  __shared__ uint32_t s_last;
-
+__device__ __forceinline__ void tiled_n_body(const TiledArgs &a, uint32_t tile, uint32_t w,
+                                             uint32_t *sp, uint32_t *s_thr,
+                                             int (*s_red)[2]) {
   const Geometry &G = a.geo;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t tile = blockIdx.x, w = blockIdx.y;
   const uint32_t L = G.L, lgL = a.lg_L, lgG = lgL - 3u, gmask = (1u << lgG) - 1u;
   const uint32_t y0 = tile * a.H;
   const uint32_t Ht = min(a.H, L - y0);
@@ -416,7 +425,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
   const uint32_t base = (y0 + L - halo) & (L - 1u);   // global row of LDS row 0
   const uint32_t slot = a.st.slot_of[w];
   if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
-  uint32_t *sp = reinterpret_cast<uint32_t *>(smem);
 
   // rows [base, base+np) mod L of this walker, four bits per site; a packed
   // word (32 sites) becomes four LDS dwords (rows shorter than a word only
@@ -499,7 +507,57 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
   // interior rows back to HBM, packed (contiguous)
   pack_tile_n(a.dst + (size_t)w * nwr + ((y0 * L) >> 5), sp + ((size_t)halo << lgG), (Ht * L) >> 5,
               tid, nt);
-  tiled_epilogue(a, tid, nt, &s_last);
+}
+
+template <int V>
+__global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ uint32_t s_thr[kClasses];
+  __shared__ int s_red[kMaxThreads / 64][2];
+  __shared__ uint32_t s_last;
+  tiled_n_body<V>(a, blockIdx.x, blockIdx.y, reinterpret_cast<uint32_t *>(smem), s_thr, s_red);
+  tiled_epilogue(a, threadIdx.x, blockDim.x, &s_last, gridDim.x * gridDim.y);
+}
+
+
+// Batched 2D tiled sweep: the tiled kernel's work for many instances of one
+// lattice size in one launch.  Each instance's schedule (sweep, records,
+// exchange step, spin buffer) comes from its device counters; its last
+// workgroup to finish (its own arrival counter) runs its epilogue.
+template <int V>
+__global__ __launch_bounds__(kMaxThreads) void k_batch_tiled(const BatchInst *insts,
+                                                             const BatchTileItem *items,
+                                                             uint32_t H, uint32_t K) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ uint32_t s_thr[kClasses];
+  __shared__ int s_red[kMaxThreads / 64][2];
+  __shared__ uint32_t s_last;
+  const BatchTileItem it = items[blockIdx.x];
+  const BatchInst &I = insts[it.inst];
+  const uint32_t nsw = cycle_sweeps(I.ctr, K);
+  if (nsw == 0u) return; // every workgroup of an idle instance leaves here
+  const uint32_t tiles = I.ctr[kCtrTiles], every = I.ctr[kCtrEvery], cur = I.ctr[kCtrCur];
+  TiledArgs a;
+  a.st = I.st;
+  a.geo = I.geo;
+  a.key = I.key;
+  a.sch.s0 = I.ctr[kCtrSweeps];
+  a.sch.nsw = nsw;
+  a.sch.record_every = I.record_every;
+  a.sch.rec_base = I.ctr[kCtrRecords];
+  a.sch.exchange_every = every;
+  a.sch.do_exchange = (every && (a.sch.s0 + nsw) % every == 0u) ? 1u : 0u;
+  a.sch.ex_step = I.ctr[kCtrExchanges];
+  a.H = H;
+  a.halo = tiles > 1u ? 2u * nsw : 0u;
+  a.src = I.st.spins[cur];
+  a.dst = a.halo ? I.st.spins[cur ^ 1u] : I.st.spins[cur];
+  a.lg_L = I.lg_L;
+  a.lg_spr = I.lg_L - 3u - (V == 8 ? 3u : V == 4 ? 2u : V == 2 ? 1u : 0u);
+  a.lg_rows = 0u;
+  a.z2 = I.z2;
+  tiled_n_body<V>(a, it.tile, it.w, reinterpret_cast<uint32_t *>(smem), s_thr, s_red);
+  tiled_epilogue(a, threadIdx.x, blockDim.x, &s_last, I.geo.R * max(tiles, 1u));
 }
 
 // 3D +-J EA tiled sweep (nibble layout): tiles of z-planes with halo planes.
@@ -600,7 +658,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
   // Write the interior planes back, packed (contiguous in global memory).
   pack_tile_n(a.dst + (size_t)w * (G.N >> 5) + y0 * ((L * L) >> 5), sp + ((size_t)halo << lgPl),
               Ht * ((L * L) >> 5), tid, nt);
-  tiled_epilogue(a, tid, nt, &s_last);
+  tiled_epilogue(a, tid, nt, &s_last, gridDim.x * gridDim.y);
 }
 
 struct FusedArgs {
@@ -1023,15 +1081,6 @@ __host__ __device__ inline BatchLayout batch_layout(uint32_t W, uint32_t N, uint
   return b;
 }
 
-// Sweeps of this cycle for an instance: at most K, never past the target, and
-// never past the next exchange point (a cycle always ends on one).
-__device__ __forceinline__ uint32_t cycle_sweeps(const uint32_t *ctr, uint32_t K) {
-  if (!ctr[kCtrActive]) return 0u;
-  const uint32_t s = ctr[kCtrSweeps], every = ctr[kCtrEvery];
-  uint32_t n = min(K, ctr[kCtrTarget] - s);
-  if (every) n = min(n, every - s % every);
-  return n;
-}
 
 // Batched sweep, one workgroup = walkers [w0, w0 + W) of one instance whole
 // in LDS at four bits per site (EA: with the instance's bond planes), the
@@ -1163,17 +1212,20 @@ __global__ void k_batch_target(const BatchInst *insts, uint32_t n, uint32_t add,
   ctr[kCtrEvery] = every;
 }
 
-// One thread per instance: advance the schedule by this cycle's sweeps.
-__global__ void k_batch_advance(const BatchInst *insts, uint32_t n, uint32_t K) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const BatchInst &I = insts[i];
+// One thread per instance: advance the schedule by this cycle's sweeps (and,
+// for a tiled instance, switch to the spin buffer the cycle wrote).
+__global__ void k_batch_advance(const BatchInst *insts, const uint32_t *list, uint32_t n,
+                                uint32_t K) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const BatchInst &I = insts[list ? list[q] : q];
   uint32_t *ctr = I.ctr;
   const uint32_t nsw = cycle_sweeps(ctr, K);
   if (nsw == 0u) return;
   const uint32_t s0 = ctr[kCtrSweeps], every = ctr[kCtrEvery];
   if (I.record_every) ctr[kCtrRecords] += (s0 + nsw) / I.record_every - s0 / I.record_every;
   if (every && (s0 + nsw) % every == 0u) ctr[kCtrExchanges] += 1u;
+  if (ctr[kCtrTiles] > 1u) ctr[kCtrCur] ^= 1u;
   ctr[kCtrSweeps] = s0 + nsw;
   if (s0 + nsw >= ctr[kCtrTarget]) ctr[kCtrActive] = 0u;
 }
@@ -1524,6 +1576,28 @@ hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, 
                 : launch_persist_v<2, 1>(a, g.R, threads, lds, stream);
 }
 
+hipError_t launch_batch_tiled(const BatchInst *insts, const BatchTileItem *items, uint32_t n_items,
+                              const Geometry &g, uint32_t H, uint32_t threads, uint32_t K,
+                              hipStream_t stream) {
+  if (n_items == 0) return hipSuccess;
+  if (g.dim != 2 || K < 1 || K > kMaxSweepsPerLaunch || H < 1 || H > g.L ||
+      (H < g.L && (2u * K > g.L / 2u || g.plane % 32u)))
+    return hipErrorInvalidValue;
+  const size_t lds = tiled_lds_bytes(g, H, H < g.L ? 2u * K : 0u);
+  const uint32_t V = std::min<uint32_t>(kNibbleSpan, g.gpr);
+  hipError_t err = hipSuccess;
+  auto go = [&](auto kern) {
+    if ((err = allow_lds(kern, lds)) != hipSuccess) return;
+    hipLaunchKernelGGL(kern, dim3(n_items), dim3(threads), lds, stream, insts, items, H, K);
+    err = hipGetLastError();
+  };
+  if (V == 8) go(k_batch_tiled<8>);
+  else if (V == 4) go(k_batch_tiled<4>);
+  else if (V == 2) go(k_batch_tiled<2>);
+  else go(k_batch_tiled<1>);
+  return err;
+}
+
 size_t batch_lds_bytes(const Geometry &g, uint32_t W) { return batch_layout(W, g.N, g.dim).total; }
 
 hipError_t launch_batch_sweep(const BatchInst *insts, const BatchItem *items, uint32_t n_items,
@@ -1548,9 +1622,11 @@ hipError_t launch_batch_exchange(const BatchInst *insts, const uint2 *pairs, uin
   return hipGetLastError();
 }
 
-hipError_t launch_batch_advance(const BatchInst *insts, uint32_t n, uint32_t K, hipStream_t stream) {
+hipError_t launch_batch_advance(const BatchInst *insts, const uint32_t *list, uint32_t n, uint32_t K,
+                                hipStream_t stream) {
   if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_batch_advance, dim3((n + 255u) / 256u), dim3(256), 0, stream, insts, n, K);
+  hipLaunchKernelGGL(k_batch_advance, dim3((n + 255u) / 256u), dim3(256), 0, stream, insts, list, n,
+                     K);
   return hipGetLastError();
 }
 

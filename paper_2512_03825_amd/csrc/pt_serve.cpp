@@ -21,6 +21,7 @@ namespace {
 constexpr uint32_t kMaxJobs = 65536;
 constexpr uint32_t kMaxLanes = 8;
 constexpr uint32_t kMaxDepth = 8;
+constexpr size_t kTiledLds = 144u * 1024u; // LDS budget of a tiled-lane workgroup
 
 struct Job {
   uint64_t id = 0;
@@ -32,7 +33,9 @@ struct Job {
   size_t bytes = 0, off = 0;
   pt_ctx *ctx = nullptr;
   uint32_t lane = 0;
-  uint32_t inst = ~0u;  // batched lane: instance slot
+  uint32_t inst = ~0u;  // instance slot (device descriptor and counters)
+  uint32_t tiles = 0;   // tiled lanes: tiles per walker
+  uint32_t cur = 0;     // tiled lanes: spin buffer holding the lattices (host replay)
   uint64_t queued = 0;  // sweeps queued on the device so far
   bool done = false;
   // results, copied to the host when the job finishes
@@ -42,9 +45,8 @@ struct Job {
   uint32_t n_records = 0;
 
   ~Job() { pt_destroy(ctx); }
-  uint64_t attempts() const { return (uint64_t)ctx_R() * ctx_N() * n_sweeps; }
-  uint32_t ctx_R() const { return cfg.R; }
-  uint64_t ctx_N() const {
+  uint64_t attempts() const { return (uint64_t)cfg.R * sites() * n_sweeps; }
+  uint64_t sites() const {
     const uint64_t L = cfg.L;
     return cfg.model == PT_EA3D ? L * L * L : L * L;
   }
@@ -58,18 +60,33 @@ struct Step {
   Keep keep;                       // host sources of uploads queued before it
 };
 
+// A launch group of a lane: jobs of one lattice geometry.
+struct Group {
+  Geometry g;
+  uint32_t W = 1, threads = 256, max_R = 0; // batched lane: walkers per workgroup
+  uint32_t H = 0;                           // tiled lanes: rows per tile
+  uint32_t item_off = 0, n_items = 0;
+};
+
+// A lane is a stream with its own resident jobs and device work lists: lane 0
+// runs whole-replica jobs through the batched kernels, lanes 1.. run larger
+// lattices through the batched tiled kernel.
 struct Lane {
   hipStream_t s = nullptr;
   std::deque<Step> q;
-  std::vector<uint64_t> jobs;  // tiled lanes: resident jobs in admission order
+  std::vector<uint64_t> jobs;  // resident jobs in admission order
   Keep staged;                 // uploads queued since the last step
-  uint64_t work = 0;           // tiled lanes: resident sites x replicas
-};
-
-struct Group {
-  Geometry g;
-  uint32_t W = 1, threads = 256, max_R = 0;
-  uint32_t item_off = 0, n_items = 0;
+  bool dirty = true;           // membership changed since the lists were built
+  uint64_t slots = 0;          // resident walkers (lane 0) or walker tiles (tiled lanes)
+  uint64_t work = 0;           // resident sites x replicas
+  uint32_t K = 1;              // sweeps per cycle
+  std::vector<Group> groups;
+  uint32_t n_pairs = 0, n_list = 0;
+  // device work lists in the server's tables
+  BatchItem *d_items = nullptr;      // lane 0
+  BatchTileItem *d_titems = nullptr; // tiled lanes
+  uint2 *d_pairs = nullptr;          // lane 0
+  uint32_t *d_list = nullptr;        // instances the lane advances
 };
 
 double now_s(std::chrono::steady_clock::time_point t0) {
@@ -83,21 +100,30 @@ std::shared_ptr<std::vector<uint8_t>> bytes_of(const T *p, size_t n) {
   return v;
 }
 
+// Server tables at the head of the workspace: instance descriptors and
+// counters, then per lane its work lists (each sized by max_walkers entries
+// and max_jobs instances).
 struct Head {
-  size_t insts, ctr, items, pairs, total;
+  size_t insts, ctr, total;
+  std::vector<size_t> items, pairs, list; // per lane
 };
 
 Head head_layout(const pt_server_opts &o) {
   Head h;
   size_t off = 0;
-  h.insts = off;
-  off = align_up(off + (size_t)o.max_jobs * sizeof(BatchInst));
-  h.ctr = off;
-  off = align_up(off + (size_t)o.max_jobs * kCtrWords * 4);
-  h.items = off;
-  off = align_up(off + (size_t)std::max(o.max_walkers, 1u) * sizeof(BatchItem));
-  h.pairs = off;
-  off = align_up(off + (size_t)std::max(o.max_walkers, 1u) * sizeof(uint2));
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  const size_t W = std::max(o.max_walkers, 1u);
+  h.insts = take((size_t)o.max_jobs * sizeof(BatchInst));
+  h.ctr = take((size_t)o.max_jobs * kCtrWords * 4);
+  for (uint32_t l = 0; l <= o.tiled_lanes; ++l) {
+    h.items.push_back(take(W * (l ? sizeof(BatchTileItem) : sizeof(BatchItem))));
+    h.pairs.push_back(l ? 0 : take(W * sizeof(uint2)));
+    h.list.push_back(take((size_t)o.max_jobs * 4));
+  }
   h.total = off;
   return h;
 }
@@ -113,9 +139,19 @@ pt_status check_opts(const pt_server_opts *o) {
     return fail(PT_EINVAL, "depth = %u: must be in [1, %u]", o->depth, kMaxDepth);
   if (o->cycle_sweeps < 1 || o->cycle_sweeps > 16)
     return fail(PT_EINVAL, "cycle_sweeps = %u: must be in [1, 16]", o->cycle_sweeps);
-  if (o->tiled_sweeps < 1 || o->tiled_sweeps > 4096)
-    return fail(PT_EINVAL, "tiled_sweeps = %u: must be in [1, 4096]", o->tiled_sweeps);
+  if (o->tiled_sweeps < 1 || o->tiled_sweeps > kMaxSweepsPerLaunch)
+    return fail(PT_EINVAL, "tiled_sweeps = %u: must be in [1, %u]", o->tiled_sweeps,
+                kMaxSweepsPerLaunch);
   return PT_OK;
+}
+
+// Tile rows for a tiled-lane lattice: the tallest power of two up to 256 rows
+// whose tile with halos for K sweeps fits the LDS budget (0 if none does).
+uint32_t tile_rows(const Geometry &g, uint32_t K) {
+  if (g.dim != 2 || g.plane % 32u || 2u * K > g.L / 2u) return 0;
+  for (uint32_t H = std::min<uint32_t>(256u, g.L / 2u); H >= 8u; H /= 2u)
+    if (tiled_lds_bytes(g, H, 2u * K) <= kTiledLds) return H;
+  return 0;
 }
 
 }  // namespace
@@ -126,8 +162,6 @@ struct pt_server {
   Head head{};
   BatchInst *d_insts = nullptr;
   uint32_t *d_ctr = nullptr;
-  BatchItem *d_items = nullptr;
-  uint2 *d_pairs = nullptr;
   uint8_t *arena_base = nullptr;
   Arena arena;
   std::vector<Lane> lanes; // [0] batched, [1 ..] tiled
@@ -137,12 +171,7 @@ struct pt_server {
   std::deque<uint64_t> pending;
   std::vector<uint64_t> inst_job; // instance slot -> job id (0 = free)
   std::vector<uint32_t> free_inst;
-  uint32_t inst_hi = 0;           // slots [0, inst_hi) have been used
-  uint64_t walkers = 0;           // resident batched-lane replicas
   uint64_t resident = 0;
-  bool members_dirty = true;
-  std::vector<Group> groups;
-  uint32_t n_pairs = 0;
   std::deque<pt_job_info> done_list;
   uint64_t next_id = 1, submitted = 0, finished = 0, attempts_finished = 0;
   uint64_t batched_cycles = 0, tiled_steps = 0;
@@ -168,6 +197,14 @@ hipEvent_t take_event(pt_server *sv) {
   return e;
 }
 
+// Sweeps the device runs for a job in one cycle of K (at most K, never past
+// its target or its next exchange point): the counters' rule, replayed.
+uint64_t cycle_n(const Job &j, uint32_t K) {
+  uint64_t n = std::min<uint64_t>(K, j.n_sweeps - j.queued);
+  if (j.every) n = std::min<uint64_t>(n, j.every - j.queued % j.every);
+  return n;
+}
+
 // Copy a finished job's observables to the host (copy stream, then wait).
 hipError_t collect(pt_server *sv, Job &j) {
   pt_ctx *c = j.ctx;
@@ -178,7 +215,7 @@ hipError_t collect(pt_server *sv, Job &j) {
     if (e == hipSuccess && n) e = hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToHost, sv->copy);
   };
   std::vector<int32_t> E(R), M(R);
-  std::vector<uint32_t> flags(4), ctr(kCtrWords, 0u);
+  std::vector<uint32_t> ctr(kCtrWords, 0u);
   j.wat.resize(R);
   j.att.resize(R);
   j.acc.resize(R);
@@ -187,8 +224,7 @@ hipError_t collect(pt_server *sv, Job &j) {
   D2H(M.data(), st.M, R * 4);
   D2H(j.att.data(), st.att, R * 4);
   D2H(j.acc.data(), st.acc, R * 4);
-  D2H(flags.data(), st.counter, 16);
-  if (j.lane == 0) D2H(ctr.data(), sv->d_ctr + (size_t)j.inst * kCtrWords, kCtrWords * 4);
+  D2H(ctr.data(), sv->d_ctr + (size_t)j.inst * kCtrWords, kCtrWords * 4);
   j.n_records = records_between(c->cfg.record_every, 0, j.n_sweeps);
   j.Es.resize((size_t)j.n_records * R);
   j.Ms.resize((size_t)j.n_records * R);
@@ -196,16 +232,16 @@ hipError_t collect(pt_server *sv, Job &j) {
   D2H(j.Ms.data(), st.M_series, j.Ms.size() * 4);
   if (j.flags & PT_JOB_KEEP_SPINS) {
     j.bits.resize(R * N / 32);
-    D2H(j.bits.data(), st.spins[c->cur], j.bits.size() * 4);
+    D2H(j.bits.data(), st.spins[j.cur], j.bits.size() * 4);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(sv->copy);
   if (e != hipSuccess) return e;
   j.sweeps_done = j.n_sweeps;
   j.exchanges_done = records_between(j.every, 0, j.n_sweeps);
-  if (j.lane == 0 && (ctr[kCtrSweeps] != j.n_sweeps || ctr[kCtrExchanges] != j.exchanges_done ||
-                      ctr[kCtrRecords] != j.n_records))
+  // the device's schedule must be the one the host replayed
+  if (ctr[kCtrSweeps] != j.n_sweeps || ctr[kCtrExchanges] != j.exchanges_done ||
+      ctr[kCtrRecords] != j.n_records || ctr[kCtrCur] != j.cur || ctr[kCtrActive] != 0u)
     return hipErrorUnknown;
-  if (j.lane != 0 && (c->sweeps != j.n_sweeps || c->n_records != j.n_records)) return hipErrorUnknown;
   for (size_t k = 0; k < R; ++k)
     if (j.wat[k] >= R) return hipErrorUnknown;
   j.E_slot.resize(R);
@@ -222,15 +258,12 @@ pt_status retire(pt_server *sv, uint64_t id) {
   if (collect(sv, j) != hipSuccess)
     return sv_fail(sv, hipErrorUnknown, "collecting a finished job's results");
   sv->arena.release(j.off, j.bytes);
-  if (j.lane == 0) {
-    sv->inst_job[j.inst] = 0;
-    sv->free_inst.push_back(j.inst);
-    sv->walkers -= j.cfg.R;
-  } else {
-    Lane &ln = sv->lanes[j.lane];
-    ln.jobs.erase(std::find(ln.jobs.begin(), ln.jobs.end(), id));
-    ln.work -= (uint64_t)j.cfg.R * j.ctx_N();
-  }
+  sv->inst_job[j.inst] = 0;
+  sv->free_inst.push_back(j.inst);
+  Lane &ln = sv->lanes[j.lane];
+  ln.jobs.erase(std::find(ln.jobs.begin(), ln.jobs.end(), id));
+  ln.slots -= (uint64_t)j.cfg.R * (j.lane ? j.tiles : 1u);
+  ln.work -= (uint64_t)j.cfg.R * j.sites();
   pt_destroy(j.ctx);
   j.ctx = nullptr;
   j.done = true;
@@ -269,153 +302,160 @@ pt_status drain_completed(pt_server *sv, uint32_t *n_ret) {
   return PT_OK;
 }
 
-// Admit queued jobs in arrival order while the head of the queue fits.
+// Admit queued jobs in arrival order while the head of the queue fits: an
+// instance slot, its lane's walker (or walker-tile) slots and arena memory.
 pt_status admit(pt_server *sv) {
   while (!sv->pending.empty()) {
     Job &j = *sv->jobs.at(sv->pending.front());
-    const bool batched = j.lane == 0;
-    if (sv->resident >= sv->o.max_jobs) break;
-    if (batched && (sv->free_inst.empty() || sv->walkers + j.cfg.R > sv->o.max_walkers)) break;
+    if (sv->resident >= sv->o.max_jobs || sv->free_inst.empty()) break;
+    uint32_t lane = 0;
+    if (j.tiles) {
+      // the tiled lane with the least resident work
+      lane = 1;
+      for (uint32_t l = 2; l < sv->lanes.size(); ++l)
+        if (sv->lanes[l].work < sv->lanes[lane].work) lane = l;
+    }
+    Lane &ln = sv->lanes[lane];
+    const uint64_t slots = (uint64_t)j.cfg.R * (lane ? j.tiles : 1u);
+    if (ln.slots + slots > sv->o.max_walkers) break;
     size_t off = 0;
     if (!sv->arena.alloc(j.bytes, &off)) break;
     sv->pending.pop_front();
     j.off = off;
-    Lane *ln = &sv->lanes[0];
-    if (!batched) {
-      // the tiled lane with the least resident work
-      uint32_t best = 1;
-      for (uint32_t l = 2; l < sv->lanes.size(); ++l)
-        if (sv->lanes[l].work < sv->lanes[best].work) best = l;
-      j.lane = best;
-      ln = &sv->lanes[best];
-    }
-    pt_status s = ctx_create(&j.cfg, ln->s, sv->arena_base + off, j.bytes, false, &j.ctx);
+    j.lane = lane;
+    pt_status s = ctx_create(&j.cfg, ln.s, sv->arena_base + off, j.bytes, false, &j.ctx);
     if (s != PT_OK) {
       sv->poisoned = true;
       return s;
     }
-    if (!batched && j.ctx->d.geo.dim == 2) {
-      // Tiled lanes run several jobs at once, so a job's own grid need not
-      // fill the chip: tall tiles (fewest recomputed halo rows) and 5 sweeps
-      // per launch; the context's automatic plan stays if this one is invalid.
-      pt_plan p{};
-      p.mode = PT_PLAN_TILED;
-      p.tile_planes = std::min<uint32_t>(j.ctx->d.geo.L, 256u);
-      p.sweeps_per_launch = 5;
-      p.block_threads = p.tile_planes >= 256u ? 1024u : 512u;
-      (void)pt_set_plan(j.ctx, &p);
-    }
     j.admitted = now_s(sv->t0);
     ++sv->resident;
-    if (batched) {
-      j.inst = sv->free_inst.back();
-      sv->free_inst.pop_back();
-      sv->inst_job[j.inst] = j.id;
-      sv->inst_hi = std::max(sv->inst_hi, j.inst + 1u);
-      sv->walkers += j.cfg.R;
-      const BatchInst I = batch_inst(j.ctx, sv->d_ctr + (size_t)j.inst * kCtrWords);
-      uint32_t ctr[kCtrWords] = {0u};
-      ctr[kCtrTarget] = (uint32_t)j.n_sweeps;
-      ctr[kCtrActive] = 1u;
-      ctr[kCtrEvery] = j.every;
-      auto hi = bytes_of(&I, 1), hc = bytes_of(ctr, kCtrWords);
-      hipError_t e = hipMemcpyAsync(sv->d_insts + j.inst, hi->data(), hi->size(), hipMemcpyHostToDevice, ln->s);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(sv->d_ctr + (size_t)j.inst * kCtrWords, hc->data(), hc->size(),
-                           hipMemcpyHostToDevice, ln->s);
-      if (e != hipSuccess) return sv_fail(sv, e, "job admission");
-      ln->staged.push_back(hi);
-      ln->staged.push_back(hc);
-      sv->members_dirty = true;
-    } else {
-      ln->jobs.push_back(j.id);
-      ln->work += (uint64_t)j.cfg.R * j.ctx_N();
-    }
+    j.inst = sv->free_inst.back();
+    sv->free_inst.pop_back();
+    sv->inst_job[j.inst] = j.id;
+    ln.jobs.push_back(j.id);
+    ln.slots += slots;
+    ln.work += (uint64_t)j.cfg.R * j.sites();
+    ln.dirty = true;
+    // descriptor and counters, queued on the lane after its earlier work
+    const BatchInst I = batch_inst(j.ctx, sv->d_ctr + (size_t)j.inst * kCtrWords);
+    uint32_t ctr[kCtrWords] = {0u};
+    ctr[kCtrTarget] = (uint32_t)j.n_sweeps;
+    ctr[kCtrActive] = 1u;
+    ctr[kCtrEvery] = j.every;
+    ctr[kCtrCur] = 0u;
+    ctr[kCtrTiles] = lane ? j.tiles : 0u;
+    auto hi = bytes_of(&I, 1), hc = bytes_of(ctr, kCtrWords);
+    hipError_t e = hipMemcpyAsync(sv->d_insts + j.inst, hi->data(), hi->size(), hipMemcpyHostToDevice, ln.s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(sv->d_ctr + (size_t)j.inst * kCtrWords, hc->data(), hc->size(),
+                         hipMemcpyHostToDevice, ln.s);
+    if (e != hipSuccess) return sv_fail(sv, e, "job admission");
+    ln.staged.push_back(hi);
+    ln.staged.push_back(hc);
   }
   return PT_OK;
 }
 
-// Rebuild the batched lane's work lists from the resident, unfinished jobs.
-pt_status rebuild_members(pt_server *sv) {
-  Lane &ln = sv->lanes[0];
+// Rebuild a lane's work lists from its resident, unfinished jobs.
+pt_status rebuild_lane(pt_server *sv, uint32_t l) {
+  Lane &ln = sv->lanes[l];
   std::map<std::pair<uint32_t, uint32_t>, std::vector<uint64_t>> by_geo;
-  for (uint32_t i = 0; i < sv->inst_hi; ++i) {
-    const uint64_t id = sv->inst_job[i];
-    if (!id) continue;
+  std::vector<uint32_t> list;
+  for (uint64_t id : ln.jobs) {
     Job &j = *sv->jobs.at(id);
     if (j.queued >= j.n_sweeps) continue;
     by_geo[{j.ctx->d.geo.dim, j.ctx->d.geo.L}].push_back(id);
+    list.push_back(j.inst);
   }
   std::vector<BatchItem> items;
+  std::vector<BatchTileItem> titems;
   std::vector<uint2> pairs;
-  sv->groups.clear();
+  ln.groups.clear();
   for (auto &kv : by_geo) {
     Group G;
     G.g = sv->jobs.at(kv.second[0])->ctx->d.geo;
     for (uint64_t id : kv.second) G.max_R = std::max(G.max_R, sv->jobs.at(id)->cfg.R);
-    const auto wt = batch_decomposition(G.g, G.max_R);
-    G.W = wt.first;
-    G.threads = wt.second;
-    G.item_off = (uint32_t)items.size();
-    for (uint64_t id : kv.second) {
-      const Job &j = *sv->jobs.at(id);
-      for (uint32_t w0 = 0; w0 < j.cfg.R; w0 += G.W) items.push_back({j.inst, w0});
-      for (uint32_t k = 0; k + 1 < j.cfg.R; ++k) pairs.push_back(make_uint2(j.inst, k));
+    if (l == 0) {
+      const auto wt = batch_decomposition(G.g, G.max_R);
+      G.W = wt.first;
+      G.threads = wt.second;
+      G.item_off = (uint32_t)items.size();
+      for (uint64_t id : kv.second) {
+        const Job &j = *sv->jobs.at(id);
+        for (uint32_t w0 = 0; w0 < j.cfg.R; w0 += G.W) items.push_back({j.inst, w0});
+        for (uint32_t k = 0; k + 1 < j.cfg.R; ++k) pairs.push_back(make_uint2(j.inst, k));
+      }
+      G.n_items = (uint32_t)items.size() - G.item_off;
+    } else {
+      const Job &j0 = *sv->jobs.at(kv.second[0]);
+      G.H = G.g.L / j0.tiles;
+      G.threads = G.H >= 256u ? 1024u : 512u;
+      G.item_off = (uint32_t)titems.size();
+      for (uint64_t id : kv.second) {
+        const Job &j = *sv->jobs.at(id);
+        for (uint32_t w = 0; w < j.cfg.R; ++w)
+          for (uint32_t t = 0; t < j.tiles; ++t) titems.push_back({j.inst, w, t, 0u});
+      }
+      G.n_items = (uint32_t)titems.size() - G.item_off;
     }
-    G.n_items = (uint32_t)items.size() - G.item_off;
-    sv->groups.push_back(G);
+    ln.groups.push_back(G);
   }
   // largest lattices first, so the longest workgroups start first
-  std::sort(sv->groups.begin(), sv->groups.end(), [](const Group &x, const Group &y) {
+  std::sort(ln.groups.begin(), ln.groups.end(), [](const Group &x, const Group &y) {
     return x.g.N * (x.g.dim == 3 ? 4u : 1u) > y.g.N * (y.g.dim == 3 ? 4u : 1u);
   });
-  sv->n_pairs = (uint32_t)pairs.size();
+  ln.n_pairs = (uint32_t)pairs.size();
+  ln.n_list = (uint32_t)list.size();
   hipError_t e = hipSuccess;
-  if (!items.empty()) {
-    auto hv = bytes_of(items.data(), items.size());
-    e = hipMemcpyAsync(sv->d_items, hv->data(), hv->size(), hipMemcpyHostToDevice, ln.s);
+  auto up = [&](void *dst, auto &v) {
+    if (e != hipSuccess || v.empty()) return;
+    auto hv = bytes_of(v.data(), v.size());
+    e = hipMemcpyAsync(dst, hv->data(), hv->size(), hipMemcpyHostToDevice, ln.s);
     ln.staged.push_back(hv);
-  }
-  if (e == hipSuccess && !pairs.empty()) {
-    auto hv = bytes_of(pairs.data(), pairs.size());
-    e = hipMemcpyAsync(sv->d_pairs, hv->data(), hv->size(), hipMemcpyHostToDevice, ln.s);
-    ln.staged.push_back(hv);
-  }
-  if (e != hipSuccess) return sv_fail(sv, e, "batched work lists");
-  sv->members_dirty = false;
+  };
+  up(ln.d_items, items);
+  up(ln.d_titems, titems);
+  up(ln.d_pairs, pairs);
+  up(ln.d_list, list);
+  if (e != hipSuccess) return sv_fail(sv, e, "lane work lists");
+  ln.dirty = false;
   return PT_OK;
 }
 
-// Queue one cycle of the batched lane; false if it has nothing to run.
-pt_status batched_cycle(pt_server *sv, bool *queued) {
+// Queue one cycle of lane l; *queued = false if it has nothing to run.
+pt_status lane_cycle(pt_server *sv, uint32_t l, bool *queued) {
   *queued = false;
-  if (sv->members_dirty) {
-    pt_status s = rebuild_members(sv);
+  Lane &ln = sv->lanes[l];
+  if (ln.dirty) {
+    pt_status s = rebuild_lane(sv, l);
     if (s != PT_OK) return s;
   }
-  if (sv->groups.empty()) return PT_OK;
-  Lane &ln = sv->lanes[0];
-  const uint32_t K = sv->o.cycle_sweeps;
+  if (ln.groups.empty()) return PT_OK;
+  const uint32_t K = ln.K;
   hipError_t e = hipSuccess;
-  for (const Group &G : sv->groups)
-    if (e == hipSuccess)
-      e = launch_batch_sweep(sv->d_insts, sv->d_items + G.item_off, G.n_items, G.g, G.W, G.threads, K, ln.s);
-  if (e == hipSuccess && sv->n_pairs) e = launch_batch_exchange(sv->d_insts, sv->d_pairs, sv->n_pairs, K, ln.s);
-  if (e == hipSuccess) e = launch_batch_advance(sv->d_insts, sv->inst_hi, K, ln.s);
-  if (e != hipSuccess) return sv_fail(sv, e, "batched cycle launch");
+  for (const Group &G : ln.groups) {
+    if (e != hipSuccess) break;
+    e = l == 0 ? launch_batch_sweep(sv->d_insts, ln.d_items + G.item_off, G.n_items, G.g, G.W,
+                                    G.threads, K, ln.s)
+               : launch_batch_tiled(sv->d_insts, ln.d_titems + G.item_off, G.n_items, G.g, G.H,
+                                    G.threads, K, ln.s);
+  }
+  if (e == hipSuccess && l == 0 && ln.n_pairs)
+    e = launch_batch_exchange(sv->d_insts, ln.d_pairs, ln.n_pairs, K, ln.s);
+  if (e == hipSuccess) e = launch_batch_advance(sv->d_insts, ln.d_list, ln.n_list, K, ln.s);
+  if (e != hipSuccess) return sv_fail(sv, e, "lane cycle launch");
   Step st;
   // the device's schedule of this cycle, replayed on the host
-  for (uint32_t i = 0; i < sv->inst_hi; ++i) {
-    const uint64_t id = sv->inst_job[i];
-    if (!id) continue;
+  for (uint64_t id : ln.jobs) {
     Job &j = *sv->jobs.at(id);
     if (j.queued >= j.n_sweeps) continue;
-    uint64_t n = std::min<uint64_t>(K, j.n_sweeps - j.queued);
-    if (j.every) n = std::min<uint64_t>(n, j.every - j.queued % j.every);
+    const uint64_t n = cycle_n(j, K);
     j.queued += n;
+    if (n && j.tiles > 1u && l) j.cur ^= 1u;
     if (j.queued == j.n_sweeps) {
       st.finishing.push_back(id);
-      sv->members_dirty = true;
+      ln.dirty = true;
     }
   }
   st.ev = take_event(sv);
@@ -424,40 +464,8 @@ pt_status batched_cycle(pt_server *sv, bool *queued) {
   st.keep = std::move(ln.staged);
   ln.staged.clear();
   ln.q.push_back(std::move(st));
-  ++sv->batched_cycles;
-  *queued = true;
-  return PT_OK;
-}
-
-// Queue one step of a tiled lane: every resident job there advances by up to
-// tiled_sweeps sweeps.
-pt_status tiled_step(pt_server *sv, uint32_t l, bool *queued) {
-  *queued = false;
-  Lane &ln = sv->lanes[l];
-  Step st;
-  bool any = false;
-  for (uint64_t id : ln.jobs) {
-    Job &j = *sv->jobs.at(id);
-    if (j.queued >= j.n_sweeps) continue;
-    const uint32_t n = (uint32_t)std::min<uint64_t>(sv->o.tiled_sweeps, j.n_sweeps - j.queued);
-    pt_status s = ctx_advance(j.ctx, n, j.every);
-    if (s != PT_OK) {
-      sv->poisoned = true;
-      return s;
-    }
-    j.queued += n;
-    any = true;
-    if (j.queued == j.n_sweeps) st.finishing.push_back(id);
-  }
-  if (!any) return PT_OK;
-  st.ev = take_event(sv);
-  if (!st.ev) return sv_fail(sv, hipErrorOutOfMemory, "event creation");
-  hipError_t e = hipEventRecord(st.ev, ln.s);
-  if (e != hipSuccess) return sv_fail(sv, e, "step event");
-  st.keep = std::move(ln.staged);
-  ln.staged.clear();
-  ln.q.push_back(std::move(st));
-  ++sv->tiled_steps;
+  if (l == 0) ++sv->batched_cycles;
+  else ++sv->tiled_steps;
   *queued = true;
   return PT_OK;
 }
@@ -467,7 +475,7 @@ pt_status top_up(pt_server *sv, bool *queued_any) {
   for (uint32_t l = 0; l < sv->lanes.size(); ++l) {
     while (sv->lanes[l].q.size() < sv->o.depth) {
       bool q = false;
-      pt_status s = l == 0 ? batched_cycle(sv, &q) : tiled_step(sv, l, &q);
+      pt_status s = lane_cycle(sv, l, &q);
       if (s != PT_OK) return s;
       if (!q) break;
       *queued_any = true;
@@ -501,13 +509,22 @@ pt_status pt_server_create(const pt_server_opts *opts, void *d_workspace, size_t
   sv->head = h;
   sv->d_insts = (BatchInst *)(sv->base + h.insts);
   sv->d_ctr = (uint32_t *)(sv->base + h.ctr);
-  sv->d_items = (BatchItem *)(sv->base + h.items);
-  sv->d_pairs = (uint2 *)(sv->base + h.pairs);
   sv->arena_base = sv->base + h.total;
   sv->arena.reset(ws_bytes - h.total, kAlign);
   sv->inst_job.assign(opts->max_jobs, 0);
   for (uint32_t i = opts->max_jobs; i-- > 0;) sv->free_inst.push_back(i);
   sv->lanes.resize(1 + opts->tiled_lanes);
+  for (uint32_t l = 0; l < sv->lanes.size(); ++l) {
+    Lane &ln = sv->lanes[l];
+    if (l == 0) {
+      ln.d_items = (BatchItem *)(sv->base + h.items[l]);
+      ln.d_pairs = (uint2 *)(sv->base + h.pairs[l]);
+    } else {
+      ln.d_titems = (BatchTileItem *)(sv->base + h.items[l]);
+    }
+    ln.d_list = (uint32_t *)(sv->base + h.list[l]);
+    ln.K = l == 0 ? opts->cycle_sweeps : opts->tiled_sweeps;
+  }
   hipError_t e = hipSuccess;
   for (Lane &ln : sv->lanes)
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&ln.s, hipStreamNonBlocking);
@@ -565,9 +582,21 @@ pt_status pt_server_submit(pt_server *sv, const pt_config *cfg, uint64_t n_sweep
   g.L = cfg->L;
   g.R = cfg->R;
   g.N = cfg->L * cfg->L * (dim == 3 ? cfg->L : 1u);
-  j->lane = batch_fits(g) ? 0u : 1u;
-  if (j->lane == 0 && cfg->R > sv->o.max_walkers)
-    return fail(PT_ENOMEM, "job has %u replicas, the batched lane holds %u", cfg->R, sv->o.max_walkers);
+  g.gpr = cfg->L / 8u;
+  g.rows = dim == 3 ? cfg->L : 1u;
+  g.plane = cfg->L * g.rows;
+  if (!batch_fits(g)) {
+    // a tiled lane: tiles of H rows with halos for tiled_sweeps sweeps
+    const uint32_t H = tile_rows(g, sv->o.tiled_sweeps);
+    if (!H)
+      return fail(PT_EUNSUPPORTED, "no tile of this lattice fits one workgroup's LDS with halos "
+                  "for %u sweeps", sv->o.tiled_sweeps);
+    j->tiles = g.L / H;
+  }
+  const uint64_t slots = (uint64_t)cfg->R * (j->tiles ? j->tiles : 1u);
+  if (slots > sv->o.max_walkers)
+    return fail(PT_ENOMEM, "job needs %llu walker slots, a lane holds %u", (unsigned long long)slots,
+                sv->o.max_walkers);
   if (job_id) *job_id = j->id;
   sv->pending.push_back(j->id);
   sv->jobs[j->id] = std::move(j);
@@ -626,7 +655,7 @@ pt_status pt_server_result(const pt_server *sv, uint64_t job_id, pt_obs *obs) {
   if (it == sv->jobs.end()) return fail(PT_EINVAL, "no job %llu", (unsigned long long)job_id);
   const Job &j = *it->second;
   if (!j.done) return fail(PT_ESTATE, "job %llu has not finished", (unsigned long long)job_id);
-  const size_t R = j.cfg.R, N = j.ctx_N();
+  const size_t R = j.cfg.R, N = j.sites();
   if (obs->spins && !(j.flags & PT_JOB_KEEP_SPINS))
     return fail(PT_EINVAL, "job %llu was submitted without PT_JOB_KEEP_SPINS", (unsigned long long)job_id);
   if (obs->spins && obs->spins_slot != PT_ALL_SLOTS && obs->spins_slot >= R)
@@ -677,7 +706,8 @@ pt_status pt_server_stats_get(const pt_server *sv, pt_server_stats *out) {
   out->arena_bytes = sv->arena.size();
   out->arena_used = sv->arena.used();
   out->arena_peak = sv->arena.peak();
-  out->walkers_resident = sv->walkers;
+  out->walkers_resident = 0;
+  for (const Lane &ln : sv->lanes) out->walkers_resident += ln.slots;
   out->batched_cycles = sv->batched_cycles;
   out->tiled_steps = sv->tiled_steps;
   out->attempts_finished = sv->attempts_finished;

@@ -365,8 +365,8 @@ class Batch:
         self.close()
 
 
-def server_opts(max_jobs=1024, max_walkers=32768, tiled_lanes=2, depth=2, cycle_sweeps=10,
-                tiled_sweeps=10) -> pt_server_opts:
+def server_opts(max_jobs=1024, max_walkers=32768, tiled_lanes=1, depth=2, cycle_sweeps=10,
+                tiled_sweeps=5) -> pt_server_opts:
     return pt_server_opts(int(max_jobs), int(max_walkers), int(tiled_lanes), int(depth),
                           int(cycle_sweeps), int(tiled_sweeps))
 

@@ -21,6 +21,8 @@ JOBS = [
     (0, 256, 5, 25, 5, 1, 0.0, True),
     (0, 512, 4, 24, 4, 2, 0.0, True),     # batched lane, one walker per workgroup
     (0, 1024, 3, 20, 10, 1, 0.0, False),  # tiled lane
+    (0, 1024, 5, 17, 5, 1, 0.0, True),    # tiled lane, batched with the one above
+    (0, 2048, 2, 12, 3, 2, 0.0, True),    # tiled lane, 64-row tiles
     (1, 8, 24, 70, 1, 1, 0.0, True),
     (1, 16, 10, 40, 3, 1, 0.0, False),
     (1, 32, 6, 30, 10, 5, 0.0, True),

@@ -1305,6 +1305,41 @@ __device__ __forceinline__ uint32_t bit_at(const uint32_t *words, uint32_t i) {
 }
 
 // Full recount of E_int and M of every walker from spin buffer cur.
+// Word-level recount for rows of at least 32 sites: one thread per packed word
+// (32 sites of one row); unsatisfied bonds to the +x, +y (, +z) neighbours are
+// popcounts of XORs with the shifted neighbour words (and the couplings), and
+// E_int = sum over bonds (2 [unsatisfied] - 1), M = 32 - 2 popcount per word.
+template <int DIM>
+__global__ void k_recount_words(DevState st, Geometry G, uint32_t cur) {
+  const uint32_t w = blockIdx.y;
+  const uint32_t nwr = G.N >> 5, wpr = G.L >> 5, wpp = (G.L * G.L) >> 5;
+  const uint32_t *sp = st.spins[cur] + (size_t)w * nwr;
+  int e = 0, m = 0;
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nwr; q += gridDim.x * blockDim.x) {
+    const uint32_t a = sp[q];
+    const uint32_t rs = q - q % wpr;                           // first word of the row
+    const uint32_t nx = sp[rs + (q - rs + 1u) % wpr];          // word holding site x+32
+    const uint32_t right = (a >> 1) | (nx << 31);              // +x neighbours of the 32 sites
+    const uint32_t ps = q - q % wpp;                           // first word of the plane
+    const uint32_t down = sp[ps + (q - ps + wpr) % wpp];       // +y neighbours
+    uint32_t ux = a ^ right, uy = a ^ down;
+    if (DIM == 3) {
+      ux ^= st.bonds[q];
+      uy ^= st.bonds[nwr + q];
+      const uint32_t uz = a ^ sp[(q + wpp) % nwr] ^ st.bonds[2u * nwr + q]; // +z neighbours
+      e += 2 * (int)__builtin_popcount(uz) - 32;
+    }
+    e += 2 * (int)(__builtin_popcount(ux) + __builtin_popcount(uy)) - 64;
+    m += 32 - 2 * (int)__builtin_popcount(a);
+  }
+  e = wave_sum(e);
+  m = wave_sum(m);
+  if ((threadIdx.x & 63u) == 0u) {
+    atomicAdd(&st.E[w], e);
+    atomicAdd(&st.M[w], m);
+  }
+}
+
 template <int DIM>
 __global__ void k_recount(DevState st, Geometry G, uint32_t cur) {
   const uint32_t w = blockIdx.y;
@@ -1455,6 +1490,15 @@ hipError_t launch_reset(const DevState &st, const Geometry &g, hipStream_t strea
 
 hipError_t launch_recount(const DevState &st, const Geometry &g, uint32_t cur,
                           hipStream_t stream) {
+  if (g.L >= 32u) {
+    // rows of whole packed words: one thread per word
+    const uint32_t bx = std::min<uint32_t>(((g.N >> 5) + 255u) / 256u, 1024u);
+    if (g.dim == 3)
+      hipLaunchKernelGGL(k_recount_words<3>, dim3(bx, g.R), dim3(256), 0, stream, st, g, cur);
+    else
+      hipLaunchKernelGGL(k_recount_words<2>, dim3(bx, g.R), dim3(256), 0, stream, st, g, cur);
+    return hipGetLastError();
+  }
   const uint32_t bx = std::min<uint32_t>((g.N + 255u) / 256u, 1024u);
   if (g.dim == 3)
     hipLaunchKernelGGL(k_recount<3>, dim3(bx, g.R), dim3(256), 0, stream, st, g, cur);

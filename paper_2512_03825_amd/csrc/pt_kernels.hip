@@ -884,11 +884,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
     const bool do_ex = a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u;
     if (tid == 0u) {
       // post this slot's energy first, so the partner's wait does not include
-      // the record stores below
+      // the record stores below.  The 64-bit word carries the tag and the
+      // energy together and the partner reads nothing else of ours, so relaxed
+      // agent-scope atomics suffice: no L2 write-back on the post and no L2
+      // invalidate per poll.
       uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * R;
       const uint64_t tag = (uint64_t)(e + 1u) << 32;
       if (do_ex)
-        __hip_atomic_store(&mb[slot], tag | (uint32_t)E, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&mb[slot], tag | (uint32_t)E, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (do_rec) {
         a.st.E_series[(size_t)rec * R + slot] = E;
         a.st.M_series[(size_t)rec * R + slot] = M;
@@ -909,7 +912,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
           const uint64_t sat_lo = a.st.swap_sat[2u * lo], sat_hi = a.st.swap_sat[2u * lo + 1u];
           uint64_t v = 0;
           for (uint32_t n = 0;; ++n) {
-            v = __hip_atomic_load(&mb[partner], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+            v = __hip_atomic_load(&mb[partner], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((v & 0xFFFFFFFF00000000ull) == tag) break;
             if (n >= a.spin_limit ||
                 __hip_atomic_load(&a.st.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {

@@ -449,7 +449,7 @@ def main():
         p = sim.plan()
         mode = {"auto": p["mode"], "fused": pt.PT_PLAN_FUSED, "tiled": pt.PT_PLAN_TILED,
                 "persistent": pt.PT_PLAN_PERSISTENT, "lanes": pt.PT_PLAN_LANES}[args.plan]
-        if args.tile_planes or args.sweeps_per_launch:
+        if args.plan == "auto" and (args.tile_planes or args.sweeps_per_launch):
             mode = pt.PT_PLAN_TILED
         sim.set_plan(mode, args.tile_planes or p["tile_planes"],
                      args.sweeps_per_launch or p["sweeps_per_launch"], args.threads or p["block_threads"])
@@ -498,8 +498,10 @@ def main():
     hbm_bytes = w.R * ((w.L + halo_planes) * plane_bits + w.L * plane_bits) / 8
     if w.dim == 3:
         hbm_bytes += 3 * w.sites / 8 * (tiles if tiles > 1 else 1)  # packed couplings, read once per tile
+    split = plan["mode"] == pt.PT_PLAN_PERSISTENT and w.dim == 3 and plan["tile_planes"] == w.L // 2
     kernel = {pt.PT_PLAN_TILED: "k_tiled_n" if w.dim == 2 else "k_tiled", pt.PT_PLAN_FUSED: "k_fused",
-              pt.PT_PLAN_PERSISTENT: "k_persist", pt.PT_PLAN_LANES: "k_lanes"}[plan["mode"]]
+              pt.PT_PLAN_PERSISTENT: "k_persist_split" if split else "k_persist",
+              pt.PT_PLAN_LANES: "k_lanes"}[plan["mode"]]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 VALU lane slots)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": measured_traffic(kernel, w.name, plan, per_launch), "kernel": kernel,
@@ -509,6 +511,11 @@ def main():
                 "attempts_per_s_in_kernel": per_launch * w.attempts_per_sweep / (avg_ms * 1e-3),
                 "hbm_algorithmic_bytes_per_launch": int(hbm_bytes),
                 "hbm_algorithmic_GBps": round(hbm_bytes / (avg_ms * 1e-3) / 1e9, 1)}
+    if split:
+        # two workgroups per walker post their boundary planes and energy shares
+        # every sweep (64-bit tagged words) and read the sibling's
+        post_bytes = 2 * 8 * (w.L * w.L // 8 + 2)
+        roofline["boundary_post_bytes_per_launch"] = 2 * post_bytes * w.R * per_launch
 
     if args.copy_calibration:
         a = torch.empty(64 << 20, dtype=torch.uint8, device="cuda:0").fill_(1)

@@ -165,7 +165,8 @@ Layout layout(const pt_config *cfg, const Derived &d) {
   l.Es = take((size_t)cfg->max_records * R * 4);
   l.Ms = take((size_t)cfg->max_records * R * 4);
   l.counter = take(16);
-  l.mailbox = take(4 * R * 8);
+  l.mailbox = take(8 * R * 8);
+  l.halo = take(split_halo_words(g) * 8);
   l.field = take(R * kFieldDigits * 8);
   l.fsign = take(R * 4);
   l.total = o;
@@ -228,6 +229,13 @@ pt_status device_fail(pt_ctx *c, hipError_t e, const char *what) {
   return fail(PT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
+// Workgroups per walker of a persistent plan: two when 3D and tile_planes = L/2.
+uint32_t persist_parts(const Geometry &g, const pt_plan &p) {
+  return (p.mode == PT_PLAN_PERSISTENT && g.dim == 3 && g.L >= 16u && g.L <= 32u &&
+          p.tile_planes == g.L / 2u)
+             ? 2u : 1u;
+}
+
 pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
   const Geometry &g = c->d.geo;
   if (p.mode == PT_PLAN_LANES) { // block size follows R
@@ -250,13 +258,20 @@ pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
   if (p.mode == PT_PLAN_PERSISTENT) {
     if (c->cfg.h != 0.0 && g.dim == 2)
       return fail(PT_EINVAL, "the persistent plan exchanges energies only; it needs h = 0");
-    if (persist_lds_bytes(g) > max_lds_bytes())
-      return fail(PT_EINVAL, "persistent plan needs %zu bytes of LDS per walker (max %zu)",
-                  persist_lds_bytes(g), max_lds_bytes());
-    const uint32_t cap = persist_max_workgroups(g, p.block_threads);
-    if (cap < g.R)
+    if (p.tile_planes != 0u && p.tile_planes != g.L && p.tile_planes != g.L / 2u)
+      return fail(PT_EINVAL, "persistent plan: tile_planes = %u must be L (one workgroup per walker) "
+                  "or L/2 (two, 3D)", p.tile_planes);
+    const uint32_t parts = persist_parts(g, p);
+    if (p.tile_planes == g.L / 2u && parts != 2u)
+      return fail(PT_EINVAL, "persistent plan with two workgroups per walker: 3D with 16 <= L <= 32 only");
+    const size_t lds = persist_lds_bytes(g, parts);
+    if (lds > max_lds_bytes())
+      return fail(PT_EINVAL, "persistent plan needs %zu bytes of LDS per workgroup (max %zu)", lds,
+                  max_lds_bytes());
+    const uint32_t cap = persist_max_workgroups(g, p.block_threads, parts);
+    if (cap < parts * g.R)
       return fail(PT_EINVAL, "persistent plan needs %u co-resident workgroups, the device holds %u",
-                  g.R, cap);
+                  parts * g.R, cap);
     return PT_OK;
   }
   if (p.mode != PT_PLAN_TILED) return fail(PT_EINVAL, "unknown plan mode %u", p.mode);
@@ -291,6 +306,17 @@ pt_plan auto_plan(const pt_ctx *c) {
     p.tile_planes = g.L;
     p.sweeps_per_launch = 1;
     return p;
+  }
+  // 3D walkers whose halves fit a workgroup's LDS, and enough compute units
+  // for two workgroups per walker: each walker split over two co-resident
+  // workgroups for a whole run, exchanges decided pairwise.
+  if (g.dim == 3 && g.R >= 64) {
+    pt_plan q{};
+    q.mode = PT_PLAN_PERSISTENT;
+    q.block_threads = 512; // 4 groups per item at L = 32 (measured best against 768, 1024)
+    q.tile_planes = g.L / 2u;
+    q.sweeps_per_launch = 1;
+    if (check_plan(c, q) == PT_OK) return q;
   }
   // Many walkers whose lattices fit a workgroup's LDS: one co-resident workgroup
   // per walker for a whole run, exchanges decided pairwise (no launch per sweep).
@@ -407,8 +433,8 @@ pt_status ctx_advance(pt_ctx *c, uint32_t n, uint32_t every) {
                 ? launch_fused(c->st, g, c->keys, c->cur, c->plan.block_threads, sch, c->stream)
             : c->plan.mode == PT_PLAN_LANES
                 ? launch_lanes(c->st, g, c->keys, c->cur, sch, c->stream)
-                : launch_persist(c->st, g, c->keys, c->cur, c->plan.block_threads, sch,
-                                 kSpinLimit, c->stream);
+                : launch_persist(c->st, g, c->keys, c->cur, c->plan.block_threads,
+                                 persist_parts(g, c->plan), sch, kSpinLimit, c->stream);
     } else {
       nsw = std::min(left, c->plan.sweeps_per_launch);
       if (every) nsw = std::min<uint32_t>(nsw, every - (uint32_t)(c->sweeps % every));
@@ -495,6 +521,7 @@ pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d
   st.M_series = (int32_t *)(base + l.Ms);
   st.counter = (uint32_t *)(base + l.counter);
   st.mailbox = (uint64_t *)(base + l.mailbox);
+  st.halo = (uint64_t *)(base + l.halo);
   st.staging = base + l.staging;
 
   hipError_t e = hipSuccess;
@@ -553,7 +580,7 @@ pt_status pt_set_plan(pt_ctx *ctx, const pt_plan *plan) {
   ctx->plan = *plan;
   if (ctx->plan.mode == PT_PLAN_FUSED || ctx->plan.mode == PT_PLAN_PERSISTENT ||
       ctx->plan.mode == PT_PLAN_LANES) {
-    ctx->plan.tile_planes = ctx->d.geo.L;
+    if (persist_parts(ctx->d.geo, ctx->plan) == 1u) ctx->plan.tile_planes = ctx->d.geo.L;
     ctx->plan.sweeps_per_launch = 1;
   }
   if (ctx->plan.mode == PT_PLAN_LANES) ctx->plan.block_threads = (ctx->d.geo.R + 63u) & ~63u;

@@ -33,7 +33,7 @@ struct Tables {
 
 struct Layout {
   size_t spins[2], bonds, staging, flip, swap_tab, swap_off, swap_D, swap_sat, wat, sof, E, M,
-      acc3, att, acc, Es, Ms, counter, mailbox, field, fsign, total;
+      acc3, att, acc, Es, Ms, counter, mailbox, halo, field, fsign, total;
 };
 
 struct Derived {

@@ -39,7 +39,9 @@ struct DevState {
   int32_t *E_series;   // [max_records][R] slot order
   int32_t *M_series;
   uint32_t *counter;   // [4] workgroup-arrival counter of the tiled sweep; [1] persistent-kernel abort flag
-  uint64_t *mailbox;   // [4][R] persistent kernel: (step + 1) << 32 | E_int posted by the holder of a slot
+  uint64_t *mailbox;   // [4][R][2] persistent kernels: (step + 1) << 32 | E_int (share) posted by the holder of a slot
+  uint64_t *halo;      // [2][R][2][split_post_words(L)] split persistent plan (3D): per sweep and part,
+                       // (sweep + 1) << 32 | word: boundary planes (bit-packed), then E_int and M shares
   uint8_t *staging;    // +-1 bytes uploaded by the host (only if the config uploads)
 };
 
@@ -142,11 +144,20 @@ hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, ui
 hipError_t launch_lanes(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
                         const Schedule &sch, hipStream_t stream);
 size_t lanes_lds_bytes(const Geometry &g);
-// One co-resident workgroup per walker for the whole launch; exchange decisions
-// are taken pairwise through per-slot mailboxes (cooperative launch).
+// One co-resident workgroup per walker (parts = 1), or in 3D two per walker,
+// each holding half of the z-planes (parts = 2), for the whole launch; exchange
+// decisions are taken pairwise through per-slot mailboxes (cooperative launch).
 hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
-                          uint32_t threads, const Schedule &sch, uint32_t spin_limit,
-                          hipStream_t stream);
+                          uint32_t threads, uint32_t parts, const Schedule &sch,
+                          uint32_t spin_limit, hipStream_t stream);
+// Words one part of a split walker posts per sweep: its two lowest and two
+// highest z-planes bit-packed (4 L^2 / 32), then its E_int and M shares.
+inline uint32_t split_post_words(uint32_t L) { return L * L / 8u + 2u; }
+// The split plan exists for 3D lattices with 16 <= L <= 32 (two parts of L/2
+// planes, each staging two halo planes per side); uint64 words of the post area.
+inline size_t split_halo_words(const Geometry &g) {
+  return (g.dim == 3 && g.L >= 16u && g.L <= 32u) ? (size_t)4u * g.R * split_post_words(g.L) : 0u;
+}
 
 // Groups of 8 sites one lane updates per item (V): 2D min(4, L/8), 3D min(2, L/8).
 uint32_t span_groups(const Geometry &g);
@@ -154,9 +165,9 @@ uint32_t span_groups(const Geometry &g);
 // LDS bytes needed by the kernels (host-side planning).
 size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo);
 size_t fused_lds_bytes(const Geometry &g);
-size_t persist_lds_bytes(const Geometry &g);
+size_t persist_lds_bytes(const Geometry &g, uint32_t parts);
 // Workgroups of the persistent kernel that can be co-resident (0 if unknown).
-uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads);
+uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads, uint32_t parts);
 size_t max_lds_bytes();
 
 }  // namespace ptmi

@@ -48,6 +48,9 @@ constexpr int kMaxThreads = 1024;
 // measurement among 2, 4, 8) and the persistent kernel (among 2, 4).
 constexpr uint32_t kNibbleSpan = 8;
 constexpr uint32_t kPersistSpan = 4;
+// Words of a split-plan post each lane of the posting wave handles (L <= 32:
+// at most 4 * 32 + 2 = 130 words over 64 lanes).
+constexpr uint32_t kSplitWordsPerLane = 3;
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -802,6 +805,7 @@ struct PersistArgs {
   Schedule sch;
   uint32_t *spins; // bit-packed, updated in place
   uint32_t lg_L, lg_spr, lg_rows, lg_items;
+  uint32_t lg_ipp;     // split plan: log2 of the items of one z-plane
   int32_t z2;
   uint32_t spin_limit; // polls of a partner's mailbox before the launch gives up
 };
@@ -865,17 +869,19 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
           span3d_n<V>(sp, bx, by, bz, lgG, lgPl, pl, pu, pd, y, (y + L - 1u) & (L - 1u),
                       (y + 1u) & (L - 1u), g0, gmask, off, r, s_thr, t);
       }
+      if (c == 1u) {
+        // this wave's energy and magnetisation changes over the sweep, ready
+        // at the barrier that ends the sweep
+        int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb), dM = 4 * (int)t.sb - 2 * (int)t.n;
+        dE = wave_sum(dE);
+        dM = wave_sum(dM);
+        if ((tid & 63u) == 0u) {
+          s_red[tid >> 6][0] = dE;
+          s_red[tid >> 6][1] = dM;
+        }
+      }
       __syncthreads();
     }
-    // this walker's energy and magnetisation change over the sweep
-    int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb), dM = 4 * (int)t.sb - 2 * (int)t.n;
-    dE = wave_sum(dE);
-    dM = wave_sum(dM);
-    if ((tid & 63u) == 0u) {
-      s_red[tid >> 6][0] = dE;
-      s_red[tid >> 6][1] = dM;
-    }
-    __syncthreads();
     for (uint32_t v = 0; v < (nt >> 6); ++v) {
       E += s_red[v][0];
       M += s_red[v][1];
@@ -912,10 +918,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
           const uint64_t sat_lo = a.st.swap_sat[2u * lo], sat_hi = a.st.swap_sat[2u * lo + 1u];
           uint64_t v = 0;
           for (uint32_t n = 0;; ++n) {
+            // both loads in flight together: one memory round trip per poll
             v = __hip_atomic_load(&mb[partner], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t ab =
+                __hip_atomic_load(&a.st.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             if ((v & 0xFFFFFFFF00000000ull) == tag) break;
-            if (n >= a.spin_limit ||
-                __hip_atomic_load(&a.st.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            if (n >= a.spin_limit || ab) {
               __hip_atomic_store(&a.st.counter[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               stop = 1u;
               break;
@@ -962,6 +970,264 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
   if (tid == 0u) {
     a.st.E[w] = E;
     a.st.M[w] = M;
+    a.st.slot_of[w] = slot;
+    a.st.walker_at[slot] = w;
+  }
+}
+
+// Split persistent walkers (3D): walker w runs as two co-resident workgroups,
+// part p owning the z-planes [p L/2, (p+1) L/2), so R walkers fill 2R compute
+// units.  A part stages two halo planes on each side (local planes 0, 1 and
+// L/2+2, L/2+3; its own planes are 2 .. L/2+1).  In the colour-0 half sweep it
+// also updates the inner halo plane on each side, with the draws and the
+// threshold row the plane's owner uses, so it computes exactly the owner's
+// values; colour 1 of its own planes then sees correct neighbours, and one
+// exchange of boundary planes per sweep suffices.  At the end of every sweep a
+// part posts its two lowest and two highest own planes (bit-packed) and its
+// shares of E_int and M, and at an exchange step its E_int share in the slot's
+// mailbox; each 64-bit word carries its tag (sweep or step + 1) beside 32 bits
+// of data, so the reader takes data and tag in one relaxed load and needs no
+// fence.  The parts of both walkers of a pair sum the same shares and take the
+// same decision from the same draw.  Two generations of posts suffice: a part
+// cannot post sweep s + 2 before its sibling has posted s + 1, which the
+// sibling does only after reading the post of sweep s.
+template <int V>
+__global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ uint32_t s_thr[kClasses];
+  __shared__ int s_red[kMaxThreads / 64][2];
+  __shared__ uint32_t s_slot, s_stop;
+  const Geometry &G = a.geo;
+  const uint32_t R = G.R, L = G.L, lgL = a.lg_L, lmask = L - 1u;
+  const uint32_t lgG = lgL - 3u, gmask = (1u << lgG) - 1u; // nibble dwords per row
+  const uint32_t lgPl = lgL + lgG;                          // nibble dwords per plane
+  const uint32_t Lp = L >> 1, NP = Lp + 4u;                 // own planes, staged planes
+  const uint32_t wpp = (L * L) >> 5, nwr = G.N >> 5;        // packed words per plane, per walker
+  const uint32_t nb = 4u * wpp, npost = nb + 2u;            // boundary words, words per post
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t w = blockIdx.x >> 1, p = blockIdx.x & 1u, z0 = p * Lp;
+  const uint32_t pdw = NP << lgPl;
+  uint32_t *sp = reinterpret_cast<uint32_t *>(smem);
+  uint32_t *bx = sp + pdw, *by = bx + pdw, *bz = by + pdw;
+  uint32_t *thr = bz + pdw;
+  for (uint32_t q = tid; q < R * kClasses; q += nt) thr[q] = a.st.flip_thr[q];
+
+  uint32_t slot = a.st.slot_of[w];
+  // this part's shares of the walker's E_int and M: part 0 starts from the
+  // totals, each part adds the changes of its own sites
+  int32_t Es = p ? 0 : a.st.E[w], Ms = p ? 0 : a.st.M[w];
+  int32_t Et = a.st.E[w], Mt = a.st.M[w]; // walker totals after the last sweep
+  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+  {
+    // planes z0 - 2 .. z0 + L/2 + 1, periodic in z
+    const uint32_t f = ((z0 + L - 2u) & lmask) * wpp, cnt = NP * wpp, m = nwr - 1u;
+    unpack_tile_n(sp, a.spins + (size_t)w * nwr, f, cnt, m, tid, nt);
+    unpack_tile_n(bx, a.st.bonds, f, cnt, m, tid, nt);
+    unpack_tile_n(by, a.st.bonds + nwr, f, cnt, m, tid, nt);
+    unpack_tile_n(bz, a.st.bonds + 2u * nwr, f, cnt, m, tid, nt);
+  }
+  __syncthreads();
+
+  const uint32_t smask = (1u << a.lg_spr) - 1u;
+  uint32_t rec = a.sch.rec_base, e = a.sch.ex_step;
+  for (uint32_t j = 0; j < a.sch.nsw; ++j) {
+    const uint32_t s = a.sch.s0 + j;
+    TallyN t = {0u, 0u, 0u};
+    for (uint32_t c = 0; c < 2u; ++c) {
+      // own planes 2 .. L/2 + 1, V groups per item
+      for (uint32_t q = tid; q < (Lp << a.lg_ipp); q += nt) {
+        const uint32_t lp = 2u + (q >> a.lg_ipp);
+        const uint32_t g0 = (q & smask) * V;
+        const uint32_t y = (q >> a.lg_spr) & lmask;
+        const uint32_t z = (z0 + lp + L - 2u) & lmask; // global plane
+        const uint32_t off = (c + lp + y) & 1u;         // z0 is even
+        const uint32_t ctr0 = (((z << lgL) + y) << lgG) + g0;
+        Words r[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v)
+          r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+        span3d_n<V>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
+                    (y + 1u) & lmask, g0, gmask, off, r, s_thr, t);
+      }
+      if (c == 0u) {
+        // the inner halo planes (local 1 and L/2 + 2), one group per item on
+        // the first waves: one such wave per SIMD keeps the pass balanced.
+        // Their flips are the sibling's to count.
+        const uint32_t gpp = L << lgG; // groups per plane
+        for (uint32_t q = tid; q < 2u * gpp; q += nt) {
+          const uint32_t lp = q < gpp ? 1u : Lp + 2u;
+          const uint32_t g0 = q & gmask;
+          const uint32_t y = (q >> lgG) & lmask;
+          const uint32_t z = (z0 + lp + L - 2u) & lmask;
+          const uint32_t off = (lp + y) & 1u;
+          const uint32_t ctr = (((z << lgL) + y) << lgG) + g0;
+          Words r[1];
+          r[0] = philox(ctr, s, slot, kPurposeFlip, a.key.k0, a.key.k1);
+          TallyN tl = {0u, 0u, 0u};
+          span3d_n<1>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
+                      (y + 1u) & lmask, g0, gmask, off, r, s_thr, tl);
+        }
+      } else {
+        // this wave's energy and magnetisation changes over the sweep, ready
+        // at the barrier that ends the sweep
+        int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb), dM = 4 * (int)t.sb - 2 * (int)t.n;
+        dE = wave_sum(dE);
+        dM = wave_sum(dM);
+        if ((tid & 63u) == 0u) {
+          s_red[tid >> 6][0] = dE;
+          s_red[tid >> 6][1] = dM;
+        }
+      }
+      __syncthreads();
+    }
+    const bool do_rec = a.sch.record_every && (s + 1u) % a.sch.record_every == 0u;
+    const bool do_ex = a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u;
+    if (tid < 64u) { // wave 0 posts, waits, receives and decides; the rest wait below
+      for (uint32_t v = 0; v < (nt >> 6); ++v) {
+        Es += s_red[v][0];
+        Ms += s_red[v][1];
+      }
+      const uint64_t hi = 0xFFFFFFFF00000000ull;
+      const uint64_t tag = (uint64_t)(s + 1u) << 32, etag = (uint64_t)(e + 1u) << 32;
+      const size_t gen = (size_t)(s & 1u) * R + w;
+      uint64_t *mine = a.st.halo + (gen * 2u + p) * npost;
+      const uint64_t *sib = a.st.halo + (gen * 2u + (p ^ 1u)) * npost;
+      uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * 2u * R;
+      // post: words [0, 2 wpp) = own planes 2, 3; [2 wpp, 4 wpp) = planes L/2, L/2 + 1
+      for (uint32_t q = tid; q < nb; q += 64u) {
+        const bool lo = q < 2u * wpp;
+        const uint4 x = reinterpret_cast<const uint4 *>(sp + ((lo ? 2u : Lp) << lgPl))[lo ? q : q - 2u * wpp];
+        const uint32_t word =
+            gather8(x.x) | (gather8(x.y) << 8) | (gather8(x.z) << 16) | (gather8(x.w) << 24);
+        __hip_atomic_store(mine + q, tag | word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      uint32_t partner = 0xFFFFFFFFu;
+      if (do_ex) {
+        const uint32_t par = e & 1u;
+        if ((slot & 1u) == par && slot + 1u < R) partner = slot + 1u;
+        else if ((slot & 1u) != par && slot >= 1u) partner = slot - 1u;
+      }
+      if (tid == 0u) {
+        if (do_ex)
+          __hip_atomic_store(&mb[2u * slot + p], etag | (uint32_t)Es, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine + nb, tag | (uint32_t)Es, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine + nb + 1u, tag | (uint32_t)Ms, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      }
+      // everything of the swap test that does not need the energies, before waiting
+      uint32_t lo = 0u, rr = 0u, toff = 0u;
+      int32_t D = 0;
+      uint64_t sat_lo = 0u, sat_hi = 0u;
+      if (tid == 0u && partner != 0xFFFFFFFFu) {
+        lo = min(slot, partner);
+        rr = philox(lo, e, 0u, kPurposeSwap, a.key.k0, a.key.k1).x;
+        D = (int32_t)a.st.swap_D[lo];
+        toff = a.st.swap_off[lo];
+        sat_lo = a.st.swap_sat[2u * lo];
+        sat_hi = a.st.swap_sat[2u * lo + 1u];
+      }
+      // wait for the sibling's post and, at an exchange step, the partner
+      // slot's two shares.  Every round issues all of a lane's loads before
+      // testing any (one memory round trip per round); a word is consumed when
+      // its tag arrives and cannot change again before this part has posted
+      // its next sweep, so reloading a consumed word is harmless.
+      uint32_t pend = 0u;
+#pragma unroll
+      for (uint32_t k = 0; k < kSplitWordsPerLane; ++k)
+        if (tid + 64u * k < npost) pend |= 1u << k;
+      uint32_t ppend = (partner != 0xFFFFFFFFu && tid < 2u) ? 1u : 0u;
+      const uint64_t *pmb = &mb[2u * (partner != 0xFFFFFFFFu ? partner : slot) + (tid & 1u)];
+      int32_t sE = 0, sM = 0, pE = 0;
+      uint32_t stop = 0u;
+      for (uint32_t n = 0;; ++n) {
+        uint64_t v[kSplitWordsPerLane];
+#pragma unroll
+        for (uint32_t k = 0; k < kSplitWordsPerLane; ++k)
+          v[k] = __hip_atomic_load(sib + min(tid + 64u * k, npost - 1u), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t pv = __hip_atomic_load(pmb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t ab =
+            __hip_atomic_load(&a.st.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+        for (uint32_t k = 0; k < kSplitWordsPerLane; ++k) {
+          if (!((pend >> k) & 1u) || (v[k] & hi) != tag) continue;
+          pend &= ~(1u << k);
+          const uint32_t q = tid + 64u * k, x = (uint32_t)v[k];
+          if (q < nb) {
+            // the sibling's lowest planes are this part's upper halo, its
+            // highest planes the lower halo
+            const bool lo = q < 2u * wpp;
+            reinterpret_cast<uint4 *>(sp + (lo ? ((Lp + 2u) << lgPl) : 0u))[lo ? q : q - 2u * wpp] =
+                make_uint4(spread8(x & 0xFFu), spread8(__builtin_amdgcn_ubfe(x, 8u, 8u)),
+                           spread8(__builtin_amdgcn_ubfe(x, 16u, 8u)), spread8(x >> 24));
+          } else if (q == nb) {
+            sE = (int32_t)x;
+          } else {
+            sM = (int32_t)x;
+          }
+        }
+        if (ppend && (pv & hi) == etag) {
+          ppend = 0u;
+          pE = (int32_t)(uint32_t)pv;
+        }
+        if (!__any((pend | ppend) != 0u)) break;
+        if (n >= a.spin_limit || __any(ab != 0u)) {
+          if (tid == 0u)
+            __hip_atomic_store(&a.st.counter[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          stop = 1u;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      sE = wave_sum(sE);
+      sM = wave_sum(sM);
+      const int32_t pE0 = __shfl(pE, 0, 64), pE1 = __shfl(pE, 1, 64);
+      if (tid == 0u) {
+        Et = Es + sE;
+        Mt = Ms + sM;
+        uint32_t nslot = slot;
+        if (!stop) {
+          if (do_rec && p == 0u) {
+            a.st.E_series[(size_t)rec * R + slot] = Et;
+            a.st.M_series[(size_t)rec * R + slot] = Mt;
+          }
+          if (partner != 0xFFFFFFFFu) {
+            const int32_t Ep = pE0 + pE1;
+            const int32_t Elo = (slot == lo) ? Et : Ep, Ehi = (slot == lo) ? Ep : Et;
+            const int32_t d = (Elo - Ehi) / 4; // E_int differences are multiples of 4
+            uint64_t T;
+            if (d < -D) T = sat_lo;
+            else if (d > D) T = sat_hi;
+            else {
+              const uint32_t idx = toff + (uint32_t)(d + D);
+              T = idx < a.st.swap_n ? a.st.swap_tab[idx] : 0u; // a valid table always passes
+            }
+            const bool accept = (uint64_t)rr < T;
+            if (slot == lo && p == 0u) {
+              atomicAdd(&a.st.att[lo], 1u);
+              if (accept) atomicAdd(&a.st.acc[lo], 1u);
+            }
+            if (accept) {
+              nslot = partner;
+              for (uint32_t q = 0; q < kClasses; ++q) s_thr[q] = thr[nslot * kClasses + q];
+            }
+          }
+        }
+        s_slot = nslot;
+        s_stop = stop;
+      }
+    }
+    if (do_rec) ++rec;
+    if (do_ex) ++e;
+    __syncthreads();
+    if (s_stop) break;
+    slot = s_slot;
+  }
+  pack_tile_n(a.spins + (size_t)w * nwr + z0 * wpp, sp + (2u << lgPl), Lp * wpp, tid, nt);
+  if (tid == 0u && p == 0u) {
+    a.st.E[w] = Et;
+    a.st.M[w] = Mt;
     a.st.slot_of[w] = slot;
     a.st.walker_at[slot] = w;
   }
@@ -1285,8 +1551,11 @@ __global__ void k_init_bonds(DevState st, Geometry G, Keys key, uint32_t upload)
   }
 }
 
-__global__ void k_reset(DevState st, Geometry G) {
+__global__ void k_reset(DevState st, Geometry G, uint32_t halo_words) {
   const uint32_t R = G.R;
+  // posts are matched by their tags: none may survive from an earlier use of the memory
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < halo_words; q += gridDim.x * blockDim.x)
+    st.halo[q] = 0;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < kMaxSweepsPerLaunch * R * 4u;
        q += gridDim.x * blockDim.x) {
     st.acc3[q] = 0;
@@ -1299,7 +1568,7 @@ __global__ void k_reset(DevState st, Geometry G) {
       st.acc[q] = 0;
     }
     if (q < 4u) st.counter[q] = 0;
-    if (q < 4u * R) st.mailbox[q] = 0;
+    if (q < 8u * R) st.mailbox[q] = 0;
   }
 }
 
@@ -1427,6 +1696,31 @@ hipError_t launch_persist_v(PersistArgs &a, uint32_t R, uint32_t threads, size_t
                                     dim3(threads), args, (unsigned int)lds, stream);
 }
 
+template <int V>
+hipError_t launch_persist_split_v(PersistArgs &a, uint32_t R, uint32_t threads, size_t lds,
+                                  hipStream_t stream) {
+  hipError_t err = allow_lds(k_persist_split<V>, lds);
+  if (err != hipSuccess) return err;
+  void *args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_persist_split<V>),
+                                    dim3(2u * R), dim3(threads), args, (unsigned int)lds, stream);
+}
+
+// Groups per item of the split kernel: one item per thread in a colour-1 pass
+// (a power of two, at most kPersistSpan and the groups of a row).
+uint32_t split_span(const Geometry &g, uint32_t threads) {
+  const uint32_t per = (g.L / 2u) * g.L * g.gpr / std::max<uint32_t>(threads, 1u);
+  uint32_t V = 1u;
+  while (V * 2u <= per && V * 2u <= std::min<uint32_t>(kPersistSpan, g.gpr)) V *= 2u;
+  return V;
+}
+
+const void *split_fn(uint32_t V) {
+  return V == 4   ? reinterpret_cast<const void *>(k_persist_split<4>)
+         : V == 2 ? reinterpret_cast<const void *>(k_persist_split<2>)
+                  : reinterpret_cast<const void *>(k_persist_split<1>);
+}
+
 template <int DIM, int V>
 hipError_t launch_fused_v(const FusedArgs &a, uint32_t threads, size_t lds, hipStream_t stream) {
   hipError_t err = allow_lds(k_fused<DIM, V>, lds);
@@ -1446,19 +1740,27 @@ size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo) {
 
 size_t fused_lds_bytes(const Geometry &g) { return fused_layout(g.R, g.N, g.dim).total; }
 
-size_t persist_lds_bytes(const Geometry &g) {
+size_t persist_lds_bytes(const Geometry &g, uint32_t parts) {
+  if (parts == 2u) {
+    // L/2 + 4 staged planes of spins and three bond arrays, every slot's
+    // thresholds; at least 96 KB, so that one part holds a compute unit alone
+    // (both parts of a walker must advance at the same rate)
+    const size_t need = (size_t)(g.L / 2u + 4u) * g.plane / 2u * 4u + (size_t)g.R * kClasses * 4u;
+    return std::max<size_t>(need, 96u * 1024u);
+  }
   return (size_t)g.N / 2u * (g.dim == 3 ? 4u : 1u) + (size_t)g.R * kClasses * 4u; // four bits per site
 }
 
-uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads) {
+uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads, uint32_t parts) {
   const uint32_t V = std::min<uint32_t>(kPersistSpan, g.gpr);
-  const void *fn = g.dim == 3 ? (V == 4   ? reinterpret_cast<const void *>(k_persist<3, 4>)
+  const void *fn = parts == 2u ? split_fn(split_span(g, threads))
+                 : g.dim == 3 ? (V == 4   ? reinterpret_cast<const void *>(k_persist<3, 4>)
                                  : V == 2 ? reinterpret_cast<const void *>(k_persist<3, 2>)
                                           : reinterpret_cast<const void *>(k_persist<3, 1>))
                  : V == 4 ? reinterpret_cast<const void *>(k_persist<2, 4>)
                  : V == 2 ? reinterpret_cast<const void *>(k_persist<2, 2>)
                           : reinterpret_cast<const void *>(k_persist<2, 1>);
-  const size_t lds = persist_lds_bytes(g);
+  const size_t lds = persist_lds_bytes(g, parts);
   if (lds > 65536 && hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int per_cu = 0, dev = 0, cus = 0;
@@ -1487,7 +1789,8 @@ hipError_t launch_init_bonds(const DevState &st, const Geometry &g, const Keys &
 
 hipError_t launch_reset(const DevState &st, const Geometry &g, hipStream_t stream) {
   const uint32_t n = kMaxSweepsPerLaunch * g.R * 4u;
-  hipLaunchKernelGGL(k_reset, dim3((n + 255u) / 256u), dim3(256), 0, stream, st, g);
+  const uint32_t hw = (uint32_t)split_halo_words(g);
+  hipLaunchKernelGGL(k_reset, dim3((n + 255u) / 256u), dim3(256), 0, stream, st, g, hw);
   return hipGetLastError();
 }
 
@@ -1598,22 +1901,34 @@ hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, ui
 }
 
 hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
-                          uint32_t threads, const Schedule &sch, uint32_t spin_limit,
-                          hipStream_t stream) {
+                          uint32_t threads, uint32_t parts, const Schedule &sch,
+                          uint32_t spin_limit, hipStream_t stream) {
   PersistArgs a;
   a.st = st;
   a.geo = g;
   a.key = k;
   a.sch = sch;
   a.spins = st.spins[cur];
-  const uint32_t V = std::min<uint32_t>(kPersistSpan, g.gpr);
   a.lg_L = ilog2(g.L);
-  a.lg_spr = ilog2(g.gpr / V);
   a.lg_rows = ilog2(g.rows);
-  a.lg_items = ilog2(g.N / (8u * V));
   a.z2 = g.dim == 3 ? 12 : 8;
   a.spin_limit = spin_limit;
-  const size_t lds = persist_lds_bytes(g);
+  if (parts == 2u) {
+    if (g.dim != 3 || g.L < 16u || g.L > 32u) return hipErrorInvalidValue;
+    const uint32_t V = split_span(g, threads);
+    a.lg_spr = ilog2(g.gpr / V);
+    a.lg_ipp = a.lg_L + a.lg_spr;
+    a.lg_items = 0u;
+    const size_t lds = persist_lds_bytes(g, 2u);
+    return V == 4   ? launch_persist_split_v<4>(a, g.R, threads, lds, stream)
+           : V == 2 ? launch_persist_split_v<2>(a, g.R, threads, lds, stream)
+                    : launch_persist_split_v<1>(a, g.R, threads, lds, stream);
+  }
+  const uint32_t V = std::min<uint32_t>(kPersistSpan, g.gpr);
+  a.lg_spr = ilog2(g.gpr / V);
+  a.lg_items = ilog2(g.N / (8u * V));
+  a.lg_ipp = 0u;
+  const size_t lds = persist_lds_bytes(g, 1u);
   if (g.dim == 3)
     return V == 4   ? launch_persist_v<3, 4>(a, g.R, threads, lds, stream)
            : V == 2 ? launch_persist_v<3, 2>(a, g.R, threads, lds, stream)

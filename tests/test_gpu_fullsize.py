@@ -37,14 +37,21 @@ def make_sim(pt, w, max_records):
     return pt.Simulation(cfg)
 
 
-@pytest.mark.parametrize("name", ["ising2d_L1024_R64", "ea3d_L32_R128"])
-def test_fullsize_prefix_matches_oracle(pt, name):
+@pytest.mark.parametrize("name, plan", [
+    ("ising2d_L1024_R64", None),
+    ("ea3d_L32_R128", None),                                   # two workgroups per walker
+    ("ea3d_L32_R128", dict(mode=3, tile_planes=32, block_threads=1024)),  # one per walker
+])
+def test_fullsize_prefix_matches_oracle(pt, name, plan):
     g = json.load(open(os.path.join(GOLDEN, name + ".json")))
     w = HOT_PATH[name]
     assert g["L"] == w.L and g["R"] == w.R and g["seed"] == w.seed
     assert np.array_equal(np.array(g["beta"]), w.beta)
-    say("full-size prefix", name, "sweeps", g["sweeps"])
+    say("full-size prefix", name, "sweeps", g["sweeps"], "plan", plan)
     sim = make_sim(pt, w, g["sweeps"])
+    if plan is not None:
+        sim.set_plan(**plan)
+    say("plan", sim.plan())
     sim.run(g["sweeps"], w.exchange_every)
     obs = sim.observables(spins="all")
     np.testing.assert_array_equal(obs["E_series"], np.array(g["E_series"], np.int32))

@@ -138,6 +138,36 @@ def test_persistent_plan(pt, oracle_mod, model, L, R, every, threads):
              split=True, tag="persist-split")
 
 
+@pytest.mark.parametrize("L, R, every, rec, threads", [
+    (16, 5, 2, 1, 512),     # one group per item
+    (16, 6, 1, 2, 1024),
+    (32, 4, 1, 1, 1024),    # the EA workload's lattice, two groups per item
+    (32, 7, 3, 1, 512),     # four groups per item, odd R
+    (32, 9, 1, 3, 768),     # more threads than a pass has items in the last rounds
+    (32, 5, 0, 1, 256),     # no exchange steps: boundary posts only
+])
+def test_split_persistent_plan(pt, oracle_mod, L, R, every, rec, threads):
+    """3D walkers split over two co-resident workgroups of L/2 z-planes each."""
+    beta = beta_geometric(0.5, 3.0, R)
+    plan = dict(mode=PERSISTENT, tile_planes=L // 2, block_threads=threads)
+    sim, _ = run_case(pt, oracle_mod, 1, L, R, beta, 23, 36, every, record_every=rec, plan=plan,
+                      coupling_seed=6, tag="persist-2")
+    assert sim.plan()["tile_planes"] == L // 2
+    run_case(pt, oracle_mod, 1, L, R, beta, 23, 18, every, record_every=rec, plan=plan,
+             coupling_seed=6, split=True, tag="persist-2-split")
+
+
+def test_split_persistent_plan_rejects_other_shapes(pt):
+    for model, L in ((0, 32), (1, 8), (1, 64)):  # 2D; 3D lattices too small or too large to split
+        cfg = pt.Config(model, L, 4, beta_geometric(0.5, 3.0, 4), seed=1)
+        sim = pt.Simulation(cfg)
+        with pytest.raises(pt.PTError):
+            sim.set_plan(PERSISTENT, tile_planes=L // 2, block_threads=256)
+        with pytest.raises(pt.PTError):
+            sim.set_plan(PERSISTENT, tile_planes=3, block_threads=256)
+        sim.close()
+
+
 @pytest.mark.parametrize("h, plan", [
     (0.05, None),
     (-0.08, dict(mode=TILED, tile_planes=8, sweeps_per_launch=2, block_threads=256)),

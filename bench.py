@@ -277,7 +277,11 @@ def bench_served(args):
     # run of the same configuration (100 sweeps, after creation), then the
     # same arrivals served first come, first served
     svc = np.zeros(len(ws))
+    last_note = time.time()
     for i, (w, c) in enumerate(zip(ws, cfgs)):
+        if time.time() - last_note > 10:
+            print("[plain per-instance] timed %d of %d jobs" % (i, len(ws)), file=sys.stderr, flush=True)
+            last_note = time.time()
         sim = pt.Simulation(c, device="cuda:0")
         n = min(w.sweeps, 100)
         torch.cuda.synchronize()

@@ -163,6 +163,14 @@ pt_status pt_set_plan(pt_ctx *ctx, const pt_plan *plan);
 /* Read the plan in use. */
 pt_status pt_get_plan(const pt_ctx *ctx, pt_plan *plan);
 
+/* Bound of the persistent plans' waits for a partner's post: the number of
+ * polls (each followed by a short sleep) after which a launch gives up and
+ * every workgroup of it leaves its loop; pt_observables then returns
+ * PT_EDEVICE.  Default 2^24 polls, orders of magnitude above any legitimate
+ * wait.  0 gives up at the first wait, which lets a test exercise that path
+ * deterministically.  Applies to launches queued afterwards. */
+pt_status pt_set_wait_limit(pt_ctx *ctx, uint32_t polls);
+
 /* Execution phase, MH part (Sec. 2.1, Eq. 1): n_sweeps checkerboard sweeps
  * s, s+1, ..., s+n-1 of every walker at its current slot's beta, recording
  * E_int and M after every sweep with (s'+1) % record_every == 0.  Asynchronous.

@@ -50,9 +50,6 @@ bool is_pow2(uint32_t v) { return v && !(v & (v - 1u)); }
 
 constexpr uint32_t kMaxR = 4096;
 constexpr uint32_t kFusedChunk = 4096;   // sweeps per fused or persistent launch
-// Polls of a partner's mailbox (each followed by a short sleep) before a
-// persistent launch gives up: orders of magnitude above any legitimate wait.
-constexpr uint32_t kSpinLimit = 1u << 24;
 
 // Saturation of the logistic swap rule: beyond |x| >= 32 ln 2 the decision no
 // longer depends on the 32-bit draw.
@@ -434,7 +431,7 @@ pt_status ctx_advance(pt_ctx *c, uint32_t n, uint32_t every) {
             : c->plan.mode == PT_PLAN_LANES
                 ? launch_lanes(c->st, g, c->keys, c->cur, sch, c->stream)
                 : launch_persist(c->st, g, c->keys, c->cur, c->plan.block_threads,
-                                 persist_parts(g, c->plan), sch, kSpinLimit, c->stream);
+                                 persist_parts(g, c->plan), sch, c->wait_limit, c->stream);
     } else {
       nsw = std::min(left, c->plan.sweeps_per_launch);
       if (every) nsw = std::min<uint32_t>(nsw, every - (uint32_t)(c->sweeps % every));
@@ -590,6 +587,13 @@ pt_status pt_set_plan(pt_ctx *ctx, const pt_plan *plan) {
 pt_status pt_get_plan(const pt_ctx *ctx, pt_plan *plan) {
   if (!ctx || !plan) return fail(PT_EINVAL, "NULL argument");
   *plan = ctx->plan;
+  return PT_OK;
+}
+
+pt_status pt_set_wait_limit(pt_ctx *ctx, uint32_t polls) {
+  pt_status s = usable(ctx);
+  if (s != PT_OK) return s;
+  ctx->wait_limit = polls;
   return PT_OK;
 }
 

@@ -63,6 +63,9 @@ struct pt_ctx {
   uint64_t sweeps = 0, exchanges = 0;
   uint32_t n_records = 0;
   uint32_t cur = 0;
+  // polls of a partner's post (each followed by a short sleep) before a
+  // persistent launch gives up: orders of magnitude above any legitimate wait
+  uint32_t wait_limit = 1u << 24;
   bool poisoned = false;
 };
 

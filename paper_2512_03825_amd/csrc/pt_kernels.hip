@@ -922,12 +922,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
             v = __hip_atomic_load(&mb[partner], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t ab =
                 __hip_atomic_load(&a.st.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if ((v & 0xFFFFFFFF00000000ull) == tag) break;
+            // the bound and the abort flag first: a limit of 0 gives up at once
             if (n >= a.spin_limit || ab) {
               __hip_atomic_store(&a.st.counter[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
               stop = 1u;
               break;
             }
+            if ((v & 0xFFFFFFFF00000000ull) == tag) break;
             __builtin_amdgcn_s_sleep(1);
           }
           if (!stop) {
@@ -1171,13 +1172,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
           ppend = 0u;
           pE = (int32_t)(uint32_t)pv;
         }
-        if (!__any((pend | ppend) != 0u)) break;
+        // the bound and the abort flag first: a limit of 0 gives up at once
         if (n >= a.spin_limit || __any(ab != 0u)) {
           if (tid == 0u)
             __hip_atomic_store(&a.st.counter[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           stop = 1u;
           break;
         }
+        if (!__any((pend | ppend) != 0u)) break;
         __builtin_amdgcn_s_sleep(1);
       }
       sE = wave_sum(sE);

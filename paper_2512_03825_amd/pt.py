@@ -23,7 +23,7 @@ STATUS = {0: "PT_OK", -1: "PT_EINVAL", -2: "PT_ENOMEM", -3: "PT_EDEVICE", -4: "P
           -5: "PT_EUNSUPPORTED"}
 
 # Every symbol include/pt.h declares.
-EXPORTS = ("pt_workspace_bytes", "pt_create", "pt_set_plan", "pt_get_plan", "pt_sweep",
+EXPORTS = ("pt_workspace_bytes", "pt_create", "pt_set_plan", "pt_get_plan", "pt_set_wait_limit", "pt_sweep",
            "pt_exchange", "pt_run", "pt_observables", "pt_flip_thresholds", "pt_swap_threshold",
            "pt_destroy", "pt_last_error", "pt_batch_workspace_bytes", "pt_batch_create",
            "pt_batch_run", "pt_batch_observables", "pt_batch_group_plan", "pt_batch_destroy",
@@ -94,6 +94,7 @@ def _load():
         "pt_create": (st, [P(pt_config), vp, vp, C.c_size_t, P(vp)]),
         "pt_set_plan": (st, [vp, P(pt_plan)]),
         "pt_get_plan": (st, [vp, P(pt_plan)]),
+        "pt_set_wait_limit": (st, [vp, C.c_uint32]),
         "pt_sweep": (st, [vp, C.c_uint32]),
         "pt_exchange": (st, [vp]),
         "pt_run": (st, [vp, C.c_uint32, C.c_uint32]),
@@ -197,6 +198,10 @@ def pt_get_plan(ctx) -> dict:
             "sweeps_per_launch": p.sweeps_per_launch, "block_threads": p.block_threads}
 
 
+def pt_set_wait_limit(ctx, polls: int):
+    _check(_lib.pt_set_wait_limit(ctx, int(polls)))
+
+
 def pt_sweep(ctx, n_sweeps: int):
     _check(_lib.pt_sweep(ctx, int(n_sweeps)))
 
@@ -286,6 +291,9 @@ class Simulation:
 
     def plan(self):
         return pt_get_plan(self.ctx)
+
+    def set_wait_limit(self, polls):
+        pt_set_wait_limit(self.ctx, polls)
 
     def sweep(self, n):
         pt_sweep(self.ctx, n)

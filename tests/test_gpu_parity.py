@@ -168,6 +168,33 @@ def test_split_persistent_plan_rejects_other_shapes(pt):
         sim.close()
 
 
+@pytest.mark.parametrize("model, L, R, plan", [
+    (1, 32, 6, dict(mode=PERSISTENT, tile_planes=16, block_threads=512)),   # two workgroups per walker
+    (1, 16, 5, dict(mode=PERSISTENT, tile_planes=16, block_threads=256)),   # one per walker
+    (0, 32, 8, dict(mode=PERSISTENT, block_threads=256)),
+])
+def test_persistent_wait_bound_stops_the_launch(pt, oracle_mod, model, L, R, plan):
+    """A wait limit of 0 makes every bounded wait give up at once: the launch
+    ends early (every workgroup leaves its loop), the next observables call
+    reports PT_EDEVICE and the context stays poisoned; a new context then runs
+    normally."""
+    PT_EDEVICE, PT_ESTATE = -3, -4
+    beta = beta_geometric(0.5, 3.0, R) if model == 1 else beta_geometric(0.2, 0.6, R)
+    sim = make_gpu(pt, model, L, R, beta, 29, 8, None, None, 1, 10, plan)
+    say("case wait bound", model, L, R, plan)
+    sim.set_wait_limit(0)
+    sim.run(10, 1)
+    with pytest.raises(pt.PTError) as err:
+        sim.observables()
+    assert err.value.status == PT_EDEVICE
+    with pytest.raises(pt.PTError) as err:
+        sim.run(1, 1)
+    assert err.value.status == PT_ESTATE
+    sim.close()
+    run_case(pt, oracle_mod, model, L, R, beta, 29, 6, 1, plan=plan, coupling_seed=8,
+             tag="after-abort")
+
+
 @pytest.mark.parametrize("h, plan", [
     (0.05, None),
     (-0.08, dict(mode=TILED, tile_planes=8, sweeps_per_launch=2, block_threads=256)),

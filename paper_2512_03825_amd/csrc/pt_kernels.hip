@@ -676,7 +676,7 @@ struct FusedArgs {
 
 // LDS layout of the fused kernel.
 struct FusedLayout {
-  uint32_t thr, wat, sof, E, M, acc, spins, bonds, total;
+  uint32_t thr, wat, sof, E, M, spins, bonds, total;
 };
 __host__ __device__ inline FusedLayout fused_layout(uint32_t R, uint32_t N, uint32_t dim) {
   FusedLayout f;
@@ -685,14 +685,17 @@ __host__ __device__ inline FusedLayout fused_layout(uint32_t R, uint32_t N, uint
   f.sof = f.wat + R * 4u;
   f.E = f.sof + R * 4u;
   f.M = f.E + R * 4u;
-  f.acc = f.M + R * 4u;
-  f.spins = (f.acc + R * 8u + 15u) & ~15u;
+  f.spins = (f.M + R * 4u + 15u) & ~15u;
   f.bonds = f.spins + R * N / 2u;                  // four bits per site
   f.total = f.bonds + (dim == 3 ? 3u * N / 2u : 0u);
   return f;
 }
 
-template <int DIM, int V>
+// PF: every thread holds at most one item (items <= threads), which then stays
+// the same for the whole launch.  The draws of sweep s + 1 are computed during
+// sweep s with the walker's current slot, off the latency chain of the sweep,
+// and recomputed after an exchange step only for walkers whose slot changed.
+template <int DIM, int V, bool PF>
 __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const Geometry &G = a.geo;
@@ -706,7 +709,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   uint32_t *sof = reinterpret_cast<uint32_t *>(smem + F.sof);
   int32_t *E = reinterpret_cast<int32_t *>(smem + F.E);
   int32_t *M = reinterpret_cast<int32_t *>(smem + F.M);
-  int32_t *acc = reinterpret_cast<int32_t *>(smem + F.acc);
   uint32_t *sp = reinterpret_cast<uint32_t *>(smem + F.spins);   // [R][N/8] nibble dwords
   uint32_t *bx = reinterpret_cast<uint32_t *>(smem + F.bonds), *by = bx + (N >> 3), *bz = by + (N >> 3);
 
@@ -716,8 +718,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
     sof[q] = a.st.slot_of[q];
     E[q] = a.st.E[q];
     M[q] = a.st.M[q];
-    acc[2u * q] = 0;
-    acc[2u * q + 1u] = 0;
   }
   unpack_tile_n(sp, a.spins, 0u, (R * N) >> 5, 0xFFFFFFFFu, tid, nt);
   if (DIM == 3) unpack_tile_n(bx, a.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
@@ -727,66 +727,122 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   const uint32_t shp = a.lg_spr + a.lg_rows;
   const uint32_t items = R << a.lg_items;
   uint32_t rec = a.sch.rec_base, e = a.sch.ex_step;
+  // the one item of this thread (PF)
+  const bool live = tid < items;
+  const uint32_t w1 = live ? tid >> a.lg_items : 0u, li1 = tid & imask;
+  const uint32_t g01 = (li1 & smask) * V, y1 = (li1 >> a.lg_spr) & rmask, pl1 = li1 >> shp;
+  const uint32_t ctr1 = (((pl1 << a.lg_rows) + y1) << lgG) + g01;
+  uint32_t dslot = PF ? sof[w1] : 0u; // slot the draws in rc were taken for
+  Words rc[2][V];
+  if constexpr (PF) {
+#pragma unroll
+    for (uint32_t c = 0; c < 2u; ++c)
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        rc[c][v] = philox(ctr1 + v, a.sch.s0, dslot, c | kPurposeFlip, a.key.k0, a.key.k1);
+  }
   for (uint32_t j = 0; j < a.sch.nsw; ++j) {
     const uint32_t s = a.sch.s0 + j;
-    for (uint32_t c = 0; c < 2u; ++c) {
-      uint32_t cur = 0xFFFFFFFFu;
+    if constexpr (PF) {
+      Words rn[2][V];
       TallyN t = {0u, 0u, 0u};
-      auto flush = [&]() {
-        atomicAdd(&acc[2u * cur], a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb));
-        atomicAdd(&acc[2u * cur + 1u], 4 * (int)t.sb - 2 * (int)t.n);
-      };
-      for (uint32_t q = tid; q < items; q += nt) {
-        const uint32_t w = q >> a.lg_items;
-        const uint32_t li = q & imask;
-        if (w != cur) {
-          if (cur != 0xFFFFFFFFu) flush();
-          cur = w;
-          t = {0u, 0u, 0u};
-        }
-        const uint32_t g0 = (li & smask) * V;
-        const uint32_t y = (li >> a.lg_spr) & rmask;
-        const uint32_t pl = li >> shp;
-        const uint32_t pu = (pl + L - 1u) & (L - 1u);
-        const uint32_t pd = (pl + 1u) & (L - 1u);
-        const uint32_t off = (c + pl + (DIM == 3 ? y : 0u)) & 1u;
-        const uint32_t slot = sof[w];
-        const uint32_t ctr0 = (((pl << a.lg_rows) + y) << lgG) + g0;
-        Words r[V];
+      const uint32_t pu = (pl1 + L - 1u) & (L - 1u), pd = (pl1 + 1u) & (L - 1u);
+      uint32_t *wsp = sp + (size_t)w1 * (N >> 3);
+#pragma unroll
+      for (uint32_t c = 0; c < 2u; ++c) {
+        // the next sweep's draws of this colour, independent of this sweep's work
 #pragma unroll
         for (int v = 0; v < V; ++v)
-          r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
-        uint32_t *wsp = sp + (size_t)w * (N >> 3);
-        if constexpr (DIM == 2)
-          span2d_n<V>(wsp + (pl << lgG), wsp + (pu << lgG), wsp + (pd << lgG), g0, gmask, off, r,
-                      thr + slot * kClasses, t);
-        else
-          span3d_n<V>(wsp, bx, by, bz, lgG, lgPl, pl, pu, pd, y, (y + L - 1u) & (L - 1u),
-                      (y + 1u) & (L - 1u), g0, gmask, off, r, thr + slot * kClasses, t);
+          rn[c][v] = philox(ctr1 + v, s + 1u, dslot, c | kPurposeFlip, a.key.k0, a.key.k1);
+        if (live) {
+          const uint32_t off = (c + pl1 + (DIM == 3 ? y1 : 0u)) & 1u;
+          if constexpr (DIM == 2)
+            span2d_n<V>(wsp + (pl1 << lgG), wsp + (pu << lgG), wsp + (pd << lgG), g01, gmask, off,
+                        rc[c], thr + dslot * kClasses, t);
+          else
+            span3d_n<V>(wsp, bx, by, bz, lgG, lgPl, pl1, pu, pd, y1, (y1 + L - 1u) & (L - 1u),
+                        (y1 + 1u) & (L - 1u), g01, gmask, off, rc[c], thr + dslot * kClasses, t);
+        }
+        if (c == 1u && live) { // tallies of both colours, once per sweep
+          atomicAdd(&E[w1], a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb));
+          atomicAdd(&M[w1], 4 * (int)t.sb - 2 * (int)t.n);
+        }
+        __syncthreads();
       }
-      if (cur != 0xFFFFFFFFu) flush();
-      __syncthreads();
+#pragma unroll
+      for (uint32_t c = 0; c < 2u; ++c)
+#pragma unroll
+        for (int v = 0; v < V; ++v) rc[c][v] = rn[c][v];
+    } else {
+      for (uint32_t c = 0; c < 2u; ++c) {
+        uint32_t cur = 0xFFFFFFFFu;
+        TallyN t = {0u, 0u, 0u};
+        auto flush = [&]() {
+          atomicAdd(&E[cur], a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb));
+          atomicAdd(&M[cur], 4 * (int)t.sb - 2 * (int)t.n);
+        };
+        for (uint32_t q = tid; q < items; q += nt) {
+          const uint32_t w = q >> a.lg_items;
+          const uint32_t li = q & imask;
+          if (w != cur) {
+            if (cur != 0xFFFFFFFFu) flush();
+            cur = w;
+            t = {0u, 0u, 0u};
+          }
+          const uint32_t g0 = (li & smask) * V;
+          const uint32_t y = (li >> a.lg_spr) & rmask;
+          const uint32_t pl = li >> shp;
+          const uint32_t pu = (pl + L - 1u) & (L - 1u);
+          const uint32_t pd = (pl + 1u) & (L - 1u);
+          const uint32_t off = (c + pl + (DIM == 3 ? y : 0u)) & 1u;
+          const uint32_t slot = sof[w];
+          const uint32_t ctr0 = (((pl << a.lg_rows) + y) << lgG) + g0;
+          Words r[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v)
+            r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+          uint32_t *wsp = sp + (size_t)w * (N >> 3);
+          if constexpr (DIM == 2)
+            span2d_n<V>(wsp + (pl << lgG), wsp + (pu << lgG), wsp + (pd << lgG), g0, gmask, off, r,
+                        thr + slot * kClasses, t);
+          else
+            span3d_n<V>(wsp, bx, by, bz, lgG, lgPl, pl, pu, pd, y, (y + L - 1u) & (L - 1u),
+                        (y + 1u) & (L - 1u), g0, gmask, off, r, thr + slot * kClasses, t);
+        }
+        if (cur != 0xFFFFFFFFu) flush();
+        __syncthreads();
+      }
     }
-    for (uint32_t v = tid; v < R; v += nt) {
-      E[v] += acc[2u * v];
-      M[v] += acc[2u * v + 1u];
-      acc[2u * v] = 0;
-      acc[2u * v + 1u] = 0;
-    }
-    __syncthreads();
+    // E and M are final for sweep s (the colour-1 barrier has passed): each
+    // walker's thread records them at its slot; only an exchange step needs
+    // another barrier (the next sweep's passes touch neither E, M nor the maps)
     if (a.sch.record_every && (s + 1u) % a.sch.record_every == 0u) {
-      for (uint32_t k = tid; k < R; k += nt) {
-        a.st.E_series[(size_t)rec * R + k] = E[wat[k]];
-        a.st.M_series[(size_t)rec * R + k] = M[wat[k]];
+      for (uint32_t v = tid; v < R; v += nt) {
+        const uint32_t k = sof[v];
+        a.st.E_series[(size_t)rec * R + k] = E[v];
+        a.st.M_series[(size_t)rec * R + k] = M[v];
       }
       ++rec;
+      // without PF the next colour-0 pass already adds to E and M
+      if constexpr (!PF) __syncthreads();
     }
-    __syncthreads(); // records read the maps before the exchange rewrites them
     if (a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u) {
+      __syncthreads(); // records read the maps before the exchange rewrites them
       exchange_step(a.st, R, a.key.k0, a.key.k1, e, E, M, wat, sof, tid, nt);
       ++e;
+      __syncthreads();
+      if constexpr (PF) {
+        const uint32_t ns = sof[w1];
+        if (ns != dslot) { // the walker moved: its next draws belong to the new slot
+          dslot = ns;
+#pragma unroll
+          for (uint32_t c = 0; c < 2u; ++c)
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+              rc[c][v] = philox(ctr1 + v, s + 1u, dslot, c | kPurposeFlip, a.key.k0, a.key.k1);
+        }
+      }
     }
-    __syncthreads();
   }
 
   pack_tile_n(a.spins, sp, (R * N) >> 5, tid, nt);
@@ -1725,9 +1781,11 @@ const void *split_fn(uint32_t V) {
 
 template <int DIM, int V>
 hipError_t launch_fused_v(const FusedArgs &a, uint32_t threads, size_t lds, hipStream_t stream) {
-  hipError_t err = allow_lds(k_fused<DIM, V>, lds);
+  const bool pf = (a.geo.R << a.lg_items) <= threads; // one item per thread at most
+  hipError_t err = pf ? allow_lds(k_fused<DIM, V, true>, lds) : allow_lds(k_fused<DIM, V, false>, lds);
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((k_fused<DIM, V>), dim3(1), dim3(threads), lds, stream, a);
+  if (pf) hipLaunchKernelGGL((k_fused<DIM, V, true>), dim3(1), dim3(threads), lds, stream, a);
+  else hipLaunchKernelGGL((k_fused<DIM, V, false>), dim3(1), dim3(threads), lds, stream, a);
   return hipGetLastError();
 }
 

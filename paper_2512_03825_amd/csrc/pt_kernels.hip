@@ -103,22 +103,38 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
+// The swap-test tables as one kernel reads them: in device memory, or copies
+// in LDS (the fused kernel stages them when they are small).
+struct SwapView {
+  const uint64_t *tab; // concatenated per-pair rows
+  const uint32_t *off; // [R] row start of pair k (entry d = -D[k])
+  const uint32_t *D;   // [R] half-width of pair k's row
+  const uint64_t *sat; // [R][2] values for d < -D and d > D
+  uint32_t n;          // entries in tab
+};
+
+__device__ __forceinline__ SwapView swap_view(const DevState &st) {
+  return SwapView{st.swap_tab, st.swap_off, st.swap_D, st.swap_sat, st.swap_n};
+}
+
 // Swap threshold of pair k for E_a - E_b (E_int at slots k, k+1).
-__device__ __forceinline__ uint64_t swap_T(const DevState &st, uint32_t k, int32_t dEint) {
+__device__ __forceinline__ uint64_t swap_T(const SwapView &v, uint32_t k, int32_t dEint) {
   const int32_t d = dEint / 4; // E_int differences are multiples of 4
-  const int32_t D = (int32_t)st.swap_D[k];
-  if (d < -D) return st.swap_sat[2u * k];
-  if (d > D) return st.swap_sat[2u * k + 1u];
-  const uint32_t idx = st.swap_off[k] + (uint32_t)(d + D);
-  return idx < st.swap_n ? st.swap_tab[idx] : 0u; // a valid table always passes
+  const int32_t D = (int32_t)v.D[k];
+  if (d < -D) return v.sat[2u * k];
+  if (d > D) return v.sat[2u * k + 1u];
+  const uint32_t idx = v.off[k] + (uint32_t)(d + D);
+  return idx < v.n ? v.tab[idx] : 0u; // a valid table always passes
+}
+__device__ __forceinline__ uint64_t swap_T(const DevState &st, uint32_t k, int32_t dEint) {
+  return swap_T(swap_view(st), k, dEint);
 }
 
 // Field factor of a swap (2D, h != 0): with y = (beta_k - beta_k+1)(-h) dM < 0,
 // one Metropolis test per set binary digit j of |dM|/2, each with its own draw
 // (word j mod 4 of block (k, e, 1 + j/4, swap purpose)).
-__device__ __forceinline__ bool field_factor(const DevState &st, uint32_t k, uint32_t e,
-                                             int32_t dM, uint32_t k0, uint32_t k1) {
-  const int32_t sg = st.field_sign[k];
+__device__ __forceinline__ bool field_factor(const DevState &st, int32_t sg, uint32_t k,
+                                             uint32_t e, int32_t dM, uint32_t k0, uint32_t k1) {
   if (sg == 0 || dM == 0 || (sg > 0) == (dM > 0)) return true; // y >= 0
   const uint32_t n = (uint32_t)(dM < 0 ? -dM : dM) >> 1;
   for (uint32_t j = 0; j < kFieldDigits && (n >> j); ++j) {
@@ -140,7 +156,7 @@ __device__ __forceinline__ void exchange_pair(const DevState &st, uint32_t k, ui
   const uint64_t T = swap_T(st, k, E[a] - E[b]);
   const uint32_t r = philox(k, e, 0u, kPurposeSwap, k0, k1).x;
   st.att[k] += 1u;
-  if ((uint64_t)r < T && field_factor(st, k, e, M[a] - M[b], k0, k1)) {
+  if ((uint64_t)r < T && field_factor(st, st.field_sign[k], k, e, M[a] - M[b], k0, k1)) {
     walker_at[k] = b;
     walker_at[k + 1u] = a;
     slot_of[a] = k + 1u;
@@ -672,20 +688,30 @@ struct FusedArgs {
   uint32_t *spins; // bit-packed, updated in place
   uint32_t lg_L, lg_spr, lg_rows, lg_items; // log2 of L, spans per row, rows per plane, spans per replica
   int32_t z2;
+  uint32_t ntab; // swap-table entries staged in LDS (0: the rows are read from device memory)
 };
 
-// LDS layout of the fused kernel.
+// LDS layout of the fused kernel: thresholds, maps, E and M, the swap test's
+// per-pair data and counters, optionally the swap-table rows, the lattices.
 struct FusedLayout {
-  uint32_t thr, wat, sof, E, M, spins, bonds, total;
+  uint32_t thr, wat, sof, E, M, xoff, xD, xfs, xatt, xacc, xsat, xtab, spins, bonds, total;
 };
-__host__ __device__ inline FusedLayout fused_layout(uint32_t R, uint32_t N, uint32_t dim) {
+__host__ __device__ inline FusedLayout fused_layout(uint32_t R, uint32_t N, uint32_t dim,
+                                                    uint32_t ntab) {
   FusedLayout f;
   f.thr = 0;
   f.wat = f.thr + R * kClasses * 4u;
   f.sof = f.wat + R * 4u;
   f.E = f.sof + R * 4u;
   f.M = f.E + R * 4u;
-  f.spins = (f.M + R * 4u + 15u) & ~15u;
+  f.xoff = f.M + R * 4u;
+  f.xD = f.xoff + R * 4u;
+  f.xfs = f.xD + R * 4u;
+  f.xatt = f.xfs + R * 4u;
+  f.xacc = f.xatt + R * 4u;
+  f.xsat = (f.xacc + R * 4u + 7u) & ~7u;
+  f.xtab = f.xsat + R * 16u;
+  f.spins = (f.xtab + ntab * 8u + 15u) & ~15u;
   f.bonds = f.spins + R * N / 2u;                  // four bits per site
   f.total = f.bonds + (dim == 3 ? 3u * N / 2u : 0u);
   return f;
@@ -703,12 +729,19 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   const uint32_t lgG = lgL - 3u, gmask = (1u << lgG) - 1u;   // dwords per row
   const uint32_t lgPl = lgL + lgG;                           // dwords per plane (3D)
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const FusedLayout F = fused_layout(R, N, DIM);
+  const FusedLayout F = fused_layout(R, N, DIM, a.ntab);
   uint32_t *thr = reinterpret_cast<uint32_t *>(smem + F.thr);
   uint32_t *wat = reinterpret_cast<uint32_t *>(smem + F.wat);
   uint32_t *sof = reinterpret_cast<uint32_t *>(smem + F.sof);
   int32_t *E = reinterpret_cast<int32_t *>(smem + F.E);
   int32_t *M = reinterpret_cast<int32_t *>(smem + F.M);
+  uint32_t *xoff = reinterpret_cast<uint32_t *>(smem + F.xoff);
+  uint32_t *xD = reinterpret_cast<uint32_t *>(smem + F.xD);
+  int32_t *xfs = reinterpret_cast<int32_t *>(smem + F.xfs);
+  uint32_t *xatt = reinterpret_cast<uint32_t *>(smem + F.xatt);
+  uint32_t *xacc = reinterpret_cast<uint32_t *>(smem + F.xacc);
+  uint64_t *xsat = reinterpret_cast<uint64_t *>(smem + F.xsat);
+  uint64_t *xtab = reinterpret_cast<uint64_t *>(smem + F.xtab);
   uint32_t *sp = reinterpret_cast<uint32_t *>(smem + F.spins);   // [R][N/8] nibble dwords
   uint32_t *bx = reinterpret_cast<uint32_t *>(smem + F.bonds), *by = bx + (N >> 3), *bz = by + (N >> 3);
 
@@ -718,7 +751,16 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
     sof[q] = a.st.slot_of[q];
     E[q] = a.st.E[q];
     M[q] = a.st.M[q];
+    xoff[q] = a.st.swap_off[q];
+    xD[q] = a.st.swap_D[q];
+    xfs[q] = a.st.field_sign[q];
+    xatt[q] = 0u;
+    xacc[q] = 0u;
+    xsat[2u * q] = a.st.swap_sat[2u * q];
+    xsat[2u * q + 1u] = a.st.swap_sat[2u * q + 1u];
   }
+  for (uint32_t q = tid; q < a.ntab; q += nt) xtab[q] = a.st.swap_tab[q];
+  const SwapView sv{a.ntab ? xtab : a.st.swap_tab, xoff, xD, xsat, a.st.swap_n};
   unpack_tile_n(sp, a.spins, 0u, (R * N) >> 5, 0xFFFFFFFFu, tid, nt);
   if (DIM == 3) unpack_tile_n(bx, a.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
   __syncthreads();
@@ -743,6 +785,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   }
   for (uint32_t j = 0; j < a.sch.nsw; ++j) {
     const uint32_t s = a.sch.s0 + j;
+    const bool do_ex = a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u;
     if constexpr (PF) {
       Words rn[2][V];
       TallyN t = {0u, 0u, 0u};
@@ -826,9 +869,21 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
       // without PF the next colour-0 pass already adds to E and M
       if constexpr (!PF) __syncthreads();
     }
-    if (a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u) {
+    if (do_ex) {
       __syncthreads(); // records read the maps before the exchange rewrites them
-      exchange_step(a.st, R, a.key.k0, a.key.k1, e, E, M, wat, sof, tid, nt);
+      for (uint32_t kk = (e & 1u) + 2u * tid; kk + 1u < R; kk += 2u * nt) {
+        const uint32_t wa = wat[kk], wb = wat[kk + 1u];
+        const uint32_t r = philox(kk, e, 0u, kPurposeSwap, a.key.k0, a.key.k1).x;
+        ++xatt[kk];
+        if ((uint64_t)r < swap_T(sv, kk, E[wa] - E[wb]) &&
+            field_factor(a.st, xfs[kk], kk, e, M[wa] - M[wb], a.key.k0, a.key.k1)) {
+          wat[kk] = wb;
+          wat[kk + 1u] = wa;
+          sof[wa] = kk + 1u;
+          sof[wb] = kk;
+          ++xacc[kk];
+        }
+      }
       ++e;
       __syncthreads();
       if constexpr (PF) {
@@ -845,12 +900,15 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
     }
   }
 
+  __syncthreads(); // the last exchange's counters
   pack_tile_n(a.spins, sp, (R * N) >> 5, tid, nt);
   for (uint32_t q = tid; q < R; q += nt) {
     a.st.walker_at[q] = wat[q];
     a.st.slot_of[q] = sof[q];
     a.st.E[q] = E[q];
     a.st.M[q] = M[q];
+    a.st.att[q] += xatt[q];
+    a.st.acc[q] += xacc[q];
   }
 }
 
@@ -1798,7 +1856,7 @@ size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo) {
   return np * g.plane / 2u * (g.dim == 3 ? 4u : 1u); // four bits per site; 3D: spins + 3 bond planes
 }
 
-size_t fused_lds_bytes(const Geometry &g) { return fused_layout(g.R, g.N, g.dim).total; }
+size_t fused_lds_bytes(const Geometry &g) { return fused_layout(g.R, g.N, g.dim, 0u).total; }
 
 size_t persist_lds_bytes(const Geometry &g, uint32_t parts) {
   if (parts == 2u) {
@@ -1951,7 +2009,12 @@ hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, ui
   a.lg_rows = ilog2(g.rows);
   a.lg_items = ilog2(g.N / (8u * V));
   a.z2 = g.dim == 3 ? 12 : 8;
-  const size_t lds = fused_lds_bytes(g);
+  // the swap-table rows go to LDS when they are small and fit beside the rest
+  a.ntab = 0u;
+  if ((size_t)st.swap_n * 8u <= 32u * 1024u &&
+      fused_layout(g.R, g.N, g.dim, st.swap_n).total <= max_lds_bytes())
+    a.ntab = st.swap_n;
+  const size_t lds = fused_layout(g.R, g.N, g.dim, a.ntab).total;
   if (g.dim == 3)
     return V == 2 ? launch_fused_v<3, 2>(a, threads, lds, stream)
                   : launch_fused_v<3, 1>(a, threads, lds, stream);

@@ -155,13 +155,13 @@ __device__ __forceinline__ void exchange_pair(const DevState &st, uint32_t k, ui
   const uint32_t a = walker_at[k], b = walker_at[k + 1u];
   const uint64_t T = swap_T(st, k, E[a] - E[b]);
   const uint32_t r = philox(k, e, 0u, kPurposeSwap, k0, k1).x;
-  st.att[k] += 1u;
+  atomicAdd(&st.att[k], 1u); // one lane per pair: the atomic only spares a round trip
   if ((uint64_t)r < T && field_factor(st, st.field_sign[k], k, e, M[a] - M[b], k0, k1)) {
     walker_at[k] = b;
     walker_at[k + 1u] = a;
     slot_of[a] = k + 1u;
     slot_of[b] = k;
-    st.acc[k] += 1u;
+    atomicAdd(&st.acc[k], 1u);
   }
 }
 
@@ -205,28 +205,39 @@ __device__ __forceinline__ void tiled_epilogue(const TiledArgs &a, uint32_t tid,
   if (!*s_last) return;
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
-  const uint32_t R = a.geo.R;
-  uint32_t rec = a.sch.rec_base;
-  for (uint32_t j = 0; j < a.sch.nsw; ++j) {
-    for (uint32_t v = tid; v < R; v += nt) {
+  // Each thread folds whole walkers: every load of a walker (its per-sweep
+  // tallies, E, M, slot) is issued before any is used, so the fold costs one
+  // memory round trip whatever the number of sweeps.  The slots do not change
+  // before the exchange step, so walker v's record goes to column slot_of[v].
+  const uint32_t R = a.geo.R, nsw = a.sch.nsw;
+  for (uint32_t v = tid; v < R; v += nt) {
+    int32_t dE[kMaxSweepsPerLaunch], dM[kMaxSweepsPerLaunch];
+#pragma unroll
+    for (uint32_t j = 0; j < kMaxSweepsPerLaunch; ++j) {
+      if (j >= nsw) break;
+      const int32_t *acc = a.st.acc3 + ((size_t)j * R + v) * 4u;
+      dE[j] = __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      dM[j] = __hip_atomic_load(acc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    int32_t Ev = a.st.E[v], Mv = a.st.M[v];
+    const uint32_t k = a.st.slot_of[v];
+    uint32_t rec = a.sch.rec_base;
+#pragma unroll
+    for (uint32_t j = 0; j < kMaxSweepsPerLaunch; ++j) {
+      if (j >= nsw) break;
       int32_t *acc = a.st.acc3 + ((size_t)j * R + v) * 4u;
-      const int32_t dE = __hip_atomic_load(acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const int32_t dM = __hip_atomic_load(acc + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(acc, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(acc + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      a.st.E[v] += dE;
-      a.st.M[v] += dM;
-    }
-    __syncthreads();
-    const uint32_t s = a.sch.s0 + j;
-    if (a.sch.record_every && (s + 1u) % a.sch.record_every == 0u) {
-      for (uint32_t k = tid; k < R; k += nt) {
-        const uint32_t v = a.st.walker_at[k];
-        a.st.E_series[(size_t)rec * R + k] = a.st.E[v];
-        a.st.M_series[(size_t)rec * R + k] = a.st.M[v];
+      Ev += dE[j];
+      Mv += dM[j];
+      if (a.sch.record_every && (a.sch.s0 + j + 1u) % a.sch.record_every == 0u) {
+        a.st.E_series[(size_t)rec * R + k] = Ev;
+        a.st.M_series[(size_t)rec * R + k] = Mv;
+        ++rec;
       }
-      ++rec;
     }
+    a.st.E[v] = Ev;
+    a.st.M[v] = Mv;
   }
   if (a.sch.do_exchange) {
     __syncthreads();

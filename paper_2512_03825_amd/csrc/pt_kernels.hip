@@ -152,11 +152,24 @@ __device__ __forceinline__ void exchange_pair(const DevState &st, uint32_t k, ui
                                               uint32_t k1, uint32_t e, const int32_t *E,
                                               const int32_t *M, uint32_t *walker_at,
                                               uint32_t *slot_of) {
+  // the pair's table data does not depend on the energies: loaded together
+  // with the walker map, so the test costs three dependent memory accesses
   const uint32_t a = walker_at[k], b = walker_at[k + 1u];
-  const uint64_t T = swap_T(st, k, E[a] - E[b]);
+  const int32_t D = (int32_t)st.swap_D[k];
+  const uint32_t toff = st.swap_off[k];
+  const uint64_t sat_lo = st.swap_sat[2u * k], sat_hi = st.swap_sat[2u * k + 1u];
+  const int32_t sg = st.field_sign[k];
   const uint32_t r = philox(k, e, 0u, kPurposeSwap, k0, k1).x;
+  const int32_t d = (E[a] - E[b]) / 4; // E_int differences are multiples of 4
+  uint64_t T;
+  if (d < -D) T = sat_lo;
+  else if (d > D) T = sat_hi;
+  else {
+    const uint32_t idx = toff + (uint32_t)(d + D);
+    T = idx < st.swap_n ? st.swap_tab[idx] : 0u; // a valid table always passes
+  }
   atomicAdd(&st.att[k], 1u); // one lane per pair: the atomic only spares a round trip
-  if ((uint64_t)r < T && field_factor(st, st.field_sign[k], k, e, M[a] - M[b], k0, k1)) {
+  if ((uint64_t)r < T && field_factor(st, sg, k, e, M[a] - M[b], k0, k1)) {
     walker_at[k] = b;
     walker_at[k + 1u] = a;
     slot_of[a] = k + 1u;

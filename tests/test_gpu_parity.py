@@ -145,6 +145,10 @@ def test_persistent_plan(pt, oracle_mod, model, L, R, every, threads):
     (32, 7, 3, 1, 512),     # four groups per item, odd R
     (32, 9, 1, 3, 768),     # more threads than a pass has items in the last rounds
     (32, 5, 0, 1, 256),     # no exchange steps: boundary posts only
+    (32, 6, 1, 1, 576),     # one item per computing thread: counts taken during the handshake
+    (32, 7, 2, 2, 576),
+    (16, 5, 1, 1, 192),     # the same at L = 16 (two groups per item)
+    (16, 4, 0, 3, 192),
 ])
 def test_split_persistent_plan(pt, oracle_mod, L, R, every, rec, threads):
     """3D walkers split over two co-resident workgroups of L/2 z-planes each."""

@@ -32,6 +32,11 @@
 //                  the kernel.
 //   k_persist      one co-resident workgroup per walker for a whole run;
 //                  exchanges decided pairwise through mailboxes.
+//   k_persist_split  3D: two co-resident workgroups per walker (half the
+//                  z-planes each, two halo planes per side), trading boundary
+//                  planes and energy shares once per sweep as tagged words.
+//   k_lanes        the paper's decomposition: one walker per lane, its lattice
+//                  in registers, sites visited one after another.
 //   k_batch_*      batched and served forms: many instances per launch.
 //   k_exchange     one exchange step (slot permutation, no lattice copies).
 //   k_init_*, k_reset, k_recount   initialisation.

@@ -435,9 +435,9 @@ def main():
     import torch
 
     from paper_2512_03825_amd import pt
-    from paper_2512_03825_amd.workloads import HOT_PATH
+    from paper_2512_03825_amd.workloads import WORKLOADS
 
-    w = HOT_PATH[args.workload]
+    w = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
     every = w.exchange_every
     # a step is 10 sweeps of the workload's schedule (a whole number of
@@ -545,7 +545,9 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sweeps)
+        # a bounded sample: at most ~3*10^8 attempts (tens of seconds on one core)
+        out["cpu_baseline"] = cpu_baseline(w, max(1, min(args.cpu_sweeps,
+                                                         int(3e8 // w.attempts_per_sweep))))
     sim.close()
     print(json.dumps(out), flush=True)
 

@@ -92,3 +92,12 @@ def test_ordered_state_at_large_beta(pt, oracle_mod, plan):
                    tag="beta 20 from all up")
     assert np.all(obs["E_series"] == -2 * N) and np.all(obs["M_series"] == N)
     assert np.all(obs["spins"] == 1)
+
+
+@pytest.mark.parametrize("every", [0, 2])
+def test_paper_shape_ladder_at_reduced_size(pt, oracle_mod, every):
+    """1500 replicas on the paper's temperature ladder T_k = 1 + 3k/R, on a
+    32 x 32 lattice (the bench runs the same ladder at 256^2 and 512^2)."""
+    from paper_2512_03825_amd.workloads import paper_shape
+    beta = paper_shape(256).beta
+    run_both(pt, oracle_mod, 0, 32, 1500, beta, 6, every, tag="paper ladder R=1500")

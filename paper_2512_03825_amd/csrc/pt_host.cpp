@@ -348,6 +348,16 @@ pt_plan auto_plan(const pt_ctx *c) {
     while (H > 32u && !fits(H)) H /= 2u;
     p.tile_planes = H;
     p.block_threads = H >= 256u ? 1024u : 512u;
+    if (H >= g.L) {
+      // Whole replicas: no halo rows to recompute, so the most sweeps per
+      // launch; when there are walkers for every slot, workgroups sized so that
+      // the ones LDS lets share a compute unit hold 16 waves together
+      // (measured: 256^2 x 1500 at 256 threads, 512^2 x 1500 at 1024).
+      p.sweeps_per_launch = kMaxSweepsPerLaunch;
+      const size_t lds = tiled_lds_bytes(g, H, 0u);
+      const uint32_t per_cu = (uint32_t)std::min<size_t>(4u, std::max<size_t>(1u, max_lds_bytes() / lds));
+      if (g.R >= 256u * per_cu) p.block_threads = 1024u / per_cu;
+    }
   }
   for (int tries = 0; tries < 8 && check_plan(c, p) != PT_OK; ++tries) {
     // shrink until the plan fits (LDS, halo rules); whole-replica tiles always fit

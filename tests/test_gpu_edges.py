@@ -101,3 +101,26 @@ def test_paper_shape_ladder_at_reduced_size(pt, oracle_mod, every):
     from paper_2512_03825_amd.workloads import paper_shape
     beta = paper_shape(256).beta
     run_both(pt, oracle_mod, 0, 32, 1500, beta, 6, every, tag="paper ladder R=1500")
+
+
+def test_auto_plans_of_the_bench_workloads(pt):
+    """The decompositions the measurements describe are the ones the automatic
+    plan picks for the benchmarked workloads."""
+    from paper_2512_03825_amd.workloads import WORKLOADS
+    want = {
+        "ising2d_L16_R8": dict(mode=FUSED, block_threads=128),
+        "ising2d_L1024_R64": dict(mode=TILED, tile_planes=256, sweeps_per_launch=5, block_threads=1024),
+        "ea3d_L32_R128": dict(mode=PERSISTENT, tile_planes=16, block_threads=512),
+        "paper_shape_L256_R1500": dict(mode=TILED, tile_planes=256, sweeps_per_launch=8,
+                                       block_threads=256),
+        "paper_shape_L512_R1500": dict(mode=TILED, tile_planes=512, sweeps_per_launch=8,
+                                       block_threads=1024),
+    }
+    for name, plan in want.items():
+        w = WORKLOADS[name]
+        sim = pt.Simulation(pt.Config(w.model, w.L, w.R, w.beta, seed=w.seed,
+                                      coupling_seed=w.coupling_seed))
+        got = sim.plan()
+        sim.close()
+        say("auto plan", name, got)
+        assert all(got[k] == v for k, v in plan.items()), (name, got)

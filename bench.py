@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--rho", type=float, default=0.8, help="served form: offered load / capacity")
     ap.add_argument("--arena-gib", type=float, default=8.0, help="served form: job arena (GiB)")
     ap.add_argument("--tiled-lanes", type=int, default=1, help="served form: streams for large lattices")
+    ap.add_argument("--class-sites", default="4096,65536",
+                    help="served form: ascending sites-per-replica bounds of the batched lanes' size "
+                         "classes, comma-separated (empty: one batched lane)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 64 MiB device-to-device copy (a kernel of known "
                          "traffic, to scale HBM counters)")
@@ -248,7 +251,7 @@ def bench_served(args):
                       max_records=w.sweeps // w.record_every) for w in ws]
     att = np.array([w.attempts_per_sweep * w.sweeps for w in ws], dtype=np.float64)
     opts = dict(max_jobs=4096, max_walkers=1 << 20, tiled_lanes=args.tiled_lanes, depth=2,
-                cycle_sweeps=10, tiled_sweeps=5)
+                cycle_sweeps=10, tiled_sweeps=5, class_sites=[int(x) for x in args.class_sites.split(",") if x])
     srv = pt.Server(int(args.arena_gib * (1 << 30)), device="cuda:0", **opts)
     # capacity: the first 200 jobs cut to 2000 sweeps, all submitted at once
     cap_ws = [w for w in ws[:200]]

@@ -247,10 +247,13 @@ void pt_batch_destroy(pt_batch *b);
  * free arena, the resident-job limit and the resident-walker limit.  An admitted
  * job's lattices, tables, random-stream position and counters stay on the
  * device until it finishes.  Jobs whose replicas fit one workgroup's LDS
- * (2D L <= 512, EA L <= 32) join the batched lane: one stream whose cycles run
+ * (2D L <= 512, EA L <= 32) join a batched lane: a stream whose cycles run
  * up to cycle_sweeps sweeps of every resident job in one launch per lattice-size
  * group, then their exchange steps (the batched form's kernels, membership
- * changing between cycles as jobs arrive and finish).  Larger 2D lattices join
+ * changing between cycles as jobs arrive and finish).  Every job in a lane
+ * advances by the same sweeps per cycle, so a lane's cycle is paced by its
+ * largest lattices; class_sites splits the batched jobs by size into lanes of
+ * their own, so that small jobs are not paced by large ones.  Larger 2D lattices join
  * a tiled lane: a stream whose cycles run up to tiled_sweeps sweeps of every
  * resident job's tiles in one launch per lattice size, each job's last
  * workgroup folding its energies, records and exchange step; tiled lanes and
@@ -263,6 +266,8 @@ void pt_batch_destroy(pt_batch *b);
  * One server must not be used from two threads at once. */
 typedef struct pt_server pt_server;
 
+#define PT_SERVER_CLASSES 3
+
 typedef struct {
   uint32_t max_jobs;       /* resident jobs at once, 1 .. 65536 */
   uint32_t max_walkers;    /* per lane: resident replicas (batched lane) or replica tiles (tiled lanes) */
@@ -270,6 +275,10 @@ typedef struct {
   uint32_t depth;          /* steps in flight per lane, 1 .. 8 */
   uint32_t cycle_sweeps;   /* batched lane: at most this many sweeps per cycle, 1 .. 16 */
   uint32_t tiled_sweeps;   /* tiled lanes: at most this many sweeps per cycle, 1 .. PT_MAX_SWEEPS_PER_LAUNCH */
+  uint32_t class_sites[PT_SERVER_CLASSES]; /* size classes of the batched lanes: ascending
+                              sites-per-replica bounds, unused entries 0 (all 0: one batched
+                              lane); a batched job runs on the lane of the first class
+                              whose bound it does not exceed, lane 0 if none */
 } pt_server_opts;
 
 #define PT_JOB_KEEP_SPINS 1u /* keep the final lattices of all slots with the results */
@@ -280,7 +289,8 @@ typedef struct {
   double admitted;         /* when its initialisation was queued */
   double finished;         /* when the host saw its last step complete */
   uint64_t attempts;       /* R * L^dim * n_sweeps */
-  uint32_t lane;           /* 0 batched, 1 .. tiled lanes */
+  uint32_t lane;           /* 0 batched (above every class), 1 .. tiled_lanes tiled,
+                              tiled_lanes + 1 + k batched class k */
   uint32_t pad;
 } pt_job_info;
 

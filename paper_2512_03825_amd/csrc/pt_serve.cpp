@@ -34,7 +34,7 @@ struct Job {
   pt_ctx *ctx = nullptr;
   uint32_t lane = 0;
   uint32_t inst = ~0u;  // instance slot (device descriptor and counters)
-  uint32_t tiles = 0;   // tiled lanes: tiles per walker
+  uint32_t tiles = 0;   // tiled lanes: tiles per walker (0: a batched-lane job)
   uint32_t cur = 0;     // tiled lanes: spin buffer holding the lattices (host replay)
   uint64_t queued = 0;  // sweeps queued on the device so far
   bool done = false;
@@ -68,24 +68,27 @@ struct Group {
   uint32_t item_off = 0, n_items = 0;
 };
 
-// A lane is a stream with its own resident jobs and device work lists: lane 0
-// runs whole-replica jobs through the batched kernels, lanes 1.. run larger
-// lattices through the batched tiled kernel.
+// A lane is a stream with its own resident jobs and device work lists: the
+// batched lanes run whole-replica jobs through the batched kernels (lane 0 for
+// lattices above every size class, then one lane per class after the tiled
+// lanes), the tiled lanes (1 .. tiled_lanes) run larger lattices through the
+// batched tiled kernel.
 struct Lane {
+  bool tiled = false;
   hipStream_t s = nullptr;
   std::deque<Step> q;
   std::vector<uint64_t> jobs;  // resident jobs in admission order
   Keep staged;                 // uploads queued since the last step
   bool dirty = true;           // membership changed since the lists were built
-  uint64_t slots = 0;          // resident walkers (lane 0) or walker tiles (tiled lanes)
+  uint64_t slots = 0;          // resident walkers (batched) or walker tiles (tiled lanes)
   uint64_t work = 0;           // resident sites x replicas
   uint32_t K = 1;              // sweeps per cycle
   std::vector<Group> groups;
   uint32_t n_pairs = 0, n_list = 0;
   // device work lists in the server's tables
-  BatchItem *d_items = nullptr;      // lane 0
+  BatchItem *d_items = nullptr;      // batched lanes
   BatchTileItem *d_titems = nullptr; // tiled lanes
-  uint2 *d_pairs = nullptr;          // lane 0
+  uint2 *d_pairs = nullptr;          // batched lanes
   uint32_t *d_list = nullptr;        // instances the lane advances
 };
 
@@ -108,6 +111,15 @@ struct Head {
   std::vector<size_t> items, pairs, list; // per lane
 };
 
+// Size classes of the batched lanes: the nonzero entries of class_sites.
+uint32_t n_classes(const pt_server_opts &o) {
+  uint32_t n = 0;
+  while (n < PT_SERVER_CLASSES && o.class_sites[n]) ++n;
+  return n;
+}
+uint32_t n_lanes(const pt_server_opts &o) { return 1u + o.tiled_lanes + n_classes(o); }
+bool lane_tiled(const pt_server_opts &o, uint32_t l) { return l >= 1u && l <= o.tiled_lanes; }
+
 Head head_layout(const pt_server_opts &o) {
   Head h;
   size_t off = 0;
@@ -119,9 +131,10 @@ Head head_layout(const pt_server_opts &o) {
   const size_t W = std::max(o.max_walkers, 1u);
   h.insts = take((size_t)o.max_jobs * sizeof(BatchInst));
   h.ctr = take((size_t)o.max_jobs * kCtrWords * 4);
-  for (uint32_t l = 0; l <= o.tiled_lanes; ++l) {
-    h.items.push_back(take(W * (l ? sizeof(BatchTileItem) : sizeof(BatchItem))));
-    h.pairs.push_back(l ? 0 : take(W * sizeof(uint2)));
+  for (uint32_t l = 0; l < n_lanes(o); ++l) {
+    const bool tiled = lane_tiled(o, l);
+    h.items.push_back(take(W * (tiled ? sizeof(BatchTileItem) : sizeof(BatchItem))));
+    h.pairs.push_back(tiled ? 0 : take(W * sizeof(uint2)));
     h.list.push_back(take((size_t)o.max_jobs * 4));
   }
   h.total = off;
@@ -142,6 +155,14 @@ pt_status check_opts(const pt_server_opts *o) {
   if (o->tiled_sweeps < 1 || o->tiled_sweeps > kMaxSweepsPerLaunch)
     return fail(PT_EINVAL, "tiled_sweeps = %u: must be in [1, %u]", o->tiled_sweeps,
                 kMaxSweepsPerLaunch);
+  const uint32_t nc = n_classes(*o);
+  for (uint32_t k = 0; k < PT_SERVER_CLASSES; ++k) {
+    if (k >= nc && o->class_sites[k])
+      return fail(PT_EINVAL, "class_sites[%u] = %u after a zero entry", k, o->class_sites[k]);
+    if (k > 0 && k < nc && o->class_sites[k] <= o->class_sites[k - 1])
+      return fail(PT_EINVAL, "class_sites must ascend: [%u] = %u after %u", k, o->class_sites[k],
+                  o->class_sites[k - 1]);
+  }
   return PT_OK;
 }
 
@@ -164,7 +185,7 @@ struct pt_server {
   uint32_t *d_ctr = nullptr;
   uint8_t *arena_base = nullptr;
   Arena arena;
-  std::vector<Lane> lanes; // [0] batched, [1 ..] tiled
+  std::vector<Lane> lanes; // [0] batched, [1 .. tiled_lanes] tiled, then a batched lane per size class
   hipStream_t copy = nullptr;
   std::vector<hipEvent_t> event_pool;
   std::map<uint64_t, std::unique_ptr<Job>> jobs;
@@ -262,7 +283,7 @@ pt_status retire(pt_server *sv, uint64_t id) {
   sv->free_inst.push_back(j.inst);
   Lane &ln = sv->lanes[j.lane];
   ln.jobs.erase(std::find(ln.jobs.begin(), ln.jobs.end(), id));
-  ln.slots -= (uint64_t)j.cfg.R * (j.lane ? j.tiles : 1u);
+  ln.slots -= (uint64_t)j.cfg.R * (j.tiles ? j.tiles : 1u);
   ln.work -= (uint64_t)j.cfg.R * j.sites();
   pt_destroy(j.ctx);
   j.ctx = nullptr;
@@ -312,11 +333,16 @@ pt_status admit(pt_server *sv) {
     if (j.tiles) {
       // the tiled lane with the least resident work
       lane = 1;
-      for (uint32_t l = 2; l < sv->lanes.size(); ++l)
+      for (uint32_t l = 2; l <= sv->o.tiled_lanes; ++l)
         if (sv->lanes[l].work < sv->lanes[lane].work) lane = l;
+    } else {
+      // the batched lane of the smallest class that holds it (lane 0: above all classes)
+      const uint32_t nc = n_classes(sv->o);
+      for (uint32_t k = 0; k < nc && !lane; ++k)
+        if (j.sites() <= sv->o.class_sites[k]) lane = sv->o.tiled_lanes + 1u + k;
     }
     Lane &ln = sv->lanes[lane];
-    const uint64_t slots = (uint64_t)j.cfg.R * (lane ? j.tiles : 1u);
+    const uint64_t slots = (uint64_t)j.cfg.R * (j.tiles ? j.tiles : 1u);
     if (ln.slots + slots > sv->o.max_walkers) break;
     size_t off = 0;
     if (!sv->arena.alloc(j.bytes, &off)) break;
@@ -344,7 +370,7 @@ pt_status admit(pt_server *sv) {
     ctr[kCtrActive] = 1u;
     ctr[kCtrEvery] = j.every;
     ctr[kCtrCur] = 0u;
-    ctr[kCtrTiles] = lane ? j.tiles : 0u;
+    ctr[kCtrTiles] = j.tiles;
     auto hi = bytes_of(&I, 1), hc = bytes_of(ctr, kCtrWords);
     hipError_t e = hipMemcpyAsync(sv->d_insts + j.inst, hi->data(), hi->size(), hipMemcpyHostToDevice, ln.s);
     if (e == hipSuccess)
@@ -376,7 +402,7 @@ pt_status rebuild_lane(pt_server *sv, uint32_t l) {
     Group G;
     G.g = sv->jobs.at(kv.second[0])->ctx->d.geo;
     for (uint64_t id : kv.second) G.max_R = std::max(G.max_R, sv->jobs.at(id)->cfg.R);
-    if (l == 0) {
+    if (!ln.tiled) {
       const auto wt = batch_decomposition(G.g, G.max_R);
       G.W = wt.first;
       G.threads = wt.second;
@@ -436,12 +462,12 @@ pt_status lane_cycle(pt_server *sv, uint32_t l, bool *queued) {
   hipError_t e = hipSuccess;
   for (const Group &G : ln.groups) {
     if (e != hipSuccess) break;
-    e = l == 0 ? launch_batch_sweep(sv->d_insts, ln.d_items + G.item_off, G.n_items, G.g, G.W,
-                                    G.threads, K, ln.s)
-               : launch_batch_tiled(sv->d_insts, ln.d_titems + G.item_off, G.n_items, G.g, G.H,
-                                    G.threads, K, ln.s);
+    e = !ln.tiled ? launch_batch_sweep(sv->d_insts, ln.d_items + G.item_off, G.n_items, G.g, G.W,
+                                       G.threads, K, ln.s)
+                  : launch_batch_tiled(sv->d_insts, ln.d_titems + G.item_off, G.n_items, G.g, G.H,
+                                       G.threads, K, ln.s);
   }
-  if (e == hipSuccess && l == 0 && ln.n_pairs)
+  if (e == hipSuccess && !ln.tiled && ln.n_pairs)
     e = launch_batch_exchange(sv->d_insts, ln.d_pairs, ln.n_pairs, K, ln.s);
   if (e == hipSuccess) e = launch_batch_advance(sv->d_insts, ln.d_list, ln.n_list, K, ln.s);
   if (e != hipSuccess) return sv_fail(sv, e, "lane cycle launch");
@@ -452,7 +478,7 @@ pt_status lane_cycle(pt_server *sv, uint32_t l, bool *queued) {
     if (j.queued >= j.n_sweeps) continue;
     const uint64_t n = cycle_n(j, K);
     j.queued += n;
-    if (n && j.tiles > 1u && l) j.cur ^= 1u;
+    if (n && j.tiles > 1u) j.cur ^= 1u;
     if (j.queued == j.n_sweeps) {
       st.finishing.push_back(id);
       ln.dirty = true;
@@ -464,8 +490,8 @@ pt_status lane_cycle(pt_server *sv, uint32_t l, bool *queued) {
   st.keep = std::move(ln.staged);
   ln.staged.clear();
   ln.q.push_back(std::move(st));
-  if (l == 0) ++sv->batched_cycles;
-  else ++sv->tiled_steps;
+  if (ln.tiled) ++sv->tiled_steps;
+  else ++sv->batched_cycles;
   *queued = true;
   return PT_OK;
 }
@@ -513,17 +539,18 @@ pt_status pt_server_create(const pt_server_opts *opts, void *d_workspace, size_t
   sv->arena.reset(ws_bytes - h.total, kAlign);
   sv->inst_job.assign(opts->max_jobs, 0);
   for (uint32_t i = opts->max_jobs; i-- > 0;) sv->free_inst.push_back(i);
-  sv->lanes.resize(1 + opts->tiled_lanes);
+  sv->lanes.resize(n_lanes(*opts));
   for (uint32_t l = 0; l < sv->lanes.size(); ++l) {
     Lane &ln = sv->lanes[l];
-    if (l == 0) {
+    ln.tiled = lane_tiled(*opts, l);
+    if (!ln.tiled) {
       ln.d_items = (BatchItem *)(sv->base + h.items[l]);
       ln.d_pairs = (uint2 *)(sv->base + h.pairs[l]);
     } else {
       ln.d_titems = (BatchTileItem *)(sv->base + h.items[l]);
     }
     ln.d_list = (uint32_t *)(sv->base + h.list[l]);
-    ln.K = l == 0 ? opts->cycle_sweeps : opts->tiled_sweeps;
+    ln.K = ln.tiled ? opts->tiled_sweeps : opts->cycle_sweeps;
   }
   hipError_t e = hipSuccess;
   for (Lane &ln : sv->lanes)

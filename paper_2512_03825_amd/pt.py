@@ -67,7 +67,8 @@ class pt_obs(C.Structure):
 
 class pt_server_opts(C.Structure):
     _fields_ = [("max_jobs", C.c_uint32), ("max_walkers", C.c_uint32), ("tiled_lanes", C.c_uint32),
-                ("depth", C.c_uint32), ("cycle_sweeps", C.c_uint32), ("tiled_sweeps", C.c_uint32)]
+                ("depth", C.c_uint32), ("cycle_sweeps", C.c_uint32), ("tiled_sweeps", C.c_uint32),
+                ("class_sites", C.c_uint32 * 3)]
 
 
 class pt_job_info(C.Structure):
@@ -374,9 +375,10 @@ class Batch:
 
 
 def server_opts(max_jobs=1024, max_walkers=32768, tiled_lanes=1, depth=2, cycle_sweeps=10,
-                tiled_sweeps=5) -> pt_server_opts:
+                tiled_sweeps=5, class_sites=(4096, 65536)) -> pt_server_opts:
+    cs = list(class_sites) + [0] * (3 - len(class_sites))
     return pt_server_opts(int(max_jobs), int(max_walkers), int(tiled_lanes), int(depth),
-                          int(cycle_sweeps), int(tiled_sweeps))
+                          int(cycle_sweeps), int(tiled_sweeps), (C.c_uint32 * 3)(*map(int, cs)))
 
 
 def pt_server_overhead_bytes(opts: pt_server_opts) -> int:

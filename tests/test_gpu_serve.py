@@ -66,15 +66,16 @@ def _run_to_completion(srv, n, limit_s=120.0):
     return finished
 
 
-@pytest.mark.parametrize("arena_scale", [1.3, 8.0])
-def test_jobs_in_the_mix_equal_jobs_alone(oracle_mod, arena_scale):
+@pytest.mark.parametrize("arena_scale, classes", [(1.3, (4096, 65536)), (8.0, (4096, 65536)), (8.0, ()),
+                                                   (8.0, (300,)), (8.0, (256, 4096, 65536))])
+def test_jobs_in_the_mix_equal_jobs_alone(oracle_mod, arena_scale, classes):
     from paper_2512_03825_amd import pt
     cfgs = [_cfg(pt, i, s) for i, s in enumerate(JOBS)]
     biggest = max(pt.pt_workspace_bytes(c) for c in cfgs)
     arena = int(biggest * arena_scale)
     say("served: %d jobs, arena %d bytes (largest job %d)" % (len(JOBS), arena, biggest))
     srv = pt.Server(arena, max_jobs=8, max_walkers=96, tiled_lanes=2, depth=2, cycle_sweeps=4,
-                    tiled_sweeps=6)
+                    tiled_sweeps=6, class_sites=classes)
     ids = {}
     # arrivals in three waves, the later ones while earlier jobs are on the device
     for wave in (range(0, 4), range(4, 8), range(8, len(JOBS))):
@@ -91,8 +92,16 @@ def test_jobs_in_the_mix_equal_jobs_alone(oracle_mod, arena_scale):
     for f in finished:
         assert f["arrival"] <= f["admitted"] <= f["finished"]
         i = ids[f["job_id"]]
-        # replicas up to 2D 512^2 (4 bits per site) and EA 32^3 fit one workgroup's LDS
-        assert (f["lane"] > 0) == (JOBS[i][0] == 0 and JOBS[i][1] >= 1024), (i, f["lane"])
+        # replicas up to 2D 512^2 (4 bits per site) and EA 32^3 fit one workgroup's LDS;
+        # the others take the batched lane of the first size class that holds them
+        # (lanes 3, 4, ... after the two tiled lanes), lane 0 if none does
+        model, L = JOBS[i][0], JOBS[i][1]
+        sites = L ** (3 if model else 2)
+        if model == 0 and L >= 1024:
+            want = (1, 2)
+        else:
+            want = (next((3 + k for k, b in enumerate(classes) if sites <= b), 0),)
+        assert f["lane"] in want, (i, f["lane"], want)
     for jid, i in ids.items():
         model, L, R, sweeps, every, rec, h, keep = JOBS[i]
         say("job", i, "model", model, "L", L, "R", R)

@@ -84,3 +84,21 @@ def test_create_checks_buffers_before_device_work(pt):
         pt.pt_create(pt.Config(0, 16, 2, np.array([0.3, 0.4]), init_spins=bad), 0, 256, 1 << 30)
     with pytest.raises(pt.PTError, match="workspace of 1024 bytes"):
         pt.pt_create(cfg, 0, 256, 1024)
+
+
+def test_server_options_are_checked(pt):
+    """Server options are validated on the host: the table size grows with the
+    batched lanes the size classes add, and bad options are refused."""
+    one = pt.pt_server_overhead_bytes(pt.server_opts(class_sites=()))
+    two = pt.pt_server_overhead_bytes(pt.server_opts(class_sites=(4096,)))
+    three = pt.pt_server_overhead_bytes(pt.server_opts(class_sites=(4096, 65536)))
+    assert one < two < three
+    for kw, msg in [(dict(class_sites=(4096, 4096)), "ascend"),
+                    (dict(class_sites=(65536, 4096)), "ascend"),
+                    (dict(class_sites=(0, 4096)), "after a zero entry"),
+                    (dict(tiled_lanes=0), "tiled_lanes"),
+                    (dict(depth=9), "depth"),
+                    (dict(cycle_sweeps=17), "cycle_sweeps"),
+                    (dict(max_jobs=0), "max_jobs")]:
+        with pytest.raises(pt.PTError, match=msg):
+            pt.pt_server_overhead_bytes(pt.server_opts(**kw))

@@ -256,8 +256,8 @@ void pt_batch_destroy(pt_batch *b);
  * their own, so that small jobs are not paced by large ones.  Larger 2D lattices join
  * a tiled lane: a stream whose cycles run up to tiled_sweeps sweeps of every
  * resident job's tiles in one launch per lattice size, each job's last
- * workgroup folding its energies, records and exchange step; tiled lanes and
- * the batched lane run concurrently.  A job's results depend only on its own
+ * workgroup folding its energies, records and exchange step; all lanes run
+ * concurrently.  A job's results depend only on its own
  * pt_config (seed, stream_id, ...) and schedule, never on what else is
  * resident: they are bit-identical to running it alone with
  * pt_run(ctx, n_sweeps, exchange_every).  When a job finishes its observables
@@ -270,10 +270,10 @@ typedef struct pt_server pt_server;
 
 typedef struct {
   uint32_t max_jobs;       /* resident jobs at once, 1 .. 65536 */
-  uint32_t max_walkers;    /* per lane: resident replicas (batched lane) or replica tiles (tiled lanes) */
-  uint32_t tiled_lanes;    /* streams for jobs too large for the batched lane, 1 .. 8 */
+  uint32_t max_walkers;    /* per lane: resident replicas (batched lanes) or replica tiles (tiled lanes) */
+  uint32_t tiled_lanes;    /* streams for jobs too large for the batched lanes, 1 .. 8 */
   uint32_t depth;          /* steps in flight per lane, 1 .. 8 */
-  uint32_t cycle_sweeps;   /* batched lane: at most this many sweeps per cycle, 1 .. 16 */
+  uint32_t cycle_sweeps;   /* batched lanes: at most this many sweeps per cycle, 1 .. 16 */
   uint32_t tiled_sweeps;   /* tiled lanes: at most this many sweeps per cycle, 1 .. PT_MAX_SWEEPS_PER_LAUNCH */
   uint32_t class_sites[PT_SERVER_CLASSES]; /* size classes of the batched lanes: ascending
                               sites-per-replica bounds, unused entries 0 (all 0: one batched

@@ -43,7 +43,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="ising2d_L1024_R64")
-    ap.add_argument("--plan", choices=["auto", "fused", "tiled", "persistent", "lanes"],
+    ap.add_argument("--plan", choices=["auto", "fused", "tiled", "persistent", "lanes", "wave"],
                     default="auto", help="launch decomposition (every plan gives identical results)")
     ap.add_argument("--tile-planes", type=int, default=0)
     ap.add_argument("--sweeps-per-launch", type=int, default=0)
@@ -455,7 +455,8 @@ def main():
     if args.plan != "auto" or args.tile_planes or args.sweeps_per_launch or args.threads:
         p = sim.plan()
         mode = {"auto": p["mode"], "fused": pt.PT_PLAN_FUSED, "tiled": pt.PT_PLAN_TILED,
-                "persistent": pt.PT_PLAN_PERSISTENT, "lanes": pt.PT_PLAN_LANES}[args.plan]
+                "persistent": pt.PT_PLAN_PERSISTENT, "lanes": pt.PT_PLAN_LANES,
+                "wave": pt.PT_PLAN_WAVE}[args.plan]
         if args.plan == "auto" and (args.tile_planes or args.sweeps_per_launch):
             mode = pt.PT_PLAN_TILED
         sim.set_plan(mode, args.tile_planes or p["tile_planes"],
@@ -508,7 +509,7 @@ def main():
     split = plan["mode"] == pt.PT_PLAN_PERSISTENT and w.dim == 3 and plan["tile_planes"] == w.L // 2
     kernel = {pt.PT_PLAN_TILED: "k_tiled_n" if w.dim == 2 else "k_tiled", pt.PT_PLAN_FUSED: "k_fused",
               pt.PT_PLAN_PERSISTENT: "k_persist_split" if split else "k_persist",
-              pt.PT_PLAN_LANES: "k_lanes"}[plan["mode"]]
+              pt.PT_PLAN_LANES: "k_lanes", pt.PT_PLAN_WAVE: "k_wave"}[plan["mode"]]
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 VALU lane slots)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": measured_traffic(kernel, w.name, plan, per_launch), "kernel": kernel,

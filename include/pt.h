@@ -104,13 +104,19 @@ typedef struct {
  *               each lane holds one walker's whole lattice in registers and
  *               updates it site after site; one workgroup runs every walker and
  *               the exchange steps.  2D, L = 8 or 16, R <= 1024 only; never
- *               chosen automatically (a reference point for the other plans). */
+ *               chosen automatically (a reference point for the other plans).
+ *   WAVE        small 2D lattices: each walker in the registers of L^2/8 lanes
+ *               of one wavefront, eight sites per lane, neighbours read across
+ *               lanes, so a sweep needs no barrier; one workgroup runs every
+ *               walker and the exchange steps.  2D, L = 8 or 16, R L^2/8 <=
+ *               1024; block_threads follows R. */
 typedef enum {
   PT_PLAN_AUTO = 0,
   PT_PLAN_FUSED = 1,
   PT_PLAN_TILED = 2,
   PT_PLAN_PERSISTENT = 3,
-  PT_PLAN_LANES = 4
+  PT_PLAN_LANES = 4,
+  PT_PLAN_WAVE = 5
 } pt_plan_mode;
 typedef struct {
   uint32_t mode;              /* pt_plan_mode */

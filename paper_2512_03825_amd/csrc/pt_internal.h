@@ -144,6 +144,12 @@ hipError_t launch_fused(const DevState &st, const Geometry &g, const Keys &k, ui
 hipError_t launch_lanes(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
                         const Schedule &sch, hipStream_t stream);
 size_t lanes_lds_bytes(const Geometry &g);
+// Each walker in the registers of L^2/8 lanes of one wavefront, one nibble
+// dword per lane (2D, L = 8 or 16, R L^2/8 <= 1024 threads), one workgroup.
+hipError_t launch_wave(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
+                       const Schedule &sch, hipStream_t stream);
+size_t wave_lds_bytes(const Geometry &g);
+uint32_t wave_threads(const Geometry &g);
 // One co-resident workgroup per walker (parts = 1), or in 3D two per walker,
 // each holding half of the z-planes (parts = 2), for the whole launch; exchange
 // decisions are taken pairwise through per-slot mailboxes (cooperative launch).

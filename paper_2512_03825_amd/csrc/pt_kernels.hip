@@ -35,6 +35,9 @@
 //   k_persist_split  3D: two co-resident workgroups per walker (half the
 //                  z-planes each, two halo planes per side), trading boundary
 //                  planes and energy shares once per sweep as tagged words.
+//   k_wave         small 2D lattices: each walker in the registers of the
+//                  lanes of one wavefront (a nibble dword per lane), neighbours
+//                  by cross-lane reads, no barrier within a sweep.
 //   k_lanes        the paper's decomposition: one walker per lane, its lattice
 //                  in registers, sites visited one after another.
 //   k_batch_*      batched and served forms: many instances per launch.
@@ -746,6 +749,91 @@ __host__ __device__ inline FusedLayout fused_layout(uint32_t R, uint32_t N, uint
   return f;
 }
 
+// The LDS tables of the single-workgroup kernels (fused and wave plans).
+struct FusedTables {
+  uint32_t *thr, *wat, *sof, *xoff, *xD, *xatt, *xacc;
+  int32_t *E, *M, *xfs;
+  uint64_t *xsat, *xtab;
+};
+
+__device__ __forceinline__ FusedTables fused_tables(uint8_t *smem, const FusedLayout &F) {
+  FusedTables t;
+  t.thr = reinterpret_cast<uint32_t *>(smem + F.thr);
+  t.wat = reinterpret_cast<uint32_t *>(smem + F.wat);
+  t.sof = reinterpret_cast<uint32_t *>(smem + F.sof);
+  t.E = reinterpret_cast<int32_t *>(smem + F.E);
+  t.M = reinterpret_cast<int32_t *>(smem + F.M);
+  t.xoff = reinterpret_cast<uint32_t *>(smem + F.xoff);
+  t.xD = reinterpret_cast<uint32_t *>(smem + F.xD);
+  t.xfs = reinterpret_cast<int32_t *>(smem + F.xfs);
+  t.xatt = reinterpret_cast<uint32_t *>(smem + F.xatt);
+  t.xacc = reinterpret_cast<uint32_t *>(smem + F.xacc);
+  t.xsat = reinterpret_cast<uint64_t *>(smem + F.xsat);
+  t.xtab = reinterpret_cast<uint64_t *>(smem + F.xtab);
+  return t;
+}
+
+// Stage every slot's thresholds, the walker/slot maps, E and M, the swap test's
+// per-pair data and (ntab > 0) the swap-table rows; the exchange counters start
+// at zero and are added to device memory at the end of the launch.
+__device__ __forceinline__ void fused_stage(const FusedArgs &a, const FusedTables &t, uint32_t tid,
+                                            uint32_t nt) {
+  const uint32_t R = a.geo.R;
+  for (uint32_t q = tid; q < R * kClasses; q += nt) t.thr[q] = a.st.flip_thr[q];
+  for (uint32_t q = tid; q < R; q += nt) {
+    t.wat[q] = a.st.walker_at[q];
+    t.sof[q] = a.st.slot_of[q];
+    t.E[q] = a.st.E[q];
+    t.M[q] = a.st.M[q];
+    t.xoff[q] = a.st.swap_off[q];
+    t.xD[q] = a.st.swap_D[q];
+    t.xfs[q] = a.st.field_sign[q];
+    t.xatt[q] = 0u;
+    t.xacc[q] = 0u;
+    t.xsat[2u * q] = a.st.swap_sat[2u * q];
+    t.xsat[2u * q + 1u] = a.st.swap_sat[2u * q + 1u];
+  }
+  for (uint32_t q = tid; q < a.ntab; q += nt) t.xtab[q] = a.st.swap_tab[q];
+}
+
+__device__ __forceinline__ SwapView fused_swap_view(const FusedArgs &a, const FusedTables &t) {
+  return SwapView{a.ntab ? t.xtab : a.st.swap_tab, t.xoff, t.xD, t.xsat, a.st.swap_n};
+}
+
+// Exchange step e (pairs of parity e & 1) on the LDS maps, pairs spread over
+// the threads; E and M of every walker must be in LDS.
+__device__ __forceinline__ void fused_exchange(const FusedArgs &a, const FusedTables &t,
+                                               const SwapView &sv, uint32_t e, uint32_t tid,
+                                               uint32_t nt) {
+  const uint32_t R = a.geo.R;
+  for (uint32_t kk = (e & 1u) + 2u * tid; kk + 1u < R; kk += 2u * nt) {
+    const uint32_t wa = t.wat[kk], wb = t.wat[kk + 1u];
+    const uint32_t r = philox(kk, e, 0u, kPurposeSwap, a.key.k0, a.key.k1).x;
+    ++t.xatt[kk];
+    if ((uint64_t)r < swap_T(sv, kk, t.E[wa] - t.E[wb]) &&
+        field_factor(a.st, t.xfs[kk], kk, e, t.M[wa] - t.M[wb], a.key.k0, a.key.k1)) {
+      t.wat[kk] = wb;
+      t.wat[kk + 1u] = wa;
+      t.sof[wa] = kk + 1u;
+      t.sof[wb] = kk;
+      ++t.xacc[kk];
+    }
+  }
+}
+
+// Maps, E, M and the launch's exchange counts back to device memory.
+__device__ __forceinline__ void fused_write_back(const FusedArgs &a, const FusedTables &t,
+                                                 uint32_t tid, uint32_t nt) {
+  for (uint32_t q = tid; q < a.geo.R; q += nt) {
+    a.st.walker_at[q] = t.wat[q];
+    a.st.slot_of[q] = t.sof[q];
+    a.st.E[q] = t.E[q];
+    a.st.M[q] = t.M[q];
+    a.st.att[q] += t.xatt[q];
+    a.st.acc[q] += t.xacc[q];
+  }
+}
+
 // PF: every thread holds at most one item (items <= threads), which then stays
 // the same for the whole launch.  The draws of sweep s + 1 are computed during
 // sweep s with the walker's current slot, off the latency chain of the sweep,
@@ -759,37 +847,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   const uint32_t lgPl = lgL + lgG;                           // dwords per plane (3D)
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const FusedLayout F = fused_layout(R, N, DIM, a.ntab);
-  uint32_t *thr = reinterpret_cast<uint32_t *>(smem + F.thr);
-  uint32_t *wat = reinterpret_cast<uint32_t *>(smem + F.wat);
-  uint32_t *sof = reinterpret_cast<uint32_t *>(smem + F.sof);
-  int32_t *E = reinterpret_cast<int32_t *>(smem + F.E);
-  int32_t *M = reinterpret_cast<int32_t *>(smem + F.M);
-  uint32_t *xoff = reinterpret_cast<uint32_t *>(smem + F.xoff);
-  uint32_t *xD = reinterpret_cast<uint32_t *>(smem + F.xD);
-  int32_t *xfs = reinterpret_cast<int32_t *>(smem + F.xfs);
-  uint32_t *xatt = reinterpret_cast<uint32_t *>(smem + F.xatt);
-  uint32_t *xacc = reinterpret_cast<uint32_t *>(smem + F.xacc);
-  uint64_t *xsat = reinterpret_cast<uint64_t *>(smem + F.xsat);
-  uint64_t *xtab = reinterpret_cast<uint64_t *>(smem + F.xtab);
+  const FusedTables T = fused_tables(smem, F);
+  uint32_t *thr = T.thr, *sof = T.sof;
+  int32_t *E = T.E, *M = T.M;
   uint32_t *sp = reinterpret_cast<uint32_t *>(smem + F.spins);   // [R][N/8] nibble dwords
   uint32_t *bx = reinterpret_cast<uint32_t *>(smem + F.bonds), *by = bx + (N >> 3), *bz = by + (N >> 3);
 
-  for (uint32_t q = tid; q < R * kClasses; q += nt) thr[q] = a.st.flip_thr[q];
-  for (uint32_t q = tid; q < R; q += nt) {
-    wat[q] = a.st.walker_at[q];
-    sof[q] = a.st.slot_of[q];
-    E[q] = a.st.E[q];
-    M[q] = a.st.M[q];
-    xoff[q] = a.st.swap_off[q];
-    xD[q] = a.st.swap_D[q];
-    xfs[q] = a.st.field_sign[q];
-    xatt[q] = 0u;
-    xacc[q] = 0u;
-    xsat[2u * q] = a.st.swap_sat[2u * q];
-    xsat[2u * q + 1u] = a.st.swap_sat[2u * q + 1u];
-  }
-  for (uint32_t q = tid; q < a.ntab; q += nt) xtab[q] = a.st.swap_tab[q];
-  const SwapView sv{a.ntab ? xtab : a.st.swap_tab, xoff, xD, xsat, a.st.swap_n};
+  fused_stage(a, T, tid, nt);
+  const SwapView sv = fused_swap_view(a, T);
   unpack_tile_n(sp, a.spins, 0u, (R * N) >> 5, 0xFFFFFFFFu, tid, nt);
   if (DIM == 3) unpack_tile_n(bx, a.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
   __syncthreads();
@@ -900,19 +965,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
     }
     if (do_ex) {
       __syncthreads(); // records read the maps before the exchange rewrites them
-      for (uint32_t kk = (e & 1u) + 2u * tid; kk + 1u < R; kk += 2u * nt) {
-        const uint32_t wa = wat[kk], wb = wat[kk + 1u];
-        const uint32_t r = philox(kk, e, 0u, kPurposeSwap, a.key.k0, a.key.k1).x;
-        ++xatt[kk];
-        if ((uint64_t)r < swap_T(sv, kk, E[wa] - E[wb]) &&
-            field_factor(a.st, xfs[kk], kk, e, M[wa] - M[wb], a.key.k0, a.key.k1)) {
-          wat[kk] = wb;
-          wat[kk + 1u] = wa;
-          sof[wa] = kk + 1u;
-          sof[wb] = kk;
-          ++xacc[kk];
-        }
-      }
+      fused_exchange(a, T, sv, e, tid, nt);
       ++e;
       __syncthreads();
       if constexpr (PF) {
@@ -931,14 +984,142 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
 
   __syncthreads(); // the last exchange's counters
   pack_tile_n(a.spins, sp, (R * N) >> 5, tid, nt);
-  for (uint32_t q = tid; q < R; q += nt) {
-    a.st.walker_at[q] = wat[q];
-    a.st.slot_of[q] = sof[q];
-    a.st.E[q] = E[q];
-    a.st.M[q] = M[q];
-    a.st.att[q] += xatt[q];
-    a.st.acc[q] += xacc[q];
+  fused_write_back(a, T, tid, nt);
+}
+
+// Sum of v over each aligned group of 16 lanes (DPP row rotations, every lane
+// ends with its row's sum).
+__device__ __forceinline__ int row_sum16(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, false); // row_ror:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x122, 0xF, 0xF, false); // row_ror:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false); // row_ror:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false); // row_ror:8
+  return v;
+}
+
+// The value of lane l ^ 16 (ds_swizzle, bit-mask mode: and 0x1F, or 0, xor 0x10).
+__device__ __forceinline__ int swap16(int v) { return __builtin_amdgcn_ds_swizzle(v, 0x401F); }
+
+// Wave plan (2D, L = 8 or 16): walker w's lattice lives in the registers of
+// lanes [w G, (w + 1) G) of the workgroup, G = L^2/8, one nibble dword (one
+// Philox group) per lane.  G divides 64, so a walker's lanes sit in one
+// wavefront and a half sweep takes the rows above and below and the edge dword
+// from them with cross-lane moves: no barrier and no LDS traffic for the
+// lattice.  At L = 16 lane w G + 16 g + y holds dword g of row y, so the rows
+// above and below are the neighbours in the lane's 16-lane DPP row (rotations,
+// periodic like the lattice; the stencil adds both, so the direction of a
+// rotation does not matter) and the edge dword is lane ^ 16; at L = 8 lane
+// w G + y holds row y and the moves are lane permutes.  Each walker's E and M
+// stay in its lanes' registers (the changes of a sweep summed over the group);
+// thresholds, maps and swap data sit in LDS as in the fused plan, and an
+// exchange step takes two barriers.  As in the fused plan the next sweep's
+// draws are computed during the current one, off the sweep's dependency chain.
+template <int LL>
+__global__ __launch_bounds__(kMaxThreads) void k_wave(FusedArgs a) {
+  constexpr uint32_t GPR = LL / 8, LG_GPR = LL == 16 ? 1u : 0u; // dwords per row
+  constexpr uint32_t G = LL * LL / 8, NW = LL * LL / 32;        // lanes, packed words per walker
+  static_assert(LL == 8 || LL == 16, "wave plan: L = 8 or 16");
+  extern __shared__ __align__(16) uint8_t smem[];
+  const uint32_t R = a.geo.R, tid = threadIdx.x, nt = blockDim.x;
+  const FusedTables T = fused_tables(smem, fused_layout(R, 0u, 2u, a.ntab));
+  fused_stage(a, T, tid, nt);
+  const SwapView sv = fused_swap_view(a, T);
+
+  const uint32_t w = tid / G, lw = tid % G; // lane within the walker's group
+  const bool live = w < R;
+  const uint32_t y = LL == 16 ? (lw & 15u) : lw, g = LL == 16 ? (lw >> 4) : 0u;
+  const uint32_t li = (y << LG_GPR) | g; // the group's index: its Philox counter and packed byte
+  const uint32_t base = (tid & 63u) & ~(G - 1u); // the walker's first lane in the wavefront (L = 8)
+  const int src_up = (int)(base + ((y + LL - 1u) % LL)), src_dn = (int)(base + ((y + 1u) % LL));
+  // byte li of the packed lattice holds this dword's 8 sites
+  uint8_t *bytes = reinterpret_cast<uint8_t *>(a.spins + (size_t)(live ? w : 0u) * NW);
+  uint32_t sw = live ? spread8(bytes[li]) : 0u;
+  __syncthreads();
+
+  uint32_t dslot = live ? T.sof[w] : 0u; // the walker's slot (and that of the draws in rc)
+  int32_t Ew = live ? T.E[w] : 0, Mw = live ? T.M[w] : 0;
+  Words rc[2];
+#pragma unroll
+  for (uint32_t c = 0; c < 2u; ++c)
+    rc[c] = philox(li, a.sch.s0, dslot, c | kPurposeFlip, a.key.k0, a.key.k1);
+  uint32_t rec = a.sch.rec_base, e = a.sch.ex_step;
+  for (uint32_t j = 0; j < a.sch.nsw; ++j) {
+    const uint32_t s = a.sch.s0 + j;
+    const uint8_t *tb = reinterpret_cast<const uint8_t *>(T.thr + dslot * kClasses);
+    TallyN t = {0u, 0u, 0u};
+    Words rn[2];
+#pragma unroll
+    for (uint32_t c = 0; c < 2u; ++c) {
+      rn[c] = philox(li, s + 1u, dslot, c | kPurposeFlip, a.key.k0, a.key.k1);
+      const uint32_t off = (c + y) & 1u;
+      uint32_t up, dn, ed; // rows y -+ 1, and the row's other dword (the edge the colour sites need)
+      if constexpr (LL == 16) {
+        up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sw, 0x121, 0xF, 0xF, false); // row_ror:1
+        dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)sw, 0x12F, 0xF, 0xF, false); // row_ror:15
+        ed = (uint32_t)swap16((int)sw);
+      } else {
+        up = (uint32_t)__shfl((int)sw, src_up, 64);
+        dn = (uint32_t)__shfl((int)sw, src_dn, 64);
+        ed = sw; // one dword per row: its own edge, periodic
+      }
+      const uint32_t l = __builtin_amdgcn_alignbit(sw, ed, 28u);
+      const uint32_t rr = __builtin_amdgcn_alignbit(ed, sw, 4u);
+      uint32_t u = rr ^ sw;
+      u = xad(l, sw, u);
+      u = xad(dn, sw, u);
+      u = xad(up, sw, u);
+      sw = decide_n(sw, u, off, rc[c], tb, t);
+    }
+    rc[0] = rn[0];
+    rc[1] = rn[1];
+    // the walker's changes of this sweep, dE in the high half and dM (|dM| <= N
+    // < 2^15) in the low half of one sum over its G lanes
+    int32_t d = (a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb)) * 65536 +
+                (4 * (int)t.sb - 2 * (int)t.n);
+    if constexpr (LL == 16) {
+      d = row_sum16(d);
+      d += swap16(d);
+    } else {
+#pragma unroll
+      for (uint32_t m = G / 2u; m >= 1u; m >>= 1) d += __shfl_xor(d, (int)m, 64);
+    }
+    const int32_t dM = ((d & 0xFFFF) ^ 0x8000) - 0x8000;
+    Ew += (d - dM) / 65536;
+    Mw += dM;
+    if (a.sch.record_every && (s + 1u) % a.sch.record_every == 0u) {
+      if (live && lw == 0u) {
+        a.st.E_series[(size_t)rec * R + dslot] = Ew;
+        a.st.M_series[(size_t)rec * R + dslot] = Mw;
+      }
+      ++rec;
+    }
+    if (a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u) {
+      if (live && lw == 0u) {
+        T.E[w] = Ew;
+        T.M[w] = Mw;
+      }
+      __syncthreads();
+      fused_exchange(a, T, sv, e, tid, nt);
+      ++e;
+      __syncthreads();
+      const uint32_t ns = live ? T.sof[w] : 0u;
+      if (ns != dslot) { // the walker moved: its next draws belong to the new slot
+        dslot = ns;
+#pragma unroll
+        for (uint32_t c = 0; c < 2u; ++c)
+          rc[c] = philox(li, s + 1u, dslot, c | kPurposeFlip, a.key.k0, a.key.k1);
+      }
+    }
   }
+  if (live) {
+    bytes[li] = (uint8_t)gather8(sw);
+    if (lw == 0u) {
+      T.E[w] = Ew;
+      T.M[w] = Mw;
+    }
+  }
+  __syncthreads();
+  fused_write_back(a, T, tid, nt);
 }
 
 struct PersistArgs {
@@ -2021,6 +2202,41 @@ hipError_t launch_lanes(const DevState &st, const Geometry &g, const Keys &k, ui
     hipLaunchKernelGGL(k_lanes<8>, dim3(1), dim3(threads), lds, stream, a);
   else
     hipLaunchKernelGGL(k_lanes<16>, dim3(1), dim3(threads), lds, stream, a);
+  return hipGetLastError();
+}
+
+size_t wave_lds_bytes(const Geometry &g) { return fused_layout(g.R, 0u, 2u, 0u).total; }
+
+uint32_t wave_threads(const Geometry &g) { return (g.R * (g.N / 8u) + 63u) & ~63u; }
+
+hipError_t launch_wave(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
+                       const Schedule &sch, hipStream_t stream) {
+  const uint32_t threads = wave_threads(g);
+  if (g.dim != 2 || (g.L != 8 && g.L != 16) || threads > (uint32_t)kMaxThreads)
+    return hipErrorInvalidValue;
+  FusedArgs a;
+  a.st = st;
+  a.geo = g;
+  a.key = k;
+  a.sch = sch;
+  a.spins = st.spins[cur];
+  a.lg_L = ilog2(g.L);
+  a.lg_spr = 0u;
+  a.lg_rows = 0u;
+  a.lg_items = 0u;
+  a.z2 = 8;
+  // the swap-table rows go to LDS when they are small and fit beside the rest
+  a.ntab = 0u;
+  if ((size_t)st.swap_n * 8u <= 32u * 1024u &&
+      fused_layout(g.R, 0u, 2u, st.swap_n).total <= max_lds_bytes())
+    a.ntab = st.swap_n;
+  const size_t lds = fused_layout(g.R, 0u, 2u, a.ntab).total;
+  hipError_t err = g.L == 8 ? allow_lds(k_wave<8>, lds) : allow_lds(k_wave<16>, lds);
+  if (err != hipSuccess) return err;
+  if (g.L == 8)
+    hipLaunchKernelGGL(k_wave<8>, dim3(1), dim3(threads), lds, stream, a);
+  else
+    hipLaunchKernelGGL(k_wave<16>, dim3(1), dim3(threads), lds, stream, a);
   return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ from paper_2512_03825_amd.workloads import beta_geometric, beta_linear
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
-FUSED, TILED, PERSISTENT, LANES = 1, 2, 3, 4
+FUSED, TILED, PERSISTENT, LANES, WAVE = 1, 2, 3, 4, 5
 
 
 @pytest.fixture(scope="module")
@@ -45,6 +45,7 @@ def run_both(pt, oracle_mod, model, L, R, beta, sweeps, every, plan=None, rec=1,
     (0, 64, dict(mode=TILED, tile_planes=16, sweeps_per_launch=3, block_threads=256)),
     (0, 32, dict(mode=PERSISTENT, block_threads=256)),
     (0, 16, dict(mode=LANES)),
+    (0, 16, dict(mode=WAVE)),
     (1, 16, None),
     (1, 32, dict(mode=PERSISTENT, tile_planes=16, block_threads=512)),
 ])
@@ -108,7 +109,7 @@ def test_auto_plans_of_the_bench_workloads(pt):
     plan picks for the benchmarked workloads."""
     from paper_2512_03825_amd.workloads import WORKLOADS
     want = {
-        "ising2d_L16_R8": dict(mode=FUSED, block_threads=128),
+        "ising2d_L16_R8": dict(mode=WAVE, block_threads=256),
         "ising2d_L1024_R64": dict(mode=TILED, tile_planes=256, sweeps_per_launch=5, block_threads=1024),
         "ea3d_L32_R128": dict(mode=PERSISTENT, tile_planes=16, block_threads=512),
         "paper_shape_L256_R1500": dict(mode=TILED, tile_planes=256, sweeps_per_launch=8,

@@ -17,7 +17,7 @@ from paper_2512_03825_amd.workloads import beta_geometric, beta_linear
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
-FUSED, TILED, PERSISTENT, LANES = 1, 2, 3, 4
+FUSED, TILED, PERSISTENT, LANES, WAVE = 1, 2, 3, 4, 5
 PT_EINVAL = -1
 N_CASES = 120
 
@@ -39,7 +39,7 @@ def draw_case(i):
     every = int(rng.choice([0, 1, 2, 3, 5]))
     rec = int(rng.choice([0, 1, 2, 3]))
     # 3D cases lean to the persistent plans (one or two workgroups per walker)
-    modes = [FUSED, TILED, PERSISTENT, LANES] if model == 0 else [FUSED, TILED, PERSISTENT, PERSISTENT]
+    modes = [FUSED, TILED, PERSISTENT, LANES, WAVE] if model == 0 else [FUSED, TILED, PERSISTENT, PERSISTENT]
     mode = int(rng.choice(modes))
     threads = int(rng.integers(1, 17)) * 64
     plan = dict(mode=mode, block_threads=threads)

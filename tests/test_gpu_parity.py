@@ -14,7 +14,7 @@ from paper_2512_03825_amd.workloads import beta_geometric, beta_linear, ising16
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
-FUSED, TILED, PERSISTENT, LANES = 1, 2, 3, 4
+FUSED, TILED, PERSISTENT, LANES, WAVE = 1, 2, 3, 4, 5
 
 
 @pytest.fixture(scope="module")
@@ -54,7 +54,7 @@ def test_ising16_full_run_auto_plan(pt, oracle_mod):
     w = ising16()
     sim, orc = run_case(pt, oracle_mod, 0, w.L, w.R, w.beta, w.seed, w.sweeps, w.exchange_every,
                         tag="ising16")
-    assert sim.plan()["mode"] == FUSED
+    assert sim.plan()["mode"] == WAVE
     assert orc.swaps()[1].sum() > 0  # swaps really happen
 
 
@@ -65,6 +65,7 @@ def test_ising16_full_run_auto_plan(pt, oracle_mod):
     dict(mode=FUSED, block_threads=64),
     dict(mode=FUSED, block_threads=1024),
     dict(mode=LANES),                                                           # one walker per lane
+    dict(mode=WAVE),                                                            # walkers in wavefronts
 ])
 def test_ising16_every_plan_is_identical(pt, oracle_mod, plan):
     w = ising16()
@@ -283,6 +284,51 @@ def test_lanes_plan_matches_oracle(pt, oracle_mod, L, R, every, h, split):
         sim.run(sweeps, every)
         orc.run(sweeps, every)
     compare(sim, orc, tag)
+
+
+@pytest.mark.parametrize("L, R, every, h, split, rec", [
+    (8, 5, 3, 0.0, False, 1),
+    (16, 32, 10, 0.0, False, 1),     # the largest R at L = 16: 1024 lanes
+    (16, 9, 1, 0.15, True, 1),       # field swaps, primitive calls
+    (8, 1, 0, 0.0, False, 1),        # one walker, no exchange
+    (8, 128, 2, 0.05, False, 3),     # the largest R at L = 8, records every third sweep
+    (16, 3, 7, -0.1, False, 0),      # no records, odd R
+    (16, 2, 1, 0.0, False, 2),       # two walkers in one wavefront
+    (16, 1, 1, 0.0, True, 1),        # one walker, exchange steps with no pair
+])
+def test_wave_plan_matches_oracle(pt, oracle_mod, L, R, every, h, split, rec):
+    """Walkers held in the registers of one wavefront's lanes, against the oracle."""
+    beta = beta_linear(0.25, 0.7, R)
+    sweeps = 60
+    tag = "wave L%d R%d" % (L, R)
+    say("case", tag, "every", every, "h", h, "rec", rec)
+    nrec = sweeps // rec if rec else 0
+    cfg = pt.Config(0, L, R, beta, h=h, seed=23, stream_id=4, record_every=rec, max_records=nrec)
+    sim = pt.Simulation(cfg)
+    sim.set_plan(WAVE)
+    assert sim.plan()["mode"] == WAVE
+    assert sim.plan()["block_threads"] == (R * L * L // 8 + 63) // 64 * 64
+    orc = oracle_mod.Oracle(0, L, R, beta, h=h, seed=23, stream_id=4, record_every=rec,
+                            max_records=nrec)
+    if split:
+        for _ in range(sweeps // every):
+            sim.sweep(every)
+            sim.exchange()
+            orc.sweep(every)
+            orc.exchange()
+    else:
+        sim.run(sweeps, every)
+        orc.run(sweeps, every)
+    compare(sim, orc, tag)
+
+
+def test_wave_plan_rejects_other_shapes(pt):
+    for model, L, R in ((0, 32, 4), (1, 8, 4), (0, 16, 33), (0, 8, 129)):
+        beta = beta_linear(0.3, 0.5, R)
+        sim = pt.Simulation(pt.Config(model, L, R, beta, seed=1))
+        with pytest.raises(pt.PTError):
+            sim.set_plan(WAVE)
+        sim.close()
 
 
 def test_lanes_plan_rejects_other_shapes(pt):

@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--tile-planes", type=int, default=0)
     ap.add_argument("--sweeps-per-launch", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--exchange-every", type=int, default=-1,
+                    help="plain form: override the workload's exchange interval in sweeps "
+                         "(0: no exchange steps; -1: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
     ap.add_argument("--form", choices=["plain", "batched", "served", "physics"], default="plain",
@@ -106,12 +109,12 @@ def measured_traffic(kernel, workload, plan, per_launch):
     return int(fields["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(w, sweeps):
+def cpu_baseline(w, sweeps, every):
     """The CPU oracle, as it stands, on a bounded prefix of the same workload."""
     import oracle
     o = oracle.Oracle(w.model, w.L, w.R, w.beta, seed=w.seed, coupling_seed=w.coupling_seed)
     t0 = time.perf_counter()
-    o.run(sweeps, w.exchange_every)
+    o.run(sweeps, every)
     dt = time.perf_counter() - t0
     attempts = sweeps * w.attempts_per_sweep
     return {"value": attempts / dt, "unit": "flip attempts/s", "cores": 1, "kind": "oracle",
@@ -442,7 +445,7 @@ def main():
 
     w = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
-    every = w.exchange_every
+    every = w.exchange_every if args.exchange_every < 0 else args.exchange_every
     # a step is 10 sweeps of the workload's schedule (a whole number of
     # exchange intervals), so one step is one launch for the fused and
     # persistent plans and a few launches for the tiled plan
@@ -551,7 +554,7 @@ def main():
     if not args.no_cpu_baseline:
         # a bounded sample: at most ~3*10^8 attempts (tens of seconds on one core)
         out["cpu_baseline"] = cpu_baseline(w, max(1, min(args.cpu_sweeps,
-                                                         int(3e8 // w.attempts_per_sweep))))
+                                                         int(3e8 // w.attempts_per_sweep))), every)
     sim.close()
     print(json.dumps(out), flush=True)
 

@@ -509,7 +509,7 @@ def main():
     hbm_bytes = w.R * ((w.L + halo_planes) * plane_bits + w.L * plane_bits) / 8
     if w.dim == 3:
         hbm_bytes += 3 * w.sites / 8 * (tiles if tiles > 1 else 1)  # packed couplings, read once per tile
-    split = plan["mode"] == pt.PT_PLAN_PERSISTENT and w.dim == 3 and plan["tile_planes"] == w.L // 2
+    split = plan["mode"] == pt.PT_PLAN_PERSISTENT and plan["tile_planes"] < w.L
     kernel = {pt.PT_PLAN_TILED: "k_tiled_n" if w.dim == 2 else "k_tiled", pt.PT_PLAN_FUSED: "k_fused",
               pt.PT_PLAN_PERSISTENT: "k_persist_split" if split else "k_persist",
               pt.PT_PLAN_LANES: "k_lanes", pt.PT_PLAN_WAVE: "k_wave"}[plan["mode"]]
@@ -523,10 +523,12 @@ def main():
                 "hbm_algorithmic_bytes_per_launch": int(hbm_bytes),
                 "hbm_algorithmic_GBps": round(hbm_bytes / (avg_ms * 1e-3) / 1e9, 1)}
     if split:
-        # two workgroups per walker post their boundary planes and energy shares
-        # every sweep (64-bit tagged words) and read the sibling's
-        post_bytes = 2 * 8 * (w.L * w.L // 8 + 2)
-        roofline["boundary_post_bytes_per_launch"] = 2 * post_bytes * w.R * per_launch
+        # each of the P workgroups of a walker posts its two lowest and two
+        # highest planes (rows in 2D) and its energy shares every sweep as 64-bit
+        # tagged words, and reads as many
+        parts = w.L // plan["tile_planes"]
+        post_bytes = 8 * (4 * plane_bits // 32 + 2)
+        roofline["boundary_post_bytes_per_launch"] = 2 * post_bytes * parts * w.R * per_launch
 
     if args.copy_calibration:
         a = torch.empty(64 << 20, dtype=torch.uint8, device="cuda:0").fill_(1)

@@ -162,7 +162,7 @@ Layout layout(const pt_config *cfg, const Derived &d) {
   l.Es = take((size_t)cfg->max_records * R * 4);
   l.Ms = take((size_t)cfg->max_records * R * 4);
   l.counter = take(16);
-  l.mailbox = take(8 * R * 8);
+  l.mailbox = take(4 * kMaxParts * R * 8);
   l.halo = take(split_halo_words(g) * 8);
   l.field = take(R * kFieldDigits * 8);
   l.fsign = take(R * 4);
@@ -226,11 +226,10 @@ pt_status device_fail(pt_ctx *c, hipError_t e, const char *what) {
   return fail(PT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Workgroups per walker of a persistent plan: two when 3D and tile_planes = L/2.
+// Workgroups per walker of a persistent plan: L / tile_planes (1 for 0 or L).
 uint32_t persist_parts(const Geometry &g, const pt_plan &p) {
-  return (p.mode == PT_PLAN_PERSISTENT && g.dim == 3 && g.L >= 16u && g.L <= 32u &&
-          p.tile_planes == g.L / 2u)
-             ? 2u : 1u;
+  if (p.mode != PT_PLAN_PERSISTENT || p.tile_planes == 0u || p.tile_planes >= g.L) return 1u;
+  return g.L / p.tile_planes;
 }
 
 pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
@@ -266,12 +265,12 @@ pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
   if (p.mode == PT_PLAN_PERSISTENT) {
     if (c->cfg.h != 0.0 && g.dim == 2)
       return fail(PT_EINVAL, "the persistent plan exchanges energies only; it needs h = 0");
-    if (p.tile_planes != 0u && p.tile_planes != g.L && p.tile_planes != g.L / 2u)
-      return fail(PT_EINVAL, "persistent plan: tile_planes = %u must be L (one workgroup per walker) "
-                  "or L/2 (two, 3D)", p.tile_planes);
     const uint32_t parts = persist_parts(g, p);
-    if (p.tile_planes == g.L / 2u && parts != 2u)
-      return fail(PT_EINVAL, "persistent plan with two workgroups per walker: 3D with 16 <= L <= 32 only");
+    if (parts > 1u && (g.L % p.tile_planes || (parts & (parts - 1u)) ||
+                       parts > split_max_parts(g) || p.tile_planes < 8u))
+      return fail(PT_EINVAL, "persistent plan: tile_planes = %u must be L (one workgroup per walker) "
+                  "or L/P planes for P workgroups per walker (3D 16 <= L <= 32: P = 2; 2D 64 <= L <= "
+                  "1024: P = 2, 4 or 8; at least 8 planes each)", p.tile_planes);
     const size_t lds = persist_lds_bytes(g, parts);
     if (lds > max_lds_bytes())
       return fail(PT_EINVAL, "persistent plan needs %zu bytes of LDS per workgroup (max %zu)", lds,
@@ -335,6 +334,25 @@ pt_plan auto_plan(const pt_ctx *c) {
     q.tile_planes = g.L / 2u;
     q.sweeps_per_launch = 1;
     if (check_plan(c, q) == PT_OK) return q;
+  }
+  // 2D walkers (h = 0) whose rows split over P co-resident workgroups of L/P
+  // rows, with P R filling the device (one workgroup per compute unit): every
+  // part stays in LDS for a whole run and trades two boundary rows per side
+  // once per sweep (no launch, restaging or recomputed halo between sweeps).
+  if (g.dim == 2 && c->cfg.h == 0.0 && split_max_parts(g)) {
+    for (uint32_t P = 2u; P <= split_max_parts(g); P *= 2u) {
+      if (persist_lds_bytes(g, P) > max_lds_bytes()) continue;
+      pt_plan q{};
+      q.mode = PT_PLAN_PERSISTENT;
+      q.block_threads = 1024;
+      q.tile_planes = g.L / P;
+      q.sweeps_per_launch = 1;
+      const uint32_t cap = persist_max_workgroups(g, q.block_threads, P);
+      if (P * g.R > cap) break;                      // more parts only need more
+      if (8u * P * g.R < 7u * cap) continue;        // most compute units idle: more parts
+      if (check_plan(c, q) == PT_OK) return q;
+      break;
+    }
   }
   // Many walkers whose lattices fit a workgroup's LDS: one co-resident workgroup
   // per walker for a whole run, exchanges decided pairwise (no launch per sweep).

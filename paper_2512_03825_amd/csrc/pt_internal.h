@@ -16,6 +16,7 @@ constexpr uint32_t kPurposeBond = 3u << 8;
 constexpr uint32_t kClasses = 16;      // flip-threshold classes per slot: 8*b + u
 constexpr uint32_t kFieldDigits = 32;  // binary digits of |dM|/2 with a field swap factor
 constexpr uint32_t kMaxSweepsPerLaunch = 8;
+constexpr uint32_t kMaxParts = 8;            // workgroups per walker of the split persistent plan
 
 // Device pointers into the caller's workspace.
 struct DevState {
@@ -39,8 +40,9 @@ struct DevState {
   int32_t *E_series;   // [max_records][R] slot order
   int32_t *M_series;
   uint32_t *counter;   // [4] workgroup-arrival counter of the tiled sweep; [1] persistent-kernel abort flag
-  uint64_t *mailbox;   // [4][R][2] persistent kernels: (step + 1) << 32 | E_int (share) posted by the holder of a slot
-  uint64_t *halo;      // [2][R][2][split_post_words(L)] split persistent plan (3D): per sweep and part,
+  uint64_t *mailbox;   // [4][R][P] persistent kernels (P <= kMaxParts workgroups per walker):
+                       // (step + 1) << 32 | E_int (share) posted by the holder of a slot
+  uint64_t *halo;      // [2][R][P][split_post_words(g)] split persistent plan: per sweep and part,
                        // (sweep + 1) << 32 | word: boundary planes (bit-packed), then E_int and M shares
   uint8_t *staging;    // +-1 bytes uploaded by the host (only if the config uploads)
 };
@@ -157,12 +159,17 @@ hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, 
                           uint32_t threads, uint32_t parts, const Schedule &sch,
                           uint32_t spin_limit, hipStream_t stream);
 // Words one part of a split walker posts per sweep: its two lowest and two
-// highest z-planes bit-packed (4 L^2 / 32), then its E_int and M shares.
-inline uint32_t split_post_words(uint32_t L) { return L * L / 8u + 2u; }
-// The split plan exists for 3D lattices with 16 <= L <= 32 (two parts of L/2
-// planes, each staging two halo planes per side); uint64 words of the post area.
+// highest planes (3D z-planes, 2D rows) bit-packed, then its E_int and M shares.
+inline uint32_t split_post_words(const Geometry &g) { return 4u * (g.plane / 32u) + 2u; }
+// Workgroups per walker the split plan allows: 3D 16 <= L <= 32 two (L/2
+// z-planes each); 2D 64 <= L <= 1024 up to kMaxParts (rows); 0 otherwise.
+inline uint32_t split_max_parts(const Geometry &g) {
+  if (g.dim == 3) return (g.L >= 16u && g.L <= 32u) ? 2u : 0u;
+  return (g.L >= 64u && g.L <= 1024u) ? kMaxParts : 0u;
+}
+// uint64 words of the post area: two generations of every part's post.
 inline size_t split_halo_words(const Geometry &g) {
-  return (g.dim == 3 && g.L >= 16u && g.L <= 32u) ? (size_t)4u * g.R * split_post_words(g.L) : 0u;
+  return (size_t)2u * g.R * split_max_parts(g) * split_post_words(g);
 }
 
 // Groups of 8 sites one lane updates per item (V): 2D min(4, L/8), 3D min(2, L/8).

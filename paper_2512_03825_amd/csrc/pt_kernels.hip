@@ -56,9 +56,11 @@ constexpr int kMaxThreads = 1024;
 // measurement among 2, 4, 8) and the persistent kernel (among 2, 4).
 constexpr uint32_t kNibbleSpan = 8;
 constexpr uint32_t kPersistSpan = 4;
-// Words of a split-plan post each lane of the posting wave handles (L <= 32:
-// at most 4 * 32 + 2 = 130 words over 64 lanes).
+// Words a split-plan part reads per sweep, per lane of the reading wave: the
+// boundary planes (4 x 32 packed words for 3D L <= 32 and 2D L <= 1024) and
+// 2 (P - 1) shares, at most 142 words over 64 lanes.
 constexpr uint32_t kSplitWordsPerLane = 3;
+static_assert(kMaxSweepsPerLaunch * 4u >= 4u * kMaxParts, "k_reset clears the mailboxes in its acc3 loop");
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -1129,7 +1131,7 @@ struct PersistArgs {
   Schedule sch;
   uint32_t *spins; // bit-packed, updated in place
   uint32_t lg_L, lg_spr, lg_rows, lg_items;
-  uint32_t lg_ipp;     // split plan: log2 of the items of one z-plane
+  uint32_t lg_ipp;     // split plan: log2 of the items of one plane (3D z-plane, 2D row)
   int32_t z2;
   uint32_t spin_limit; // polls of a partner's mailbox before the launch gives up
 };
@@ -1300,10 +1302,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
   }
 }
 
-// Split persistent walkers (3D): walker w runs as two co-resident workgroups,
-// part p owning the z-planes [p L/2, (p+1) L/2), so R walkers fill 2R compute
+// Split persistent walkers: walker w runs as P = NPARTS co-resident
+// workgroups, part p owning the Lp = L/P planes [p Lp, (p+1) Lp) -- z-planes in
+// 3D, rows in 2D (a "plane" below is either) -- so R walkers fill P R compute
 // units.  A part stages two halo planes on each side (local planes 0, 1 and
-// L/2+2, L/2+3; its own planes are 2 .. L/2+1).  In the colour-0 half sweep it
+// Lp+2, Lp+3; its own planes are 2 .. Lp+1).  In the colour-0 half sweep it
 // also updates the inner halo plane on each side, with the draws and the
 // threshold row the plane's owner uses, so it computes exactly the owner's
 // values; colour 1 of its own planes then sees correct neighbours, and one
@@ -1312,11 +1315,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
 // shares of E_int and M, and at an exchange step its E_int share in the slot's
 // mailbox; each 64-bit word carries its tag (sweep or step + 1) beside 32 bits
 // of data, so the reader takes data and tag in one relaxed load and needs no
-// fence.  The parts of both walkers of a pair sum the same shares and take the
-// same decision from the same draw.  Two generations of posts suffice: a part
-// cannot post sweep s + 2 before its sibling has posted s + 1, which the
-// sibling does only after reading the post of sweep s.
-template <int V>
+// fence.  A part reads the lower planes of the part above, the upper planes of
+// the part below and the shares of every other part; the parts of both
+// walkers of a pair sum the same shares and take the same decision from the
+// same draw.  Two generations of posts suffice: a part cannot post sweep s + 2
+// before every part has posted s + 1, which each does only after reading every
+// post of sweep s.
+template <int DIM, int V, int NPARTS>
 __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint32_t s_thr[kClasses];
@@ -1324,17 +1329,21 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
   __shared__ uint32_t s_slot, s_stop;
   const Geometry &G = a.geo;
   const uint32_t R = G.R, L = G.L, lgL = a.lg_L, lmask = L - 1u;
-  const uint32_t lgG = lgL - 3u, gmask = (1u << lgG) - 1u; // nibble dwords per row
-  const uint32_t lgPl = lgL + lgG;                          // nibble dwords per plane
-  const uint32_t Lp = L >> 1, NP = Lp + 4u;                 // own planes, staged planes
-  const uint32_t wpp = (L * L) >> 5, nwr = G.N >> 5;        // packed words per plane, per walker
-  const uint32_t nb = 4u * wpp, npost = nb + 2u;            // boundary words, words per post
+  const uint32_t lgG = lgL - 3u, gmask = (1u << lgG) - 1u;  // nibble dwords per row
+  const uint32_t lgPl = DIM == 3 ? lgL + lgG : lgG;          // nibble dwords per plane
+  constexpr uint32_t P = NPARTS, LGP = NPARTS == 8 ? 3u : NPARTS == 4 ? 2u : 1u;
+  static_assert(NPARTS == 2 || NPARTS == 4 || NPARTS == 8, "split plan: 2, 4 or 8 parts");
+  const uint32_t Lp = L >> LGP, NP = Lp + 4u;                 // own planes, staged planes
+  const uint32_t wpp = G.plane >> 5, nwr = G.N >> 5;         // packed words per plane, per walker
+  const uint32_t nb = 4u * wpp, npost = nb + 2u;             // boundary words, words per post
+  const uint32_t nread = nb + 2u * (P - 1u);                 // words a part reads per sweep
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t w = blockIdx.x >> 1, p = blockIdx.x & 1u, z0 = p * Lp;
+  const uint32_t w = blockIdx.x >> LGP, p = blockIdx.x & (P - 1u), z0 = p * Lp;
+  const uint32_t pup = (p + 1u) & (P - 1u), pdn = (p + P - 1u) & (P - 1u);
   const uint32_t pdw = NP << lgPl;
   uint32_t *sp = reinterpret_cast<uint32_t *>(smem);
-  uint32_t *bx = sp + pdw, *by = bx + pdw, *bz = by + pdw;
-  uint32_t *thr = bz + pdw;
+  uint32_t *bx = sp + pdw, *by = bx + pdw, *bz = by + pdw;  // 3D only
+  uint32_t *thr = DIM == 3 ? bz + pdw : bx;
   for (uint32_t q = tid; q < R * kClasses; q += nt) thr[q] = a.st.flip_thr[q];
 
   uint32_t slot = a.st.slot_of[w];
@@ -1344,12 +1353,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
   int32_t Et = a.st.E[w], Mt = a.st.M[w]; // walker totals after the last sweep
   if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
   {
-    // planes z0 - 2 .. z0 + L/2 + 1, periodic in z
+    // planes z0 - 2 .. z0 + Lp + 1, periodic
     const uint32_t f = ((z0 + L - 2u) & lmask) * wpp, cnt = NP * wpp, m = nwr - 1u;
     unpack_tile_n(sp, a.spins + (size_t)w * nwr, f, cnt, m, tid, nt);
-    unpack_tile_n(bx, a.st.bonds, f, cnt, m, tid, nt);
-    unpack_tile_n(by, a.st.bonds + nwr, f, cnt, m, tid, nt);
-    unpack_tile_n(bz, a.st.bonds + 2u * nwr, f, cnt, m, tid, nt);
+    if constexpr (DIM == 3) {
+      unpack_tile_n(bx, a.st.bonds, f, cnt, m, tid, nt);
+      unpack_tile_n(by, a.st.bonds + nwr, f, cnt, m, tid, nt);
+      unpack_tile_n(bz, a.st.bonds + 2u * nwr, f, cnt, m, tid, nt);
+    }
   }
   __syncthreads();
 
@@ -1359,38 +1370,46 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
     const uint32_t s = a.sch.s0 + j;
     TallyN t = {0u, 0u, 0u};
     for (uint32_t c = 0; c < 2u; ++c) {
-      // own planes 2 .. L/2 + 1, V groups per item
+      // own planes 2 .. Lp + 1, V groups per item
       for (uint32_t q = tid; q < (Lp << a.lg_ipp); q += nt) {
         const uint32_t lp = 2u + (q >> a.lg_ipp);
         const uint32_t g0 = (q & smask) * V;
-        const uint32_t y = (q >> a.lg_spr) & lmask;
+        const uint32_t y = DIM == 3 ? (q >> a.lg_spr) & lmask : 0u;
         const uint32_t z = (z0 + lp + L - 2u) & lmask; // global plane
         const uint32_t off = (c + lp + y) & 1u;         // z0 is even
-        const uint32_t ctr0 = (((z << lgL) + y) << lgG) + g0;
+        const uint32_t ctr0 = DIM == 3 ? (((z << lgL) + y) << lgG) + g0 : (z << lgG) + g0;
         Words r[V];
 #pragma unroll
         for (int v = 0; v < V; ++v)
           r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
-        span3d_n<V>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
-                    (y + 1u) & lmask, g0, gmask, off, r, s_thr, t);
+        if constexpr (DIM == 3)
+          span3d_n<V>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
+                      (y + 1u) & lmask, g0, gmask, off, r, s_thr, t);
+        else
+          span2d_n<V>(sp + (lp << lgPl), sp + ((lp - 1u) << lgPl), sp + ((lp + 1u) << lgPl), g0,
+                      gmask, off, r, s_thr, t);
       }
       if (c == 0u) {
-        // the inner halo planes (local 1 and L/2 + 2), one group per item on
+        // the inner halo planes (local 1 and Lp + 2), one group per item on
         // the first waves: one such wave per SIMD keeps the pass balanced.
-        // Their flips are the sibling's to count.
-        const uint32_t gpp = L << lgG; // groups per plane
+        // Their flips are their owners' to count.
+        const uint32_t gpp = 1u << lgPl; // groups per plane
         for (uint32_t q = tid; q < 2u * gpp; q += nt) {
           const uint32_t lp = q < gpp ? 1u : Lp + 2u;
           const uint32_t g0 = q & gmask;
-          const uint32_t y = (q >> lgG) & lmask;
+          const uint32_t y = DIM == 3 ? (q >> lgG) & lmask : 0u;
           const uint32_t z = (z0 + lp + L - 2u) & lmask;
           const uint32_t off = (lp + y) & 1u;
-          const uint32_t ctr = (((z << lgL) + y) << lgG) + g0;
+          const uint32_t ctr = DIM == 3 ? (((z << lgL) + y) << lgG) + g0 : (z << lgG) + g0;
           Words r[1];
           r[0] = philox(ctr, s, slot, kPurposeFlip, a.key.k0, a.key.k1);
           TallyN tl = {0u, 0u, 0u};
-          span3d_n<1>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
-                      (y + 1u) & lmask, g0, gmask, off, r, s_thr, tl);
+          if constexpr (DIM == 3)
+            span3d_n<1>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
+                        (y + 1u) & lmask, g0, gmask, off, r, s_thr, tl);
+          else
+            span2d_n<1>(sp + (lp << lgPl), sp + ((lp - 1u) << lgPl), sp + ((lp + 1u) << lgPl), g0,
+                        gmask, off, r, s_thr, tl);
         }
       } else {
         // this wave's energy and magnetisation changes over the sweep, ready
@@ -1414,11 +1433,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
       }
       const uint64_t hi = 0xFFFFFFFF00000000ull;
       const uint64_t tag = (uint64_t)(s + 1u) << 32, etag = (uint64_t)(e + 1u) << 32;
-      const size_t gen = (size_t)(s & 1u) * R + w;
-      uint64_t *mine = a.st.halo + (gen * 2u + p) * npost;
-      const uint64_t *sib = a.st.halo + (gen * 2u + (p ^ 1u)) * npost;
-      uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * 2u * R;
-      // post: words [0, 2 wpp) = own planes 2, 3; [2 wpp, 4 wpp) = planes L/2, L/2 + 1
+      // the posts of this sweep's generation for walker w, one per part
+      uint64_t *posts = a.st.halo + ((size_t)(s & 1u) * R + w) * P * npost;
+      uint64_t *mine = posts + (size_t)p * npost;
+      uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * P * R;
+      // post: words [0, 2 wpp) = own planes 2, 3; [2 wpp, 4 wpp) = planes Lp, Lp + 1
       for (uint32_t q = tid; q < nb; q += 64u) {
         const bool lo = q < 2u * wpp;
         const uint4 x = reinterpret_cast<const uint4 *>(sp + ((lo ? 2u : Lp) << lgPl))[lo ? q : q - 2u * wpp];
@@ -1434,7 +1453,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
       }
       if (tid == 0u) {
         if (do_ex)
-          __hip_atomic_store(&mb[2u * slot + p], etag | (uint32_t)Es, __ATOMIC_RELAXED,
+          __hip_atomic_store(&mb[P * slot + p], etag | (uint32_t)Es, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(mine + nb, tag | (uint32_t)Es, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(mine + nb + 1u, tag | (uint32_t)Ms, __ATOMIC_RELAXED,
@@ -1452,25 +1471,36 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
         sat_lo = a.st.swap_sat[2u * lo];
         sat_hi = a.st.swap_sat[2u * lo + 1u];
       }
-      // wait for the sibling's post and, at an exchange step, the partner
-      // slot's two shares.  Every round issues all of a lane's loads before
-      // testing any (one memory round trip per round); a word is consumed when
-      // its tag arrives and cannot change again before this part has posted
-      // its next sweep, so reloading a consumed word is harmless.
+      // Word q of what this part reads: the lower boundary planes of the part
+      // above (q < 2 wpp, its post words q), the upper ones of the part below
+      // (2 wpp <= q < 4 wpp), then the E_int and M shares of the other parts.
+      uint32_t src[kSplitWordsPerLane]; // word offsets from posts
       uint32_t pend = 0u;
 #pragma unroll
-      for (uint32_t k = 0; k < kSplitWordsPerLane; ++k)
-        if (tid + 64u * k < npost) pend |= 1u << k;
-      uint32_t ppend = (partner != 0xFFFFFFFFu && tid < 2u) ? 1u : 0u;
-      const uint64_t *pmb = &mb[2u * (partner != 0xFFFFFFFFu ? partner : slot) + (tid & 1u)];
+      for (uint32_t k = 0; k < kSplitWordsPerLane; ++k) {
+        const uint32_t q = min(tid + 64u * k, nread - 1u);
+        if (tid + 64u * k < nread) pend |= 1u << k;
+        if (q < 2u * wpp) src[k] = pup * npost + q;
+        else if (q < nb) src[k] = pdn * npost + q;
+        else {
+          const uint32_t i = q - nb;
+          src[k] = ((p + 1u + (i >> 1)) & (P - 1u)) * npost + nb + (i & 1u);
+        }
+      }
+      // wait for those and, at an exchange step, the partner slot's shares.
+      // Every round issues all of a lane's loads before testing any (one memory
+      // round trip per round); a word is consumed when its tag arrives and
+      // cannot change again before this part has posted its next sweep, so
+      // reloading a consumed word is harmless.
+      uint32_t ppend = (partner != 0xFFFFFFFFu && tid < P) ? 1u : 0u;
+      const uint64_t *pmb = &mb[P * (partner != 0xFFFFFFFFu ? partner : slot) + (tid & (P - 1u))];
       int32_t sE = 0, sM = 0, pE = 0;
       uint32_t stop = 0u;
       for (uint32_t n = 0;; ++n) {
         uint64_t v[kSplitWordsPerLane];
 #pragma unroll
         for (uint32_t k = 0; k < kSplitWordsPerLane; ++k)
-          v[k] = __hip_atomic_load(sib + min(tid + 64u * k, npost - 1u), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+          v[k] = __hip_atomic_load(posts + src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint64_t pv = __hip_atomic_load(pmb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const uint32_t ab =
             __hip_atomic_load(&a.st.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1480,16 +1510,16 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
           pend &= ~(1u << k);
           const uint32_t q = tid + 64u * k, x = (uint32_t)v[k];
           if (q < nb) {
-            // the sibling's lowest planes are this part's upper halo, its
-            // highest planes the lower halo
+            // the part above's lowest planes are this part's upper halo, the
+            // part below's highest planes the lower halo
             const bool lo = q < 2u * wpp;
             reinterpret_cast<uint4 *>(sp + (lo ? ((Lp + 2u) << lgPl) : 0u))[lo ? q : q - 2u * wpp] =
                 make_uint4(spread8(x & 0xFFu), spread8(__builtin_amdgcn_ubfe(x, 8u, 8u)),
                            spread8(__builtin_amdgcn_ubfe(x, 16u, 8u)), spread8(x >> 24));
-          } else if (q == nb) {
-            sE = (int32_t)x;
+          } else if (((q - nb) & 1u) == 0u) {
+            sE += (int32_t)x;
           } else {
-            sM = (int32_t)x;
+            sM += (int32_t)x;
           }
         }
         if (ppend && (pv & hi) == etag) {
@@ -1508,7 +1538,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
       }
       sE = wave_sum(sE);
       sM = wave_sum(sM);
-      const int32_t pE0 = __shfl(pE, 0, 64), pE1 = __shfl(pE, 1, 64);
+      // the partner slot's P shares, held by lanes 0 .. P-1: independent reads
+      int32_t Ep = 0;
+#pragma unroll
+      for (uint32_t k = 0; k < P; ++k) Ep += __shfl(pE, (int)k, 64);
       if (tid == 0u) {
         Et = Es + sE;
         Mt = Ms + sM;
@@ -1519,7 +1552,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
             a.st.M_series[(size_t)rec * R + slot] = Mt;
           }
           if (partner != 0xFFFFFFFFu) {
-            const int32_t Ep = pE0 + pE1;
             const int32_t Elo = (slot == lo) ? Et : Ep, Ehi = (slot == lo) ? Ep : Et;
             const int32_t d = (Elo - Ehi) / 4; // E_int differences are multiples of 4
             uint64_t T;
@@ -1894,7 +1926,7 @@ __global__ void k_reset(DevState st, Geometry G, uint32_t halo_words) {
       st.acc[q] = 0;
     }
     if (q < 4u) st.counter[q] = 0;
-    if (q < 8u * R) st.mailbox[q] = 0;
+    if (q < 4u * kMaxParts * R) st.mailbox[q] = 0;
   }
 }
 
@@ -2022,29 +2054,49 @@ hipError_t launch_persist_v(PersistArgs &a, uint32_t R, uint32_t threads, size_t
                                     dim3(threads), args, (unsigned int)lds, stream);
 }
 
-template <int V>
+template <int DIM, int V, int P>
 hipError_t launch_persist_split_v(PersistArgs &a, uint32_t R, uint32_t threads, size_t lds,
                                   hipStream_t stream) {
-  hipError_t err = allow_lds(k_persist_split<V>, lds);
+  hipError_t err = allow_lds(k_persist_split<DIM, V, P>, lds);
   if (err != hipSuccess) return err;
   void *args[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_persist_split<V>),
-                                    dim3(2u * R), dim3(threads), args, (unsigned int)lds, stream);
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(k_persist_split<DIM, V, P>),
+                                    dim3(P * R), dim3(threads), args, (unsigned int)lds, stream);
+}
+
+// 2D split launch for V groups per item and 2, 4 or 8 parts.
+template <int V>
+hipError_t launch_persist_split_2d(PersistArgs &a, uint32_t R, uint32_t parts, uint32_t threads,
+                                   size_t lds, hipStream_t stream) {
+  return parts == 8   ? launch_persist_split_v<2, V, 8>(a, R, threads, lds, stream)
+         : parts == 4 ? launch_persist_split_v<2, V, 4>(a, R, threads, lds, stream)
+                      : launch_persist_split_v<2, V, 2>(a, R, threads, lds, stream);
 }
 
 // Groups per item of the split kernel: one item per thread in a colour-1 pass
-// (a power of two, at most kPersistSpan and the groups of a row).
-uint32_t split_span(const Geometry &g, uint32_t threads) {
-  const uint32_t per = (g.L / 2u) * g.L * g.gpr / std::max<uint32_t>(threads, 1u);
+// (a power of two, at most the groups of a row and kPersistSpan, 2D kNibbleSpan).
+uint32_t split_span(const Geometry &g, uint32_t threads, uint32_t parts) {
+  const uint32_t per = (g.L / parts) * g.rows * g.gpr / std::max<uint32_t>(threads, 1u);
+  const uint32_t cap = std::min<uint32_t>(g.dim == 3 ? kPersistSpan : kNibbleSpan, g.gpr);
   uint32_t V = 1u;
-  while (V * 2u <= per && V * 2u <= std::min<uint32_t>(kPersistSpan, g.gpr)) V *= 2u;
+  while (V * 2u <= per && V * 2u <= cap) V *= 2u;
   return V;
 }
 
-const void *split_fn(uint32_t V) {
-  return V == 4   ? reinterpret_cast<const void *>(k_persist_split<4>)
-         : V == 2 ? reinterpret_cast<const void *>(k_persist_split<2>)
-                  : reinterpret_cast<const void *>(k_persist_split<1>);
+template <int V>
+const void *split_fn_2d(uint32_t parts) {
+  return parts == 8   ? reinterpret_cast<const void *>(k_persist_split<2, V, 8>)
+         : parts == 4 ? reinterpret_cast<const void *>(k_persist_split<2, V, 4>)
+                      : reinterpret_cast<const void *>(k_persist_split<2, V, 2>);
+}
+
+const void *split_fn(uint32_t dim, uint32_t V, uint32_t parts) {
+  if (dim == 3)
+    return V == 4   ? reinterpret_cast<const void *>(k_persist_split<3, 4, 2>)
+           : V == 2 ? reinterpret_cast<const void *>(k_persist_split<3, 2, 2>)
+                    : reinterpret_cast<const void *>(k_persist_split<3, 1, 2>);
+  return V == 8 ? split_fn_2d<8>(parts) : V == 4 ? split_fn_2d<4>(parts)
+       : V == 2 ? split_fn_2d<2>(parts) : split_fn_2d<1>(parts);
 }
 
 template <int DIM, int V>
@@ -2069,11 +2121,12 @@ size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo) {
 size_t fused_lds_bytes(const Geometry &g) { return fused_layout(g.R, g.N, g.dim, 0u).total; }
 
 size_t persist_lds_bytes(const Geometry &g, uint32_t parts) {
-  if (parts == 2u) {
-    // L/2 + 4 staged planes of spins and three bond arrays, every slot's
-    // thresholds; at least 96 KB, so that one part holds a compute unit alone
-    // (both parts of a walker must advance at the same rate)
-    const size_t need = (size_t)(g.L / 2u + 4u) * g.plane / 2u * 4u + (size_t)g.R * kClasses * 4u;
+  if (parts >= 2u) {
+    // L/parts + 4 staged planes of spins (and, 3D, three bond arrays), every
+    // slot's thresholds; at least 96 KB, so that one part holds a compute
+    // unit alone (all parts of a walker must advance at the same rate)
+    const size_t need = (size_t)(g.L / parts + 4u) * g.plane / 2u * (g.dim == 3 ? 4u : 1u) +
+                        (size_t)g.R * kClasses * 4u;
     return std::max<size_t>(need, 96u * 1024u);
   }
   return (size_t)g.N / 2u * (g.dim == 3 ? 4u : 1u) + (size_t)g.R * kClasses * 4u; // four bits per site
@@ -2081,7 +2134,7 @@ size_t persist_lds_bytes(const Geometry &g, uint32_t parts) {
 
 uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads, uint32_t parts) {
   const uint32_t V = std::min<uint32_t>(kPersistSpan, g.gpr);
-  const void *fn = parts == 2u ? split_fn(split_span(g, threads))
+  const void *fn = parts >= 2u ? split_fn(g.dim, split_span(g, threads, parts), parts)
                  : g.dim == 3 ? (V == 4   ? reinterpret_cast<const void *>(k_persist<3, 4>)
                                  : V == 2 ? reinterpret_cast<const void *>(k_persist<3, 2>)
                                           : reinterpret_cast<const void *>(k_persist<3, 1>))
@@ -2281,16 +2334,24 @@ hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, 
   a.lg_rows = ilog2(g.rows);
   a.z2 = g.dim == 3 ? 12 : 8;
   a.spin_limit = spin_limit;
-  if (parts == 2u) {
-    if (g.dim != 3 || g.L < 16u || g.L > 32u) return hipErrorInvalidValue;
-    const uint32_t V = split_span(g, threads);
+  if (parts >= 2u) {
+    if (parts > split_max_parts(g) || (parts & (parts - 1u)) || g.L / parts < 8u)
+      return hipErrorInvalidValue;
+    const uint32_t V = split_span(g, threads, parts);
     a.lg_spr = ilog2(g.gpr / V);
-    a.lg_ipp = a.lg_L + a.lg_spr;
+    a.lg_ipp = g.dim == 3 ? a.lg_L + a.lg_spr : a.lg_spr;
     a.lg_items = 0u;
-    const size_t lds = persist_lds_bytes(g, 2u);
-    return V == 4   ? launch_persist_split_v<4>(a, g.R, threads, lds, stream)
-           : V == 2 ? launch_persist_split_v<2>(a, g.R, threads, lds, stream)
-                    : launch_persist_split_v<1>(a, g.R, threads, lds, stream);
+    const size_t lds = persist_lds_bytes(g, parts);
+    if (g.dim == 3) {
+      if (parts != 2u) return hipErrorInvalidValue;
+      return V == 4   ? launch_persist_split_v<3, 4, 2>(a, g.R, threads, lds, stream)
+             : V == 2 ? launch_persist_split_v<3, 2, 2>(a, g.R, threads, lds, stream)
+                      : launch_persist_split_v<3, 1, 2>(a, g.R, threads, lds, stream);
+    }
+    return V == 8   ? launch_persist_split_2d<8>(a, g.R, parts, threads, lds, stream)
+           : V == 4 ? launch_persist_split_2d<4>(a, g.R, parts, threads, lds, stream)
+           : V == 2 ? launch_persist_split_2d<2>(a, g.R, parts, threads, lds, stream)
+                    : launch_persist_split_2d<1>(a, g.R, parts, threads, lds, stream);
   }
   const uint32_t V = std::min<uint32_t>(kPersistSpan, g.gpr);
   a.lg_spr = ilog2(g.gpr / V);

@@ -110,7 +110,7 @@ def test_auto_plans_of_the_bench_workloads(pt):
     from paper_2512_03825_amd.workloads import WORKLOADS
     want = {
         "ising2d_L16_R8": dict(mode=WAVE, block_threads=256),
-        "ising2d_L1024_R64": dict(mode=TILED, tile_planes=256, sweeps_per_launch=5, block_threads=1024),
+        "ising2d_L1024_R64": dict(mode=PERSISTENT, tile_planes=256, block_threads=1024),
         "ea3d_L32_R128": dict(mode=PERSISTENT, tile_planes=16, block_threads=512),
         "paper_shape_L256_R1500": dict(mode=TILED, tile_planes=256, sweeps_per_launch=8,
                                        block_threads=256),

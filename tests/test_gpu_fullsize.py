@@ -39,6 +39,7 @@ def make_sim(pt, w, max_records):
 
 @pytest.mark.parametrize("name, plan", [
     ("ising2d_L1024_R64", None),
+    ("ising2d_L1024_R64", dict(mode=2, tile_planes=256, sweeps_per_launch=5, block_threads=1024)),
     ("ea3d_L32_R128", None),                                   # two workgroups per walker
     ("ea3d_L32_R128", dict(mode=3, tile_planes=32, block_threads=1024)),  # one per walker
 ])

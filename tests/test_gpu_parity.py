@@ -162,14 +162,40 @@ def test_split_persistent_plan(pt, oracle_mod, L, R, every, rec, threads):
              coupling_seed=6, split=True, tag="persist-2-split")
 
 
+@pytest.mark.parametrize("L, R, every, rec, threads, parts", [
+    (64, 4, 1, 1, 256, 2),
+    (64, 3, 3, 2, 256, 4),      # odd R
+    (64, 5, 1, 1, 512, 8),      # eight rows per part
+    (128, 4, 2, 1, 512, 4),
+    (256, 3, 0, 1, 1024, 8),    # no exchange steps: boundary posts only
+    (1024, 2, 1, 1, 1024, 4),   # the 1024^2 workload's decomposition
+])
+def test_split_persistent_plan_2d(pt, oracle_mod, L, R, every, rec, threads, parts):
+    """2D walkers split over P co-resident workgroups of L/P rows each."""
+    beta = beta_geometric(0.2, 0.6, R)
+    plan = dict(mode=PERSISTENT, tile_planes=L // parts, block_threads=threads)
+    sweeps = 24 if L < 1024 else 12
+    sim, _ = run_case(pt, oracle_mod, 0, L, R, beta, 29, sweeps, every, record_every=rec,
+                      plan=plan, tag="persist-2d-%d" % parts)
+    assert sim.plan()["tile_planes"] == L // parts
+    run_case(pt, oracle_mod, 0, L, R, beta, 29, sweeps // 2, every, record_every=rec, plan=plan,
+             split=True, tag="persist-2d-%d-split" % parts)
+
+
 def test_split_persistent_plan_rejects_other_shapes(pt):
-    for model, L in ((0, 32), (1, 8), (1, 64)):  # 2D; 3D lattices too small or too large to split
+    for model, L in ((0, 32), (1, 8), (1, 64)):  # lattices too small or too large to split
         cfg = pt.Config(model, L, 4, beta_geometric(0.5, 3.0, 4), seed=1)
         sim = pt.Simulation(cfg)
         with pytest.raises(pt.PTError):
             sim.set_plan(PERSISTENT, tile_planes=L // 2, block_threads=256)
         with pytest.raises(pt.PTError):
             sim.set_plan(PERSISTENT, tile_planes=3, block_threads=256)
+        sim.close()
+    # 2D: parts of fewer than 8 rows, a non-power-of-two part count, a lattice too large
+    for L, tp in ((64, 4), (64, 24), (2048, 256)):
+        sim = pt.Simulation(pt.Config(0, L, 2, beta_geometric(0.2, 0.6, 2), seed=1))
+        with pytest.raises(pt.PTError):
+            sim.set_plan(PERSISTENT, tile_planes=tp, block_threads=256)
         sim.close()
 
 

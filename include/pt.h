@@ -95,11 +95,13 @@ typedef struct {
  *               epilogue of the last workgroup.
  *   PERSISTENT  one co-resident workgroup per walker keeps its lattice in LDS
  *               for a whole pt_run call; exchange steps are decided pairwise
- *               between neighbouring slots without a global barrier.  With
- *               tile_planes = L/2 (3D, 16 <= L <= 32) each walker runs as two
- *               co-resident workgroups of L/2 z-planes that trade boundary
- *               planes and energy shares once per sweep (2R workgroups, one
- *               per compute unit); tile_planes = 0 or L means one per walker.
+ *               between neighbouring slots without a global barrier (h = 0 in
+ *               2D).  With tile_planes = L/P each walker runs as P co-resident
+ *               workgroups of L/P planes (3D z-planes, 2D rows) that trade
+ *               boundary planes and energy shares once per sweep (P R
+ *               workgroups, one per compute unit): 3D 16 <= L <= 32 with P = 2,
+ *               2D 64 <= L <= 1024 with P = 2, 4 or 8 and at least 8 rows per
+ *               part; tile_planes = 0 or L means one workgroup per walker.
  *   LANES       the paper's GPU decomposition (Sec. 3: one replica per thread):
  *               each lane holds one walker's whole lattice in registers and
  *               updates it site after site; one workgroup runs every walker and
@@ -121,7 +123,7 @@ typedef enum {
 typedef struct {
   uint32_t mode;              /* pt_plan_mode */
   uint32_t tile_planes;       /* TILED: rows (2D) or z-planes (3D) per workgroup tile;
-                                 PERSISTENT: L or, 3D, L/2 (two workgroups per walker) */
+                                 PERSISTENT: L, or L/P for P workgroups per walker */
   uint32_t sweeps_per_launch; /* TILED: 1 .. PT_MAX_SWEEPS_PER_LAUNCH */
   uint32_t block_threads;     /* 64 .. 1024, multiple of 64 */
 } pt_plan;

@@ -32,8 +32,8 @@
 //                  the kernel.
 //   k_persist      one co-resident workgroup per walker for a whole run;
 //                  exchanges decided pairwise through mailboxes.
-//   k_persist_split  3D: two co-resident workgroups per walker (half the
-//                  z-planes each, two halo planes per side), trading boundary
+//   k_persist_split  P co-resident workgroups per walker (L/P z-planes in 3D,
+//                  rows in 2D, two halo planes per side), trading boundary
 //                  planes and energy shares once per sweep as tagged words.
 //   k_wave         small 2D lattices: each walker in the registers of the
 //                  lanes of one wavefront (a nibble dword per lane), neighbours

@@ -162,7 +162,7 @@ Layout layout(const pt_config *cfg, const Derived &d) {
   l.Es = take((size_t)cfg->max_records * R * 4);
   l.Ms = take((size_t)cfg->max_records * R * 4);
   l.counter = take(16);
-  l.mailbox = take(4 * kMaxParts * R * 8);
+  l.mailbox = take(8 * kMaxParts * R * 8);
   l.halo = take(split_halo_words(g) * 8);
   l.field = take(R * kFieldDigits * 8);
   l.fsign = take(R * 4);
@@ -263,8 +263,6 @@ pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
     return PT_OK;
   }
   if (p.mode == PT_PLAN_PERSISTENT) {
-    if (c->cfg.h != 0.0 && g.dim == 2)
-      return fail(PT_EINVAL, "the persistent plan exchanges energies only; it needs h = 0");
     const uint32_t parts = persist_parts(g, p);
     if (parts > 1u && (g.L % p.tile_planes || (parts & (parts - 1u)) ||
                        parts > split_max_parts(g) || p.tile_planes < 8u))
@@ -339,7 +337,7 @@ pt_plan auto_plan(const pt_ctx *c) {
   // rows, with P R filling the device (one workgroup per compute unit): every
   // part stays in LDS for a whole run and trades two boundary rows per side
   // once per sweep (no launch, restaging or recomputed halo between sweeps).
-  if (g.dim == 2 && c->cfg.h == 0.0 && split_max_parts(g)) {
+  if (g.dim == 2 && split_max_parts(g)) {
     for (uint32_t P = 2u; P <= split_max_parts(g); P *= 2u) {
       if (persist_lds_bytes(g, P) > max_lds_bytes()) continue;
       pt_plan q{};
@@ -356,7 +354,7 @@ pt_plan auto_plan(const pt_ctx *c) {
   }
   // Many walkers whose lattices fit a workgroup's LDS: one co-resident workgroup
   // per walker for a whole run, exchanges decided pairwise (no launch per sweep).
-  if (g.R >= 128 && !(g.dim == 2 && c->cfg.h != 0.0)) {
+  if (g.R >= 128) {
     pt_plan q{};
     q.mode = PT_PLAN_PERSISTENT;
     q.block_threads = 1024;

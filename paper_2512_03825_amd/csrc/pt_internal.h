@@ -40,8 +40,8 @@ struct DevState {
   int32_t *E_series;   // [max_records][R] slot order
   int32_t *M_series;
   uint32_t *counter;   // [4] workgroup-arrival counter of the tiled sweep; [1] persistent-kernel abort flag
-  uint64_t *mailbox;   // [4][R][P] persistent kernels (P <= kMaxParts workgroups per walker):
-                       // (step + 1) << 32 | E_int (share) posted by the holder of a slot
+  uint64_t *mailbox;   // [4][R][P][2] persistent kernels (P <= kMaxParts workgroups per walker):
+                       // (step + 1) << 32 | E_int share, then M share, posted by the holder of a slot
   uint64_t *halo;      // [2][R][P][split_post_words(g)] split persistent plan: per sweep and part,
                        // (sweep + 1) << 32 | word: boundary planes (bit-packed), then E_int and M shares
   uint8_t *staging;    // +-1 bytes uploaded by the host (only if the config uploads)

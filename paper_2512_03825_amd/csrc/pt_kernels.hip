@@ -60,7 +60,6 @@ constexpr uint32_t kPersistSpan = 4;
 // boundary planes (4 x 32 packed words for 3D L <= 32 and 2D L <= 1024) and
 // 2 (P - 1) shares, at most 142 words over 64 lanes.
 constexpr uint32_t kSplitWordsPerLane = 3;
-static_assert(kMaxSweepsPerLaunch * 4u >= 4u * kMaxParts, "k_reset clears the mailboxes in its acc3 loop");
 
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
@@ -1138,9 +1137,10 @@ struct PersistArgs {
 
 // Persistent replica workgroups: walker w = blockIdx.x keeps its lattice in
 // LDS for the whole launch.  After each sweep it folds its own E and M, writes
-// its slot's record, and at an exchange step posts (step, E) in the mailbox of
-// its slot, waits for the partner slot's post, and takes the same decision as
-// the partner (same draw, same table entry) -- there is no global barrier.
+// its slot's record, and at an exchange step posts (step, E) and (step, M) in
+// the mailbox of its slot, waits for the partner slot's posts, and takes the
+// same decision as the partner (same draws, same table entries, the field
+// factor from the same dM) -- there is no global barrier.
 // A partner is at most a few steps apart, so four mailbox generations suffice.
 template <int DIM, int V>
 __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
@@ -1220,10 +1220,14 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
       // energy together and the partner reads nothing else of ours, so relaxed
       // agent-scope atomics suffice: no L2 write-back on the post and no L2
       // invalidate per poll.
-      uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * R;
+      uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * 2u * R; // [slot][E, M]
       const uint64_t tag = (uint64_t)(e + 1u) << 32;
-      if (do_ex)
-        __hip_atomic_store(&mb[slot], tag | (uint32_t)E, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (do_ex) {
+        __hip_atomic_store(&mb[2u * slot], tag | (uint32_t)E, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if constexpr (DIM == 2) // M for the field factor (2D only)
+          __hip_atomic_store(&mb[2u * slot + 1u], tag | (uint32_t)M, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      }
       if (do_rec) {
         a.st.E_series[(size_t)rec * R + slot] = E;
         a.st.M_series[(size_t)rec * R + slot] = M;
@@ -1242,10 +1246,15 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
           const int32_t D = (int32_t)a.st.swap_D[lo];
           const uint32_t toff = a.st.swap_off[lo];
           const uint64_t sat_lo = a.st.swap_sat[2u * lo], sat_hi = a.st.swap_sat[2u * lo + 1u];
-          uint64_t v = 0;
+          const int32_t sg = DIM == 2 ? a.st.field_sign[lo] : 0;
+          uint64_t v = 0, vm = 0;
           for (uint32_t n = 0;; ++n) {
-            // both loads in flight together: one memory round trip per poll
-            v = __hip_atomic_load(&mb[partner], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            // all loads in flight together: one memory round trip per poll
+            v = __hip_atomic_load(&mb[2u * partner], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if constexpr (DIM == 2)
+              vm = __hip_atomic_load(&mb[2u * partner + 1u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+              vm = tag;
             const uint32_t ab =
                 __hip_atomic_load(&a.st.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             // the bound and the abort flag first: a limit of 0 gives up at once
@@ -1254,12 +1263,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
               stop = 1u;
               break;
             }
-            if ((v & 0xFFFFFFFF00000000ull) == tag) break;
+            if ((v & 0xFFFFFFFF00000000ull) == tag && (vm & 0xFFFFFFFF00000000ull) == tag) break;
             __builtin_amdgcn_s_sleep(1);
           }
           if (!stop) {
-            const int32_t Ep = (int32_t)(uint32_t)v;
+            const int32_t Ep = (int32_t)(uint32_t)v, Mp = (int32_t)(uint32_t)vm;
             const int32_t Elo = (slot == lo) ? E : Ep, Ehi = (slot == lo) ? Ep : E;
+            const int32_t Mlo = (slot == lo) ? M : Mp, Mhi = (slot == lo) ? Mp : M;
             const int32_t d = (Elo - Ehi) / 4; // E_int differences are multiples of 4
             uint64_t T;
             if (d < -D) T = sat_lo;
@@ -1268,7 +1278,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
               const uint32_t idx = toff + (uint32_t)(d + D);
               T = idx < a.st.swap_n ? a.st.swap_tab[idx] : 0u; // a valid table always passes
             }
-            const bool accept = (uint64_t)r < T;
+            bool accept = (uint64_t)r < T;
+            if constexpr (DIM == 2)
+              accept = accept && field_factor(a.st, sg, lo, e, Mlo - Mhi, a.key.k0, a.key.k1);
             if (slot == lo) {
               atomicAdd(&a.st.att[lo], 1u);
               if (accept) atomicAdd(&a.st.acc[lo], 1u);
@@ -1313,7 +1325,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
 // exchange of boundary planes per sweep suffices.  At the end of every sweep a
 // part posts its two lowest and two highest own planes (bit-packed) and its
 // shares of E_int and M, and at an exchange step its E_int share in the slot's
-// mailbox; each 64-bit word carries its tag (sweep or step + 1) beside 32 bits
+// mailbox beside its M share; each 64-bit word carries its tag (sweep or step + 1) beside 32 bits
 // of data, so the reader takes data and tag in one relaxed load and needs no
 // fence.  A part reads the lower planes of the part above, the upper planes of
 // the part below and the shares of every other part; the parts of both
@@ -1436,7 +1448,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
       // the posts of this sweep's generation for walker w, one per part
       uint64_t *posts = a.st.halo + ((size_t)(s & 1u) * R + w) * P * npost;
       uint64_t *mine = posts + (size_t)p * npost;
-      uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * P * R;
+      uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * 2u * P * R; // [slot][part][E, M]
       // post: words [0, 2 wpp) = own planes 2, 3; [2 wpp, 4 wpp) = planes Lp, Lp + 1
       for (uint32_t q = tid; q < nb; q += 64u) {
         const bool lo = q < 2u * wpp;
@@ -1452,16 +1464,20 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
         else if ((slot & 1u) != par && slot >= 1u) partner = slot - 1u;
       }
       if (tid == 0u) {
-        if (do_ex)
-          __hip_atomic_store(&mb[P * slot + p], etag | (uint32_t)Es, __ATOMIC_RELAXED,
+        if (do_ex) {
+          __hip_atomic_store(&mb[2u * (P * slot + p)], etag | (uint32_t)Es, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
+          if constexpr (DIM == 2) // M for the field factor (2D only)
+            __hip_atomic_store(&mb[2u * (P * slot + p) + 1u], etag | (uint32_t)Ms, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
         __hip_atomic_store(mine + nb, tag | (uint32_t)Es, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(mine + nb + 1u, tag | (uint32_t)Ms, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
       }
       // everything of the swap test that does not need the energies, before waiting
       uint32_t lo = 0u, rr = 0u, toff = 0u;
-      int32_t D = 0;
+      int32_t D = 0, sg = 0;
       uint64_t sat_lo = 0u, sat_hi = 0u;
       if (tid == 0u && partner != 0xFFFFFFFFu) {
         lo = min(slot, partner);
@@ -1470,6 +1486,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
         toff = a.st.swap_off[lo];
         sat_lo = a.st.swap_sat[2u * lo];
         sat_hi = a.st.swap_sat[2u * lo + 1u];
+        if constexpr (DIM == 2) sg = a.st.field_sign[lo];
       }
       // Word q of what this part reads: the lower boundary planes of the part
       // above (q < 2 wpp, its post words q), the upper ones of the part below
@@ -1487,13 +1504,17 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
           src[k] = ((p + 1u + (i >> 1)) & (P - 1u)) * npost + nb + (i & 1u);
         }
       }
-      // wait for those and, at an exchange step, the partner slot's shares.
+      // wait for those and, at an exchange step, the partner slot's E and M shares.
       // Every round issues all of a lane's loads before testing any (one memory
       // round trip per round); a word is consumed when its tag arrives and
       // cannot change again before this part has posted its next sweep, so
       // reloading a consumed word is harmless.
-      uint32_t ppend = (partner != 0xFFFFFFFFu && tid < P) ? 1u : 0u;
-      const uint64_t *pmb = &mb[P * (partner != 0xFFFFFFFFu ? partner : slot) + (tid & (P - 1u))];
+      // lane k < 2P reads word k of the partner slot's posts (E and M shares by
+      // part); in 3D, without a field, lane k < P reads part k's E share only
+      constexpr uint32_t NW = DIM == 2 ? 2u * P : P;
+      uint32_t ppend = (partner != 0xFFFFFFFFu && tid < NW) ? 1u : 0u;
+      const uint32_t pw = DIM == 2 ? (tid & (2u * P - 1u)) : 2u * (tid & (P - 1u));
+      const uint64_t *pmb = &mb[2u * P * (partner != 0xFFFFFFFFu ? partner : slot) + pw];
       int32_t sE = 0, sM = 0, pE = 0;
       uint32_t stop = 0u;
       for (uint32_t n = 0;; ++n) {
@@ -1538,10 +1559,18 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
       }
       sE = wave_sum(sE);
       sM = wave_sum(sM);
-      // the partner slot's P shares, held by lanes 0 .. P-1: independent reads
-      int32_t Ep = 0;
+      // the partner slot's P shares of E (even lanes 0 .. 2P-2) and of M (odd
+      // lanes): independent reads
+      int32_t Ep = 0, Mp = 0;
 #pragma unroll
-      for (uint32_t k = 0; k < P; ++k) Ep += __shfl(pE, (int)k, 64);
+      for (uint32_t k = 0; k < P; ++k) {
+        if constexpr (DIM == 2) {
+          Ep += __shfl(pE, (int)(2u * k), 64);
+          Mp += __shfl(pE, (int)(2u * k + 1u), 64);
+        } else {
+          Ep += __shfl(pE, (int)k, 64);
+        }
+      }
       if (tid == 0u) {
         Et = Es + sE;
         Mt = Ms + sM;
@@ -1553,6 +1582,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
           }
           if (partner != 0xFFFFFFFFu) {
             const int32_t Elo = (slot == lo) ? Et : Ep, Ehi = (slot == lo) ? Ep : Et;
+            const int32_t Mlo = (slot == lo) ? Mt : Mp, Mhi = (slot == lo) ? Mp : Mt;
             const int32_t d = (Elo - Ehi) / 4; // E_int differences are multiples of 4
             uint64_t T;
             if (d < -D) T = sat_lo;
@@ -1561,7 +1591,9 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
               const uint32_t idx = toff + (uint32_t)(d + D);
               T = idx < a.st.swap_n ? a.st.swap_tab[idx] : 0u; // a valid table always passes
             }
-            const bool accept = (uint64_t)rr < T;
+            bool accept = (uint64_t)rr < T;
+            if constexpr (DIM == 2)
+              accept = accept && field_factor(a.st, sg, lo, e, Mlo - Mhi, a.key.k0, a.key.k1);
             if (slot == lo && p == 0u) {
               atomicAdd(&a.st.att[lo], 1u);
               if (accept) atomicAdd(&a.st.acc[lo], 1u);
@@ -1926,8 +1958,10 @@ __global__ void k_reset(DevState st, Geometry G, uint32_t halo_words) {
       st.acc[q] = 0;
     }
     if (q < 4u) st.counter[q] = 0;
-    if (q < 4u * kMaxParts * R) st.mailbox[q] = 0;
   }
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < 8u * kMaxParts * R;
+       q += gridDim.x * blockDim.x)
+    st.mailbox[q] = 0;
 }
 
 __device__ __forceinline__ uint32_t bit_at(const uint32_t *words, uint32_t i) {

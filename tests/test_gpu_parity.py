@@ -182,6 +182,40 @@ def test_split_persistent_plan_2d(pt, oracle_mod, L, R, every, rec, threads, par
              split=True, tag="persist-2d-%d-split" % parts)
 
 
+@pytest.mark.parametrize("L, R, every, h, parts, threads, split", [
+    (32, 6, 1, 0.1, 1, 256, False),      # one workgroup per walker
+    (64, 5, 3, -0.05, 1, 512, True),
+    (64, 4, 1, 0.1, 2, 256, False),      # rows split over P workgroups
+    (128, 5, 2, -0.08, 4, 512, True),
+    (256, 3, 1, 0.05, 8, 1024, False),
+])
+def test_persistent_plans_with_field(pt, oracle_mod, L, R, every, h, parts, threads, split):
+    """2D with h != 0: the persistent plans' pairwise exchange decisions include
+    the field factor (both walkers' magnetisations through the mailboxes).  The
+    ladder is narrow enough that swaps are accepted in every case."""
+    beta = beta_linear(0.40, 0.40 + 2.0 / L, R)
+    sweeps = 24
+    tag = "persist field L%d R%d P%d h%.2f" % (L, R, parts, h)
+    say("case", tag, "every", every, "split", split)
+    cfg = pt.Config(0, L, R, beta, h=h, seed=31, stream_id=2, record_every=1, max_records=sweeps)
+    sim = pt.Simulation(cfg)
+    sim.set_plan(PERSISTENT, tile_planes=L // parts, block_threads=threads)
+    assert sim.plan()["mode"] == PERSISTENT and sim.plan()["tile_planes"] == L // parts
+    orc = oracle_mod.Oracle(0, L, R, beta, h=h, seed=31, stream_id=2, record_every=1,
+                            max_records=sweeps)
+    if split:
+        for _ in range(sweeps // every):
+            sim.sweep(every)
+            sim.exchange()
+            orc.sweep(every)
+            orc.exchange()
+    else:
+        sim.run(sweeps, every)
+        orc.run(sweeps, every)
+    obs = compare(sim, orc, tag)
+    assert obs["swap_acc"].sum() > 0
+
+
 def test_split_persistent_plan_rejects_other_shapes(pt):
     for model, L in ((0, 32), (1, 8), (1, 64)):  # lattices too small or too large to split
         cfg = pt.Config(model, L, 4, beta_geometric(0.5, 3.0, 4), seed=1)

@@ -95,8 +95,8 @@ typedef struct {
  *               epilogue of the last workgroup.
  *   PERSISTENT  one co-resident workgroup per walker keeps its lattice in LDS
  *               for a whole pt_run call; exchange steps are decided pairwise
- *               between neighbouring slots without a global barrier (h = 0 in
- *               2D).  With tile_planes = L/P each walker runs as P co-resident
+ *               between neighbouring slots without a global barrier.  With
+ *               tile_planes = L/P each walker runs as P co-resident
  *               workgroups of L/P planes (3D z-planes, 2D rows) that trade
  *               boundary planes and energy shares once per sweep (P R
  *               workgroups, one per compute unit): 3D 16 <= L <= 32 with P = 2,

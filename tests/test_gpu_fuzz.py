@@ -2,7 +2,7 @@
 
 Each case draws a model, lattice, replica count, beta ladder, field (2D), seed,
 schedule (sweeps, exchange interval, record interval), a launch plan (any
-mode, tile height, sweeps per launch, threads, one or two workgroups per
+mode, tile height, sweeps per launch, threads, one to eight workgroups per
 walker) and whether the run goes through pt_run or the primitive pt_sweep /
 pt_exchange calls.  A plan the library rejects for this shape must be rejected
 with PT_EINVAL (and the automatic plan is used instead); every run must equal
@@ -46,7 +46,7 @@ def draw_case(i):
     if mode == TILED:
         plan.update(tile_planes=int(rng.integers(1, L + 1)), sweeps_per_launch=int(rng.integers(1, 9)))
     elif mode == PERSISTENT:
-        plan.update(tile_planes=int(rng.choice([L, L // 2, L // 2])))
+        plan.update(tile_planes=int(rng.choice([L, L // 2, L // 2, L // 4, L // 8])))
     primitive = bool(rng.random() < 0.3)
     return dict(model=model, L=L, R=R, h=h, beta=beta, seed=int(rng.integers(1, 1 << 30)),
                 coupling_seed=int(rng.integers(1, 1 << 30)), sweeps=sweeps, every=every, rec=rec,

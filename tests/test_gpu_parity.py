@@ -237,6 +237,8 @@ def test_split_persistent_plan_rejects_other_shapes(pt):
     (1, 32, 6, dict(mode=PERSISTENT, tile_planes=16, block_threads=512)),   # two workgroups per walker
     (1, 16, 5, dict(mode=PERSISTENT, tile_planes=16, block_threads=256)),   # one per walker
     (0, 32, 8, dict(mode=PERSISTENT, block_threads=256)),
+    (0, 64, 4, dict(mode=PERSISTENT, tile_planes=16, block_threads=256)),   # 2D, four per walker
+    (0, 128, 3, dict(mode=PERSISTENT, tile_planes=64, block_threads=512)),  # 2D, two per walker
 ])
 def test_persistent_wait_bound_stops_the_launch(pt, oracle_mod, model, L, R, plan):
     """A wait limit of 0 makes every bounded wait give up at once: the launch

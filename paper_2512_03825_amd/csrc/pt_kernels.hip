@@ -1557,8 +1557,20 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
         if (!__any((pend | ppend) != 0u)) break;
         __builtin_amdgcn_s_sleep(1);
       }
-      sE = wave_sum(sE);
-      sM = wave_sum(sM);
+      {
+        // the other parts' shares arrived in lanes sl .. sl + 2(P-1) - 1 of
+        // one load round (E at even offsets, M at odd; the launch checks that
+        // they do not wrap past lane 63): read them directly
+        const int sl = (int)(nb & 63u);
+        int32_t tE = 0, tM = 0;
+#pragma unroll
+        for (uint32_t i = 0; i + 1u < P; ++i) {
+          tE += __shfl(sE, sl + 2 * (int)i, 64);
+          tM += __shfl(sM, sl + 2 * (int)i + 1, 64);
+        }
+        sE = tE;
+        sM = tM;
+      }
       // the partner slot's P shares of E (even lanes 0 .. 2P-2) and of M (odd
       // lanes): independent reads
       int32_t Ep = 0, Mp = 0;
@@ -2371,6 +2383,8 @@ hipError_t launch_persist(const DevState &st, const Geometry &g, const Keys &k, 
   if (parts >= 2u) {
     if (parts > split_max_parts(g) || (parts & (parts - 1u)) || g.L / parts < 8u)
       return hipErrorInvalidValue;
+    // the shares a part reads sit in consecutive lanes of one load round
+    if (((4u * (g.plane / 32u)) & 63u) + 2u * (parts - 1u) > 64u) return hipErrorInvalidValue;
     const uint32_t V = split_span(g, threads, parts);
     a.lg_spr = ilog2(g.gpr / V);
     a.lg_ipp = g.dim == 3 ? a.lg_L + a.lg_spr : a.lg_spr;

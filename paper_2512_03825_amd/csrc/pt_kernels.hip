@@ -112,6 +112,28 @@ __device__ __forceinline__ int wave_sum(int v) {
   return v;
 }
 
+// Sum of v over each aligned group of 16 lanes (DPP row rotations, every lane
+// ends with its row's sum).
+__device__ __forceinline__ int row_sum16(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, false); // row_ror:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x122, 0xF, 0xF, false); // row_ror:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false); // row_ror:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false); // row_ror:8
+  return v;
+}
+
+// The value of lane l ^ 16 (ds_swizzle, bit-mask mode: and 0x1F, or 0, xor 0x10).
+__device__ __forceinline__ int swap16(int v) { return __builtin_amdgcn_ds_swizzle(v, 0x401F); }
+
+// Sum of v over the whole wavefront, uniform (read into a scalar register):
+// DPP row sums, then the four rows' sums lane by lane -- no LDS-unit permutes
+// on the way.  Every lane must be active.
+__device__ __forceinline__ int wave_total(int v) {
+  v = row_sum16(v);
+  return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+         __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+}
+
 // The swap-test tables as one kernel reads them: in device memory, or copies
 // in LDS (the fused kernel stages them when they are small).
 struct SwapView {
@@ -536,8 +558,8 @@ __device__ __forceinline__ void tiled_n_body(const TiledArgs &a, uint32_t tile, 
       int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb);
       int dM = 4 * (int)t.sb - 2 * (int)t.n;
       t = {0u, 0u, 0u};
-      dE = wave_sum(dE);
-      dM = wave_sum(dM);
+      dE = wave_total(dE);
+      dM = wave_total(dM);
       if ((tid & 63u) == 0u) {
         s_red[tid >> 6][0] = dE;
         s_red[tid >> 6][1] = dM;
@@ -687,8 +709,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
       int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb);
       int dM = 4 * (int)t.sb - 2 * (int)t.n;
       t = {0u, 0u, 0u};
-      dE = wave_sum(dE);
-      dM = wave_sum(dM);
+      dE = wave_total(dE);
+      dM = wave_total(dM);
       if ((tid & 63u) == 0u) {
         s_red[tid >> 6][0] = dE;
         s_red[tid >> 6][1] = dM;
@@ -988,18 +1010,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   fused_write_back(a, T, tid, nt);
 }
 
-// Sum of v over each aligned group of 16 lanes (DPP row rotations, every lane
-// ends with its row's sum).
-__device__ __forceinline__ int row_sum16(int v) {
-  v += __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, false); // row_ror:1
-  v += __builtin_amdgcn_update_dpp(0, v, 0x122, 0xF, 0xF, false); // row_ror:2
-  v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false); // row_ror:4
-  v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false); // row_ror:8
-  return v;
-}
-
-// The value of lane l ^ 16 (ds_swizzle, bit-mask mode: and 0x1F, or 0, xor 0x10).
-__device__ __forceinline__ int swap16(int v) { return __builtin_amdgcn_ds_swizzle(v, 0x401F); }
 
 // Wave plan (2D, L = 8 or 16): walker w's lattice lives in the registers of
 // lanes [w G, (w + 1) G) of the workgroup, G = L^2/8, one nibble dword (one
@@ -1199,8 +1209,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
         // this wave's energy and magnetisation changes over the sweep, ready
         // at the barrier that ends the sweep
         int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb), dM = 4 * (int)t.sb - 2 * (int)t.n;
-        dE = wave_sum(dE);
-        dM = wave_sum(dM);
+        dE = wave_total(dE);
+        dM = wave_total(dM);
         if ((tid & 63u) == 0u) {
           s_red[tid >> 6][0] = dE;
           s_red[tid >> 6][1] = dM;
@@ -1427,8 +1437,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
         // this wave's energy and magnetisation changes over the sweep, ready
         // at the barrier that ends the sweep
         int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb), dM = 4 * (int)t.sb - 2 * (int)t.n;
-        dE = wave_sum(dE);
-        dM = wave_sum(dM);
+        dE = wave_total(dE);
+        dM = wave_total(dM);
         if ((tid & 63u) == 0u) {
           s_red[tid >> 6][0] = dE;
           s_red[tid >> 6][1] = dM;

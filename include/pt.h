@@ -72,7 +72,11 @@ typedef enum { PT_ISING2D = 0, PT_EA3D = 1 } pt_model;
 typedef struct {
   uint32_t abi_version;     /* must be PT_ABI_VERSION */
   uint32_t model;           /* pt_model */
-  uint32_t L;               /* linear size; power of two, 8 .. 16384 (2D), 8 .. 64 (EA) */
+  uint32_t L;               /* linear size, even (the checkerboard needs two colours on the
+                               periodic lattice): 2D 4 .. 16384, every plan for powers of two
+                               >= 8, the whole-replica tiled plan for other sides (up to the
+                               side whose replica fits one workgroup's LDS, about 560);
+                               EA: a power of two, 8 .. 64 (PT_EUNSUPPORTED otherwise) */
   uint32_t R;               /* replicas = temperature slots, 1 .. 4096 */
   const double *beta;       /* host [R], finite, >= 0, slot order; copied at create */
   double J;                 /* 2D coupling (ignored for EA) */
@@ -202,7 +206,11 @@ pt_status pt_run(pt_ctx *ctx, uint32_t n_sweeps, uint32_t exchange_every);
 
 /* Synchronise the context's stream and copy the requested observables into
  * caller-owned host buffers (layouts in pt_obs).  The only device-to-host
- * transfer of the library. */
+ * transfer of the library: the paper keeps all data on the device during the
+ * run (Sec. 3) and takes the stored chains of the MH iterations as the result
+ * (Sec. 2.1); here the chains are the per-slot E_int and M records (indexed by
+ * temperature slot, the paper's replica), plus the swap counts and, on
+ * request, the final lattices. */
 pt_status pt_observables(pt_ctx *ctx, pt_obs *obs);
 
 /* Host-side view of the threshold tables built at create (for tests and tools):
@@ -217,7 +225,9 @@ pt_status pt_flip_thresholds(const pt_ctx *ctx, uint32_t *out_R_by_16);
  * the edge of the table. */
 pt_status pt_swap_threshold(const pt_ctx *ctx, uint32_t k, int64_t d, uint64_t *out_T);
 
-/* Free the host context (never the caller's workspace or stream). NULL is a no-op. */
+/* Free the host context (never the caller's workspace or stream): the end of the
+ * execution phase (Sec. 3); the device-resident state stays in the caller's
+ * memory until the caller frees it.  NULL is a no-op. */
 void pt_destroy(pt_ctx *ctx);
 
 /* ---- batched form: many independent instances advanced together ------------

@@ -88,8 +88,12 @@ pt_status derive(const pt_config *cfg, Derived *d) {
     return fail(PT_EINVAL, "unknown model %u", cfg->model);
   const uint32_t dim = cfg->model == PT_EA3D ? 3u : 2u;
   const uint32_t maxL = dim == 3 ? 64u : 16384u;
-  if (!is_pow2(cfg->L) || cfg->L < 8u || cfg->L > maxL)
-    return fail(PT_EINVAL, "L = %u: must be a power of two in [8, %u]", cfg->L, maxL);
+  // the checkerboard needs an even side (periodic, two colours)
+  if (cfg->L < 4u || (cfg->L & 1u) || cfg->L > maxL)
+    return fail(PT_EINVAL, "L = %u: must be even, in [4, %u]", cfg->L, maxL);
+  const bool phased = !is_pow2(cfg->L) || cfg->L < 8u;
+  if (phased && dim == 3)
+    return fail(PT_EUNSUPPORTED, "L = %u: the 3D kernels need a power of two in [8, 64]", cfg->L);
   if (cfg->R < 1u || cfg->R > kMaxR) return fail(PT_EINVAL, "R = %u: must be in [1, %u]", cfg->R, kMaxR);
   if (!cfg->beta) return fail(PT_EINVAL, "beta is NULL");
   if (dim == 2 && !std::isfinite(cfg->J)) return fail(PT_EINVAL, "J is not finite");
@@ -111,6 +115,12 @@ pt_status derive(const pt_config *cfg, Derived *d) {
   g.gpr = cfg->L / 8u;
   g.rows = dim == 3 ? cfg->L : 1u;
   g.plane = cfg->L * g.rows;
+  g.nwr = (g.N + 31u) / 32u;
+  g.phased = phased ? 1u : 0u;
+  if (phased && phased_lds_bytes(g) > max_lds_bytes())
+    return fail(PT_EUNSUPPORTED, "L = %u: a 2D side that is not a power of two runs whole replicas "
+                "in LDS, which needs %zu bytes (at most %zu)", cfg->L, phased_lds_bytes(g),
+                max_lds_bytes());
   return PT_OK;
 }
 
@@ -139,8 +149,8 @@ Layout layout(const pt_config *cfg, const Derived &d) {
     o = align_up(o + bytes);
     return at;
   };
-  l.spins[0] = take(R * N / 8); // bit-packed
-  l.spins[1] = take(R * N / 8);
+  l.spins[0] = take(R * g.nwr * 4); // bit-packed, ceil(N/32) words per walker
+  l.spins[1] = take(R * g.nwr * 4);
   l.bonds = take(g.dim == 3 ? 3 * N / 8 : 0);
   // +-1 bytes the host uploads at create (only when the config provides them)
   size_t stage = 0;
@@ -234,6 +244,18 @@ uint32_t persist_parts(const Geometry &g, const pt_plan &p) {
 
 pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
   const Geometry &g = c->d.geo;
+  if (g.phased) {
+    // rows that are not whole 8-site groups: the whole-replica tiled plan only
+    if (p.mode != PT_PLAN_TILED || p.tile_planes < g.L)
+      return fail(PT_EINVAL, "L = %u is not a power of two (or below 8): only the tiled plan with "
+                  "whole replicas (tile_planes >= L) runs it", g.L);
+    if (p.block_threads < 64 || p.block_threads > 1024 || p.block_threads % 64)
+      return fail(PT_EINVAL, "block_threads = %u: must be a multiple of 64 in [64, 1024]", p.block_threads);
+    if (p.sweeps_per_launch < 1 || p.sweeps_per_launch > kMaxSweepsPerLaunch)
+      return fail(PT_EINVAL, "sweeps_per_launch = %u: must be in [1, %u]", p.sweeps_per_launch,
+                  kMaxSweepsPerLaunch);
+    return PT_OK;
+  }
   if (p.mode == PT_PLAN_LANES) { // block size follows R
     if (g.dim != 2 || (g.L != 8 && g.L != 16))
       return fail(PT_EINVAL, "the lanes plan holds a lattice in registers: 2D with L = 8 or 16 only");
@@ -300,6 +322,17 @@ pt_status check_plan(const pt_ctx *c, const pt_plan &p) {
 pt_plan auto_plan(const pt_ctx *c) {
   const Geometry &g = c->d.geo;
   pt_plan p{};
+  if (g.phased) {
+    // whole replicas in place, the most sweeps per launch; with walkers for
+    // every slot, workgroups sized so that those LDS lets share a compute unit
+    // hold about 16 waves together
+    p.mode = PT_PLAN_TILED;
+    p.tile_planes = g.L;
+    p.sweeps_per_launch = kMaxSweepsPerLaunch;
+    const uint32_t per_cu = (uint32_t)std::min<size_t>(4u, std::max<size_t>(1u, max_lds_bytes() / phased_lds_bytes(g)));
+    p.block_threads = g.R >= 256u * per_cu ? std::max<uint32_t>(64u, (1024u / per_cu) & ~63u) : 256u;
+    return p;
+  }
   // Small 2D lattices whose walkers fit one workgroup's wavefronts: no barrier
   // within a sweep (measured 1.1-1.8x the fused plan at L = 8 and 16).
   {
@@ -536,8 +569,9 @@ pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d
   // Laid out from the caller's config: its upload pointers size the staging area.
   c->lay = layout(cfg, d);
   if (ws_bytes < c->lay.total) {
+    const size_t need = c->lay.total;
     delete c;
-    return fail(PT_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, layout(cfg, d).total);
+    return fail(PT_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
   }
   c->tab = shared_tables(&c->cfg, d);
   c->stream = hip_stream;
@@ -693,7 +727,7 @@ pt_status pt_observables(pt_ctx *ctx, pt_obs *obs) {
   if (obs->E_series) D2H(obs->E_series, st.E_series, (size_t)ctx->n_records * R * 4);
   if (obs->M_series) D2H(obs->M_series, st.M_series, (size_t)ctx->n_records * R * 4);
   std::vector<uint32_t> bits; // packed walker lattices
-  const size_t wpr = N / 32;
+  const size_t wpr = ctx->d.geo.nwr;
   if (obs->spins) {
     if (obs->spins_slot == PT_ALL_SLOTS) {
       bits.resize(R * wpr);
@@ -938,6 +972,10 @@ pt_status pt_batch_create(const pt_config *cfgs, uint32_t n, void *hip_stream, v
   pt_status st;
   BatchLayoutHost l = batch_host_layout(cfgs, n, &st);
   if (st != PT_OK) return st;
+  for (uint32_t i = 0; i < n; ++i)
+    if ((cfgs[i].L & (cfgs[i].L - 1u)) || cfgs[i].L < 8u)
+      return fail(PT_EUNSUPPORTED, "instance %u: batched instances need a power-of-two side of at "
+                  "least 8 (L = %u)", i, cfgs[i].L);
   if (!d_workspace || (uintptr_t)d_workspace % kAlign) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
   if (ws_bytes < l.total) return fail(PT_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, l.total);
   pt_batch *b = new (std::nothrow) pt_batch();

@@ -55,6 +55,9 @@ struct Geometry {
   uint32_t gpr;        // 8-site groups per row = L/8
   uint32_t rows;       // rows per plane: 1 (2D) or L (3D)
   uint32_t plane;      // bytes per plane = L*rows
+  uint32_t nwr;        // packed 32-bit words per walker = ceil(N/32)
+  uint32_t phased;     // 2D rows that are not whole 8-site groups, or L not a power of two:
+                       // only the phased whole-replica kernel runs it
 };
 
 struct Keys {
@@ -177,6 +180,8 @@ uint32_t span_groups(const Geometry &g);
 
 // LDS bytes needed by the kernels (host-side planning).
 size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo);
+// LDS of the phased whole-replica kernel (2D lattices with g.phased set).
+size_t phased_lds_bytes(const Geometry &g);
 size_t fused_lds_bytes(const Geometry &g);
 size_t persist_lds_bytes(const Geometry &g, uint32_t parts);
 // Workgroups of the persistent kernel that can be co-resident (0 if unknown).

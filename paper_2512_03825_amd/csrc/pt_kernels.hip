@@ -735,6 +735,263 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
   tiled_epilogue(a, tid, nt, &s_last, gridDim.x * gridDim.y);
 }
 
+// ---- rows that are not whole 8-site groups (2D, any even L) ----------------
+// When 8 does not divide L (or L is not a power of two), the site groups that
+// share a Philox block -- sites 8G .. 8G+7 of the walker in site order -- do not
+// line up with the rows.  Row y then starts at nibble ph = (y L) mod 8 of group
+// G0 = floor(y L / 8), and the LDS keeps each row as its own run of dwords
+// "phased" like that: dword g of row y holds group G0 + g, nibble n the site
+// x = 8 g + n - ph when 0 <= x < L (other nibbles are padding, never flipped).
+// Every dword is then still exactly one Philox group, and the checkerboard
+// colour of nibble n is (n + y) mod 2 as before.  The row above or below has
+// another phase ph': its sites appear shifted by d = ph' - ph nibbles, which a
+// funnel shift (v_alignbit) of two adjacent dwords of that row undoes.  Inside
+// a row the left and right neighbours are the adjacent nibbles, except at the
+// periodic wrap: the first and last dwords of a row are single-group items that
+// patch x = 0's left neighbour (x = L-1) and x = L-1's right neighbour (x = 0),
+// and mask their padding nibbles out of the decision.  The whole replica stays
+// in LDS for the launch (in place).
+constexpr uint32_t kPhasedLead = 3u; // LDS dword of row 0's group 0, so that group 1 is 16-byte aligned
+
+struct PhasedArgs {
+  TiledArgs t;   // H = L, halo = 0: whole replicas, updated in place
+  uint32_t S;    // LDS dwords per row (a multiple of 4)
+  uint32_t Gmax; // groups a row touches, at most
+  uint32_t nI;   // interior spans per row: groups 1 + V k .. 1 + V k + V - 1, k < nI
+  uint32_t nE;   // single-group items per row: group 0, then groups 1 + V nI .. Gmax - 1
+  uint32_t lds_rows; // LDS dword of the per-row table
+};
+
+// Nibbles [lo, hi) of a dword, 0 <= lo <= hi <= 8, as the low bit of each nibble.
+__device__ __forceinline__ uint32_t nibble_bits(uint32_t lo, uint32_t hi) {
+  const uint32_t a = hi >= 8u ? 0xFFFFFFFFu : (1u << (4u * hi)) - 1u;
+  const uint32_t b = lo >= 8u ? 0xFFFFFFFFu : (1u << (4u * lo)) - 1u;
+  return (a & ~b) & 0x11111111u;
+}
+
+// Per-row constants, one uint4 per row in LDS: x = first group G0, y = LDS
+// dword of group 0 | shift of the row above << 16 | shift of the row below
+// << 21 | phase << 26, z / w = LDS dword of the first of the two dwords whose
+// funnel shift gives the view of the row above / below at group 0.
+__device__ __forceinline__ uint4 phased_row_info(uint32_t y, uint32_t L, uint32_t S) {
+  const uint32_t yu = y ? y - 1u : L - 1u, yd = (y + 1u == L) ? 0u : y + 1u;
+  const uint32_t ph = (y * L) & 7u, phu = (yu * L) & 7u, phd = (yd * L) & 7u;
+  const int du = (int)phu - (int)ph, dd = (int)phd - (int)ph;
+  const uint32_t base = kPhasedLead + y * S;
+  const uint32_t bu = kPhasedLead + yu * S - (du < 0 ? 1u : 0u);
+  const uint32_t bd = kPhasedLead + yd * S - (dd < 0 ? 1u : 0u);
+  const uint32_t shu = (uint32_t)(4 * du) & 31u, shd = (uint32_t)(4 * dd) & 31u;
+  return make_uint4((y * L) >> 3, base | (shu << 16) | (shd << 21) | (ph << 26), bu, bd);
+}
+
+// Interior span: V full dwords g0 .. g0+V-1 (1 <= g0, g0+V < the row's last dword)
+// of the row at LDS dword `base`; vu, vd = first dwords of the V+1 dwords of the
+// rows above and below whose funnel shifts by shu, shd align them with this row.
+template <int V>
+__device__ __forceinline__ void span_phased(uint32_t *lds, uint32_t base, uint32_t g0, uint32_t vu,
+                                            uint32_t shu, uint32_t vd, uint32_t shd, uint32_t off,
+                                            const Words (&r)[V], const uint32_t *thr, TallyN &t) {
+  uint32_t *row = lds + base;
+  uint32_t w[V], a[V + 1], b[V + 1], nw[V];
+  lds_load_n<V>(w, row + g0);
+#pragma unroll
+  for (int i = 0; i <= V; ++i) {
+    a[i] = lds[vu + g0 + i];
+    b[i] = lds[vd + g0 + i];
+  }
+  // the neighbouring dword on the side the colour sites need (as in span2d_n)
+  const uint32_t e = row[off ? g0 + V : g0 - 1u];
+  const uint8_t *tb = reinterpret_cast<const uint8_t *>(thr);
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const uint32_t l = __builtin_amdgcn_alignbit(w[v], v ? w[v - 1] : e, 28u);
+    const uint32_t rr = __builtin_amdgcn_alignbit(v < V - 1 ? w[v + 1] : e, w[v], 4u);
+    const uint32_t up = __builtin_amdgcn_alignbit(a[v + 1], a[v], shu);
+    const uint32_t dn = __builtin_amdgcn_alignbit(b[v + 1], b[v], shd);
+    uint32_t u = rr ^ w[v];
+    u = xad(l, w[v], u);
+    u = xad(dn, w[v], u);
+    u = xad(up, w[v], u);
+    nw[v] = decide_n(w[v], u, off, r[v], tb, t);
+  }
+  lds_store_n<V>(row + g0, nw);
+}
+
+// Edge item: the single dword g of a row of phase ph (its first or last dwords):
+// padding nibbles masked out of the decision, the row's periodic wrap patched in.
+__device__ __forceinline__ void edge_phased(uint32_t *lds, uint32_t base, uint32_t g, uint32_t ph,
+                                            uint32_t L, uint32_t vu, uint32_t shu, uint32_t vd,
+                                            uint32_t shd, uint32_t off, const Words &r,
+                                            const uint32_t *thr, TallyN &t) {
+  uint32_t *row = lds + base;
+  const uint32_t w = row[g];
+  uint32_t l = __builtin_amdgcn_alignbit(w, row[(int)g - 1], 28); // g = 0: the dword before the row
+  uint32_t rr = __builtin_amdgcn_alignbit(row[g + 1u], w, 4u);
+  // sites of the row occupy nibbles ph .. ph + L - 1 counted from group 0
+  const int lo = (int)ph - 8 * (int)g, hi = (int)(ph + L) - 8 * (int)g;
+  const uint32_t vm = nibble_bits((uint32_t)min(max(lo, 0), 8), (uint32_t)min(max(hi, 0), 8));
+  if (lo >= 0 && lo < 8) { // x = 0 sits here: its left neighbour is x = L - 1
+    const uint32_t pl = ph + L - 1u;
+    const uint32_t xv = (row[pl >> 3] >> (4u * (pl & 7u))) & 0xFu;
+    const uint32_t sh = 4u * (uint32_t)lo;
+    l = (l & ~(0xFu << sh)) | (xv << sh);
+  }
+  if (hi >= 1 && hi <= 8) { // x = L - 1 sits here: its right neighbour is x = 0
+    const uint32_t xv = (row[ph >> 3] >> (4u * (ph & 7u))) & 0xFu;
+    const uint32_t sh = 4u * (uint32_t)(hi - 1);
+    rr = (rr & ~(0xFu << sh)) | (xv << sh);
+  }
+  const uint32_t up = __builtin_amdgcn_alignbit(lds[vu + g + 1u], lds[vu + g], shu);
+  const uint32_t dn = __builtin_amdgcn_alignbit(lds[vd + g + 1u], lds[vd + g], shd);
+  uint32_t u = rr ^ w;
+  u = xad(l, w, u);
+  u = xad(dn, w, u);
+  u = xad(up, w, u);
+  // decide_n with the padding nibbles excluded: a nibble flips only if it is a site
+  const uint32_t M = off ? 0xF0F0F0F0u : 0x0F0F0F0Fu;
+  const uint32_t rot = off ? 2u : 30u;
+  const uint32_t b0 = 1u << (4u * off);
+  const uint32_t cls = ((w << 3) | u) & M;
+  const uint32_t c4 = __builtin_amdgcn_alignbit(cls, cls, rot);
+  const uint8_t *tb = reinterpret_cast<const uint8_t *>(thr);
+  const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tb + (c4 & 63u));
+  const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 8u, 6u));
+  const uint32_t t2 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 16u, 6u));
+  const uint32_t t3 = *reinterpret_cast<const uint32_t *>(tb + (c4 >> 24));
+  const uint32_t f = ((r.x <= t0 ? b0 : 0u) | (r.y <= t1 ? (b0 << 8) : 0u) |
+                      (r.z <= t2 ? (b0 << 16) : 0u) | (r.w <= t3 ? (b0 << 24) : 0u)) & vm;
+  t.n += __builtin_popcount(f);
+  t.sb = __builtin_amdgcn_udot8(w, f, t.sb, false);
+  t.sc = __builtin_amdgcn_udot8(cls, f, t.sc, false);
+  row[g] = w ^ f;
+}
+
+// Whole-replica sweep of phased rows: grid (1, R), one workgroup per walker.
+template <int V>
+__global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ uint32_t s_thr[kClasses];
+  __shared__ int s_red[kMaxThreads / 64][2];
+  __shared__ uint32_t s_last;
+  const TiledArgs &a = pa.t;
+  const Geometry &G = a.geo;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x, w = blockIdx.y;
+  const uint32_t L = G.L, S = pa.S, nwr = G.nwr;
+  uint32_t *lds = reinterpret_cast<uint32_t *>(smem);
+  uint4 *rows = reinterpret_cast<uint4 *>(lds + pa.lds_rows);
+  const uint32_t slot = a.st.slot_of[w];
+  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+
+  // stage: LDS dword (y, g) <- byte G0(y) + g of the walker's packed sites
+  // (one byte = one group of 8 sites), padding dwords zero
+  {
+    const uint8_t *src = reinterpret_cast<const uint8_t *>(a.src + (size_t)w * nwr);
+    const uint32_t nbytes = 4u * nwr, total = kPhasedLead + L * S + 4u;
+    for (uint32_t q = tid; q < total; q += nt) {
+      uint32_t v = 0u;
+      if (q >= kPhasedLead && q < kPhasedLead + L * S) {
+        const uint32_t y = (q - kPhasedLead) / S, g = (q - kPhasedLead) - y * S;
+        const uint32_t byte = ((y * L) >> 3) + g;
+        if (g < pa.Gmax && byte < nbytes) v = spread8(src[byte]);
+      }
+      lds[q] = v;
+    }
+    for (uint32_t y = tid; y < L; y += nt) rows[y] = phased_row_info(y, L, S);
+  }
+  __syncthreads();
+
+  // each thread's first items, stepped by nt items per round without divisions
+  const uint32_t nI = pa.nI, nE = pa.nE;
+  const uint32_t iy0 = nI ? tid / nI : L, ik0 = nI ? tid - iy0 * nI : 0u; // no interior spans: skip
+  const uint32_t idy = nI ? nt / nI : 0u, idk = nI ? nt - idy * nI : 0u;
+  const uint32_t ey0 = tid / nE, ek0 = tid - ey0 * nE;
+  const uint32_t edy = nt / nE, edk = nt - edy * nE;
+  TallyN t = {0u, 0u, 0u};
+  for (uint32_t hs = 0; hs < 2u * a.sch.nsw; ++hs) {
+    const uint32_t c = hs & 1u;
+    const uint32_t s = a.sch.s0 + (hs >> 1);
+    // interior spans
+    for (uint32_t y = iy0, k = ik0; y < L;) {
+      const uint4 ri = rows[y];
+      const uint32_t base = ri.y & 0xFFFFu, shu = (ri.y >> 16) & 31u, shd = (ri.y >> 21) & 31u;
+      const uint32_t g0 = 1u + k * V, off = (c + y) & 1u;
+      Words r[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        r[v] = philox(ri.x + g0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+      span_phased<V>(lds, base, g0, ri.z, shu, ri.w, shd, off, r, s_thr, t);
+      k += idk;
+      y += idy;
+      if (k >= nI) {
+        k -= nI;
+        ++y;
+      }
+    }
+    // first and last dwords of every row
+    for (uint32_t y = ey0, k = ek0; y < L;) {
+      const uint4 ri = rows[y];
+      const uint32_t base = ri.y & 0xFFFFu, shu = (ri.y >> 16) & 31u, shd = (ri.y >> 21) & 31u;
+      const uint32_t ph = ri.y >> 26;
+      const uint32_t g = k ? nI * V + k : 0u, off = (c + y) & 1u;
+      const Words r = philox(ri.x + g, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+      edge_phased(lds, base, g, ph, L, ri.z, shu, ri.w, shd, off, r, s_thr, t);
+      k += edk;
+      y += edy;
+      if (k >= nE) {
+        k -= nE;
+        ++y;
+      }
+    }
+    if (c == 1u) {
+      // per flip: dE_int = 2z - 4u, dM = 4b - 2
+      int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb);
+      int dM = 4 * (int)t.sb - 2 * (int)t.n;
+      t = {0u, 0u, 0u};
+      dE = wave_total(dE);
+      dM = wave_total(dM);
+      if ((tid & 63u) == 0u) {
+        s_red[tid >> 6][0] = dE;
+        s_red[tid >> 6][1] = dM;
+      }
+    }
+    __syncthreads();
+    if (c == 1u && tid == 0u) {
+      int sE = 0, sM = 0;
+      for (uint32_t v = 0; v < (nt >> 6); ++v) {
+        sE += s_red[v][0];
+        sM += s_red[v][1];
+      }
+      int32_t *acc = a.st.acc3 + ((size_t)(hs >> 1) * G.R + w) * 4u;
+      __hip_atomic_fetch_add(acc, sE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(acc + 1, sM, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+
+  // back to HBM: packed word q holds groups 4q .. 4q+3; a group's sites lie in
+  // the row of its first site and, past that row's end, in the next row's group 0
+  {
+    uint32_t *dst = a.dst + (size_t)w * nwr;
+    const uint32_t N = G.N;
+    for (uint32_t q = tid; q < nwr; q += nt) {
+      uint32_t word = 0u;
+      uint32_t y = (32u * q) / L;
+#pragma unroll
+      for (uint32_t b = 0; b < 4u; ++b) {
+        const uint32_t i0 = 32u * q + 8u * b; // first site of the group
+        if (i0 >= N) break;
+        while (i0 >= (y + 1u) * L) ++y;
+        const uint32_t G0 = (y * L) >> 3, gi = 4u * q + b;
+        const uint32_t k = min(8u, (y + 1u) * L - i0); // sites of the group in row y
+        uint32_t bits = lds[kPhasedLead + y * S + (gi - G0)] & nibble_bits(0u, k);
+        if (k < 8u && y + 1u < L) bits |= lds[kPhasedLead + (y + 1u) * S] & nibble_bits(k, 8u);
+        word |= gather8(bits) << (8u * b);
+      }
+      dst[q] = word;
+    }
+  }
+  tiled_epilogue(a, tid, nt, &s_last, gridDim.x * gridDim.y);
+}
+
 struct FusedArgs {
   DevState st;
   Geometry geo;
@@ -1027,7 +1284,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
 // draws are computed during the current one, off the sweep's dependency chain.
 template <int LL>
 __global__ __launch_bounds__(kMaxThreads) void k_wave(FusedArgs a) {
-  constexpr uint32_t GPR = LL / 8, LG_GPR = LL == 16 ? 1u : 0u; // dwords per row
+  constexpr uint32_t LG_GPR = LL == 16 ? 1u : 0u; // log2 of the dwords per row
   constexpr uint32_t G = LL * LL / 8, NW = LL * LL / 32;        // lanes, packed words per walker
   static_assert(LL == 8 || LL == 16, "wave plan: L = 8 or 16");
   extern __shared__ __align__(16) uint8_t smem[];
@@ -1920,21 +2177,23 @@ __global__ void k_exchange(DevState st, uint32_t R, Keys key, uint32_t e) {
 // purpose); top bit set = down.  upload: convert caller-provided +-1 bytes.
 // One thread per 32-site word of the packed lattice.
 __global__ void k_init_spins(DevState st, Geometry G, Keys key, uint32_t upload) {
-  const uint32_t wpr = G.N >> 5;
-  const uint64_t total = (uint64_t)wpr * G.R;
+  const uint32_t nwr = G.nwr;
+  const uint64_t total = (uint64_t)nwr * G.R;
   for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < total;
        q += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t w = (uint32_t)(q / wpr), i0 = 32u * (uint32_t)(q % wpr);
+    const uint32_t w = (uint32_t)(q / nwr), i0 = 32u * (uint32_t)(q % nwr);
+    const uint32_t n = min(32u, G.N - i0); // sites in this word (the last may be partial)
     uint32_t bits = 0;
     if (upload) {
       const uint8_t *src = st.staging + (size_t)w * G.N + i0;
-      for (uint32_t j = 0; j < 32u; ++j) bits |= (uint32_t)((src[j] >> 7) & 1u) << j;
+      for (uint32_t j = 0; j < n; ++j) bits |= (uint32_t)((src[j] >> 7) & 1u) << j;
     } else {
 #pragma unroll
       for (uint32_t j = 0; j < 8u; ++j) {
         const Words r = philox((i0 >> 2) + j, w, 0u, kPurposeSpin, key.k0, key.k1);
         bits |= ((r.x >> 31) | ((r.y >> 31) << 1) | ((r.z >> 31) << 2) | ((r.w >> 31) << 3)) << (4u * j);
       }
+      if (n < 32u) bits &= (1u << n) - 1u;
     }
     st.spins[0][q] = bits;
   }
@@ -2029,19 +2288,19 @@ __global__ void k_recount_words(DevState st, Geometry G, uint32_t cur) {
 template <int DIM>
 __global__ void k_recount(DevState st, Geometry G, uint32_t cur) {
   const uint32_t w = blockIdx.y;
-  const uint32_t *sp = st.spins[cur] + (size_t)w * (G.N >> 5);
+  const uint32_t *sp = st.spins[cur] + (size_t)w * G.nwr;
   const uint32_t L = G.L;
   int e = 0, m = 0;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < G.N; i += gridDim.x * blockDim.x) {
-    const uint32_t x = i & (L - 1u), y = (i / L) & (L - 1u);
+    const uint32_t x = i % L, y = (i / L) % L;
     const uint32_t bi = bit_at(sp, i);
-    const uint32_t jx = i - x + ((x + 1u) & (L - 1u));
-    const uint32_t jy = i - y * L + ((y + 1u) & (L - 1u)) * L;
+    const uint32_t jx = i - x + (x + 1u == L ? 0u : x + 1u);
+    const uint32_t jy = i - y * L + (y + 1u == L ? 0u : y + 1u) * L;
     uint32_t ux = bi ^ bit_at(sp, jx), uy = bi ^ bit_at(sp, jy);
     if (DIM == 3) {
       const uint32_t z = i / (L * L);
-      const uint32_t jz = i - z * L * L + ((z + 1u) & (L - 1u)) * L * L;
-      const uint32_t nw = G.N >> 5;
+      const uint32_t jz = i - z * L * L + (z + 1u == L ? 0u : z + 1u) * L * L;
+      const uint32_t nw = G.nwr;
       ux ^= bit_at(st.bonds, i);
       uy ^= bit_at(st.bonds + nw, i);
       const uint32_t uz = bi ^ bit_at(sp, jz) ^ bit_at(st.bonds + 2u * nw, i);
@@ -2155,6 +2414,42 @@ const void *split_fn(uint32_t dim, uint32_t V, uint32_t parts) {
        : V == 2 ? split_fn_2d<2>(parts) : split_fn_2d<1>(parts);
 }
 
+// Shape of the phased layout for a 2D lattice of side L (even).
+struct PhasedShape {
+  uint32_t Gmin, Gmax; // groups touched by the rows of phase 0 (fewest) and of the largest phase
+  uint32_t S;          // LDS dwords per row
+  uint32_t V;          // groups per interior span
+  uint32_t nI, nE;     // interior spans and single-group items per row
+  uint32_t lds_rows;   // LDS dword of the per-row table
+  size_t lds;          // LDS bytes
+};
+
+PhasedShape phased_shape(const Geometry &g) {
+  PhasedShape p;
+  const uint32_t L = g.L;
+  // row phases (y L) mod 8 are the multiples of gcd(L, 8) below 8
+  const uint32_t step = (L & 7u) == 0u ? 8u : (L & 3u) == 0u ? 4u : 2u;
+  const uint32_t phmax = step == 8u ? 0u : 8u - step;
+  p.Gmin = (L + 7u) / 8u;
+  p.Gmax = (phmax + L + 7u) / 8u;
+  p.S = (p.Gmax + 3u) & ~3u;
+  p.V = p.Gmin >= 6u ? 4u : 1u;
+  p.nI = p.Gmin >= 2u ? (p.Gmin - 2u) / p.V : 0u;
+  p.nE = p.Gmax - p.nI * p.V;
+  p.lds_rows = (kPhasedLead + L * p.S + 4u + 3u) & ~3u;
+  p.lds = (size_t)p.lds_rows * 4u + (size_t)L * 16u;
+  return p;
+}
+
+template <int V>
+hipError_t launch_phased_v(const PhasedArgs &a, uint32_t R, uint32_t threads, size_t lds,
+                           hipStream_t stream) {
+  hipError_t err = allow_lds(k_phased<V>, lds);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL((k_phased<V>), dim3(1, R), dim3(threads), lds, stream, a);
+  return hipGetLastError();
+}
+
 template <int DIM, int V>
 hipError_t launch_fused_v(const FusedArgs &a, uint32_t threads, size_t lds, hipStream_t stream) {
   const bool pf = (a.geo.R << a.lg_items) <= threads; // one item per thread at most
@@ -2170,9 +2465,12 @@ hipError_t launch_fused_v(const FusedArgs &a, uint32_t threads, size_t lds, hipS
 size_t max_lds_bytes() { return 160u * 1024u - 1024u; }
 
 size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo) {
+  if (g.phased) return phased_lds_bytes(g);
   const size_t np = (size_t)std::min(tile_planes, g.L) + 2u * halo;
   return np * g.plane / 2u * (g.dim == 3 ? 4u : 1u); // four bits per site; 3D: spins + 3 bond planes
 }
+
+size_t phased_lds_bytes(const Geometry &g) { return phased_shape(g).lds; }
 
 size_t fused_lds_bytes(const Geometry &g) { return fused_layout(g.R, g.N, g.dim, 0u).total; }
 
@@ -2209,7 +2507,7 @@ uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads, uint32_t pa
 
 hipError_t launch_init_spins(const DevState &st, const Geometry &g, const Keys &k, bool upload,
                              hipStream_t stream) {
-  const uint64_t total = (uint64_t)(g.N >> 5) * g.R;
+  const uint64_t total = (uint64_t)g.nwr * g.R;
   const uint32_t blocks = (uint32_t)std::min<uint64_t>((total + 255) / 256, 65535);
   hipLaunchKernelGGL(k_init_spins, dim3(blocks), dim3(256), 0, stream, st, g, k,
                      upload ? 1u : 0u);
@@ -2233,7 +2531,7 @@ hipError_t launch_reset(const DevState &st, const Geometry &g, hipStream_t strea
 
 hipError_t launch_recount(const DevState &st, const Geometry &g, uint32_t cur,
                           hipStream_t stream) {
-  if (g.L >= 32u) {
+  if (g.L >= 32u && !g.phased) {
     // rows of whole packed words: one thread per word
     const uint32_t bx = std::min<uint32_t>(((g.N >> 5) + 255u) / 256u, 1024u);
     if (g.dim == 3)
@@ -2272,6 +2570,23 @@ hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, ui
   a.halo = halo;
   a.src = st.spins[cur];
   a.dst = halo ? st.spins[cur ^ 1u] : st.spins[cur];
+  if (g.phased) {
+    // whole replicas only (the plan checks tile_planes >= L): rows of any even length
+    const PhasedShape ps = phased_shape(g);
+    PhasedArgs pa;
+    pa.t = a;
+    pa.t.H = g.L;
+    pa.t.halo = 0u;
+    pa.t.dst = st.spins[cur];
+    pa.t.z2 = 8;
+    pa.S = ps.S;
+    pa.Gmax = ps.Gmax;
+    pa.nI = ps.nI;
+    pa.nE = ps.nE;
+    pa.lds_rows = ps.lds_rows;
+    return ps.V == 4 ? launch_phased_v<4>(pa, g.R, threads, ps.lds, stream)
+                     : launch_phased_v<1>(pa, g.R, threads, ps.lds, stream);
+  }
   const uint32_t V = span_groups(g);
   a.lg_L = ilog2(g.L);
   a.lg_spr = ilog2(g.gpr / V);

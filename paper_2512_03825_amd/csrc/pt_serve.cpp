@@ -588,6 +588,8 @@ pt_status pt_server_submit(pt_server *sv, const pt_config *cfg, uint64_t n_sweep
   if (flags & ~PT_JOB_KEEP_SPINS) return fail(PT_EINVAL, "unknown flags 0x%x", flags);
   const size_t bytes = pt_workspace_bytes(cfg);
   if (!bytes) return PT_EINVAL; // message set by the configuration check
+  if ((cfg->L & (cfg->L - 1u)) || cfg->L < 8u)
+    return fail(PT_EUNSUPPORTED, "served jobs need a power-of-two side of at least 8 (L = %u)", cfg->L);
   if (cfg->record_every && records_between(cfg->record_every, 0, n_sweeps) > cfg->max_records)
     return fail(PT_EINVAL, "%u records would exceed max_records = %u",
                 records_between(cfg->record_every, 0, n_sweeps), cfg->max_records);
@@ -612,6 +614,8 @@ pt_status pt_server_submit(pt_server *sv, const pt_config *cfg, uint64_t n_sweep
   g.gpr = cfg->L / 8u;
   g.rows = dim == 3 ? cfg->L : 1u;
   g.plane = cfg->L * g.rows;
+  g.nwr = (g.N + 31u) / 32u;
+  g.phased = 0u;
   if (!batch_fits(g)) {
     // a tiled lane: tiles of H rows with halos for tiled_sweeps sweeps
     const uint32_t H = tile_rows(g, sv->o.tiled_sweeps);

@@ -57,3 +57,40 @@ def test_batch_matches_oracle_per_instance(oracle_mod, every, sweeps):
         orc.run(sweeps - first, every)
         compare(_Obs(batch, i), orc, "batch instance %d %s" % (i, {k: s[k] for k in ("model", "L", "R")}))
     batch.close()
+
+
+def test_batched2048_shapes_match_oracle(oracle_mod):
+    """Instances of the 2048-instance workload itself (seed 4, their own stream
+    ids, fields and ladders): for every lattice size L in {32, 64, 128, 256} and
+    replica count R in {16, 32, 64} the first such instance of the workload, 12
+    in all, advanced together with an exchange step every 5 sweeps.  The first
+    run covers the online tuning cycles (every candidate decomposition of every
+    group, including one walker per workgroup for L = 128 and 256), the second
+    the graph replay of the chosen ones; each instance is compared with the
+    oracle run alone."""
+    from paper_2512_03825_amd import pt
+    from paper_2512_03825_amd.workloads import batched2048
+    ws = batched2048()
+    picks = {}
+    for w in ws:
+        picks.setdefault((w.L, w.R), w)
+    assert len(picks) == 12 and all(w.h != 0.0 for w in picks.values())
+    specs = [picks[k] for k in sorted(picks)]
+    first, second = 60, 20
+    sweeps = first + second
+    cfgs = [pt.Config(w.model, w.L, w.R, w.beta, h=w.h, seed=w.seed, stream_id=w.stream_id,
+                      record_every=1, max_records=sweeps) for w in specs]
+    say("batched2048 shapes:", [(w.name, w.L, w.R, round(w.h, 4)) for w in specs])
+    batch = pt.Batch(cfgs)
+    batch.run(first, specs[0].exchange_every)
+    batch.run(second, specs[0].exchange_every)
+    plans = batch.group_plans()
+    say("group plans", plans)
+    for i, w in enumerate(specs):
+        say("instance", w.name, "L", w.L, "R", w.R)
+        orc = oracle_mod.Oracle(w.model, w.L, w.R, w.beta, h=w.h, seed=w.seed, stream_id=w.stream_id,
+                                record_every=1, max_records=sweeps)
+        orc.run(first, w.exchange_every)
+        orc.run(second, w.exchange_every)
+        compare(_Obs(batch, i), orc, "%s L %d R %d" % (w.name, w.L, w.R))
+    batch.close()

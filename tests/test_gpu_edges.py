@@ -116,6 +116,7 @@ def test_auto_plans_of_the_bench_workloads(pt):
                                        block_threads=256),
         "paper_shape_L512_R1500": dict(mode=TILED, tile_planes=512, sweeps_per_launch=8,
                                        block_threads=1024),
+        "paper_shape_L300_R1500": dict(mode=TILED, tile_planes=300, sweeps_per_launch=8),
     }
     for name, plan in want.items():
         w = WORKLOADS[name]

@@ -3,6 +3,9 @@
 - A prefix of each full-size schedule is compared bit for bit with values the
   CPU oracle wrote (tests/golden/*.json, made by tests/golden/make_golden.py):
   record series, walker map, swap counts and a SHA-256 of every final spin.
+  The 1024^2 x 64 lattice is also run on a narrow ladder on which swaps are
+  accepted, so that slot changes are compared in the benchmarked launch
+  configuration.
 - Longer runs are checked through properties that hold at any size: the
   incrementally tracked E and M equal a recount of the final lattices, the
   walker map stays a permutation, swap counts follow the alternating pairing,
@@ -37,23 +40,40 @@ def make_sim(pt, w, max_records):
     return pt.Simulation(cfg)
 
 
-@pytest.mark.parametrize("name, plan", [
+# the benchmarked launch configuration of the 1024^2 x 64 workload: four
+# co-resident workgroups of 256 rows per walker, 1024 threads each
+BENCH_PLAN_2D = dict(mode=3, tile_planes=256, block_threads=1024)
+
+
+@pytest.mark.parametrize("case, plan", [
     ("ising2d_L1024_R64", None),
     ("ising2d_L1024_R64", dict(mode=2, tile_planes=256, sweeps_per_launch=5, block_threads=1024)),
+    ("ising2d_L1024_R64_narrow", None),                        # accepted swaps, bench plan
+    ("ising2d_L1024_R64_narrow", dict(mode=2, tile_planes=256, sweeps_per_launch=5, block_threads=1024)),
     ("ea3d_L32_R128", None),                                   # two workgroups per walker
     ("ea3d_L32_R128", dict(mode=3, tile_planes=32, block_threads=1024)),  # one per walker
 ])
-def test_fullsize_prefix_matches_oracle(pt, name, plan):
-    g = json.load(open(os.path.join(GOLDEN, name + ".json")))
-    w = HOT_PATH[name]
+def test_fullsize_prefix_matches_oracle(pt, case, plan):
+    g = json.load(open(os.path.join(GOLDEN, case + ".json")))
+    w = HOT_PATH[g["workload"]]
+    beta = np.array(g["beta"], np.float64)
+    every = g["exchange_every"]
     assert g["L"] == w.L and g["R"] == w.R and g["seed"] == w.seed
-    assert np.array_equal(np.array(g["beta"]), w.beta)
-    say("full-size prefix", name, "sweeps", g["sweeps"], "plan", plan)
-    sim = make_sim(pt, w, g["sweeps"])
+    if case == g["workload"]:
+        assert np.array_equal(beta, w.beta) and every == w.exchange_every
+    say("full-size prefix", case, "sweeps", g["sweeps"], "exchange every", every, "plan", plan)
+    cfg = pt.Config(w.model, w.L, w.R, beta, J=w.J, seed=w.seed, coupling_seed=w.coupling_seed,
+                    record_every=w.record_every, max_records=g["sweeps"])
+    sim = pt.Simulation(cfg)
     if plan is not None:
         sim.set_plan(**plan)
-    say("plan", sim.plan())
-    sim.run(g["sweeps"], w.exchange_every)
+    got_plan = sim.plan()
+    say("plan", got_plan)
+    if plan is None and w.dim == 2:
+        # the automatic plan is the one bench.py times
+        for k, v in BENCH_PLAN_2D.items():
+            assert got_plan[k] == v, (k, got_plan)
+    sim.run(g["sweeps"], every)
     obs = sim.observables(spins="all")
     np.testing.assert_array_equal(obs["E_series"], np.array(g["E_series"], np.int32))
     np.testing.assert_array_equal(obs["M_series"], np.array(g["M_series"], np.int32))
@@ -61,6 +81,11 @@ def test_fullsize_prefix_matches_oracle(pt, name, plan):
     for k in range(w.R - 1):
         assert obs["swap_att"][k, k + 1] == g["swap_att"][k]
         assert obs["swap_acc"][k, k + 1] == g["swap_acc"][k]
+    assert obs["sweeps_done"] == g["sweeps"]
+    assert obs["exchanges_done"] == (g["sweeps"] // every if every else 0)
+    if case.endswith("_narrow"):
+        # the case exists to compare accepted swaps (slot changes) at full size
+        assert sum(g["swap_acc"]) > 0 and not np.array_equal(obs["walker_at"], np.arange(w.R))
     assert hashlib.sha256(obs["spins"].tobytes()).hexdigest() == g["spins_sha256"]
 
 

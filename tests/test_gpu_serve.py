@@ -162,3 +162,33 @@ def test_server_rejects_invalid_jobs():
     assert srv.result(jid)["sweeps_done"] == 10
     srv.release(jid)
     srv.close()
+
+
+def test_tiled_lane_job_equals_the_oracle(oracle_mod):
+    """A 1024^2 job runs on a tiled lane (its replicas do not fit one
+    workgroup's LDS), next to a batched job; its results, final spins included,
+    equal the oracle's."""
+    from paper_2512_03825_amd import pt
+    L, R, sweeps, every = 1024, 4, 20, 5
+    beta = beta_linear(0.4400, 0.4401, R)   # narrow: swaps are accepted
+    big = pt.Config(0, L, R, beta, seed=5, stream_id=2024, record_every=1, max_records=sweeps)
+    small = _cfg(pt, 0, JOBS[0])
+    srv = pt.Server(64 << 20, max_jobs=4, max_walkers=64, tiled_lanes=1, tiled_sweeps=4)
+    jid = srv.submit(big, sweeps, every, keep_spins=True)
+    srv.submit(small, JOBS[0][3], JOBS[0][4])
+    finished = _run_to_completion(srv, 2)
+    lane = {f["job_id"]: f["lane"] for f in finished}[jid]
+    assert lane == 1, lane   # the tiled lane
+    o = oracle_mod.Oracle(0, L, R, beta, seed=5, stream_id=2024, record_every=1, max_records=sweeps)
+    o.run(sweeps, every)
+    got = srv.result(jid, spins="all")
+    Es, Ms = o.series()
+    np.testing.assert_array_equal(got["E_series"], Es)
+    np.testing.assert_array_equal(got["M_series"], Ms)
+    np.testing.assert_array_equal(got["walker_at"], o.labels())
+    att, acc = o.swaps()
+    for k in range(R - 1):
+        assert got["swap_att"][k, k + 1] == att[k] and got["swap_acc"][k, k + 1] == acc[k]
+    assert sum(acc) > 0
+    np.testing.assert_array_equal(got["spins"], o.spins())
+    srv.close()

@@ -45,25 +45,37 @@ def test_workspace_bytes(pt):
     assert n2 >= n + 64 * 1024 * 1024
 
 
-@pytest.mark.parametrize("kw, msg", [
-    (dict(model=0, L=12, R=4), "power of two"),
-    (dict(model=0, L=4, R=4), "power of two"),
-    (dict(model=1, L=128, R=4), "power of two"),
-    (dict(model=0, L=16, R=0), "R = 0"),
-    (dict(model=0, L=16, R=5000), "R = 5000"),
-    (dict(model=2, L=16, R=4), "unknown model"),
-    (dict(model=0, L=16, R=4, beta=[0.3, -1, 0.4, 0.5]), "beta[1]"),
-    (dict(model=0, L=16, R=4, beta=[0.3, float("nan"), 0.4, 0.5]), "beta[1]"),
-    (dict(model=0, L=16, R=4, beta=[0.3, 100.0, 0.4, 0.5]), "underflow"),
+@pytest.mark.parametrize("kw, msg, status", [
+    (dict(model=0, L=13, R=4), "must be even", -1),
+    (dict(model=0, L=2, R=4), "must be even, in [4", -1),
+    (dict(model=0, L=32768, R=4), "must be even, in [4", -1),
+    (dict(model=1, L=128, R=4), "must be even, in [4, 64]", -1),
+    (dict(model=1, L=12, R=4), "3D kernels need a power of two", -5),
+    (dict(model=0, L=1000, R=4), "whole replicas in LDS", -5),
+    (dict(model=0, L=16, R=0), "R = 0", -1),
+    (dict(model=0, L=16, R=5000), "R = 5000", -1),
+    (dict(model=2, L=16, R=4), "unknown model", -1),
+    (dict(model=0, L=16, R=4, beta=[0.3, -1, 0.4, 0.5]), "beta[1]", -1),
+    (dict(model=0, L=16, R=4, beta=[0.3, float("nan"), 0.4, 0.5]), "beta[1]", -1),
+    (dict(model=0, L=16, R=4, beta=[0.3, 100.0, 0.4, 0.5]), "underflow", -1),
 ])
-def test_invalid_configs(pt, kw, msg):
+def test_invalid_configs(pt, kw, msg, status):
     beta = kw.pop("beta", [0.3] * kw["R"]) if kw["R"] <= 16 else np.full(kw["R"], 0.3)
     cfg = pt.Config(kw["model"], kw["L"], kw["R"], np.asarray(beta, np.float64))
     with pytest.raises(pt.PTError, match=re.escape(msg)):
         pt.pt_workspace_bytes(cfg)
     with pytest.raises(pt.PTError) as e:
         pt.pt_create(cfg, 0, 256, 1 << 30)
-    assert e.value.status == -1
+    assert e.value.status == status
+
+
+@pytest.mark.parametrize("L", [4, 6, 10, 12, 20, 24, 100, 300, 520])
+def test_even_sides_that_are_not_powers_of_two_are_accepted(pt, L):
+    """2D sides that are even but not powers of two (the paper's 300 among
+    them) size a workspace: packed spins of ceil(L^2/32) words per walker."""
+    R = 3
+    n = pt.pt_workspace_bytes(pt.Config(0, L, R, np.array([0.3, 0.4, 0.5])))
+    assert n >= 2 * R * 4 * ((L * L + 31) // 32)
 
 
 def test_field_is_accepted_and_must_be_finite(pt):

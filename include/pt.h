@@ -170,6 +170,33 @@ size_t pt_workspace_bytes(const pt_config *cfg);
 pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, size_t ws_bytes,
                     pt_ctx **out);
 
+/* For callers that cannot allocate device memory for the library (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * pt_create, except that the context's sweep scratch -- the per-sweep energy
+ * tallies, the pairwise exchange mailboxes and the split plan's boundary posts
+ * -- lives in a fixed device array inside the library (PT_STATIC_SCRATCH_BYTES,
+ * one copy per GPU and process, held until the process ends) instead of in
+ * the caller's memory.  d_state (caller-owned, 256-byte aligned) then holds
+ * only the simulation state (lattices, tables, maps, energies, record series,
+ * counters): *state_bytes gives its size.  With d_state == NULL nothing is
+ * created and *state_bytes receives the bytes needed (never more than
+ * pt_workspace_bytes(cfg)).  Neither this call nor any later call on the
+ * context allocates device memory; the array's address is looked up once per
+ * GPU, on the first call made with that GPU current.
+ * Every context created this way on one GPU shares that GPU's array, and the
+ * array keeps what the last call left: each pt_sweep / pt_run on such a
+ * context first clears the part it uses (a fill kernel on the context's
+ * stream), so calls on such contexts that overlap in time -- on different
+ * streams or threads -- race and give wrong results; serialise them.  All
+ * other calls behave as for a pt_create context, with the same results bit
+ * for bit.
+ * Errors: as pt_create; PT_ENOMEM if the configuration needs more scratch than
+ * the array holds (R, and for the split plan's posts L, too large), or if
+ * *state_bytes is below the size needed; PT_EINVAL if state_bytes is NULL. */
+#define PT_STATIC_SCRATCH_BYTES (4u << 20)
+pt_status pt_create_static(const pt_config *cfg, void *hip_stream, void *d_state,
+                           size_t *state_bytes, pt_ctx **out);
+
 /* Override the launch plan (validated; PT_EINVAL if impossible for this size). */
 pt_status pt_set_plan(pt_ctx *ctx, const pt_plan *plan);
 /* Read the plan in use. */

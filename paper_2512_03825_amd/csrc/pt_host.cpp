@@ -48,6 +48,8 @@ namespace {
 
 bool is_pow2(uint32_t v) { return v && !(v & (v - 1u)); }
 
+static_assert(kStaticScratchBytes == PT_STATIC_SCRATCH_BYTES, "scratch array size and its ABI constant differ");
+
 constexpr uint32_t kMaxR = 4096;
 constexpr uint32_t kFusedChunk = 4096;   // sweeps per fused or persistent launch
 
@@ -166,16 +168,17 @@ Layout layout(const pt_config *cfg, const Derived &d) {
   l.sof = take(R * 4);
   l.E = take(R * 4);
   l.M = take(R * 4);
-  l.acc3 = take(kMaxSweepsPerLaunch * R * 16);
   l.att = take(R * 4);
   l.acc = take(R * 4);
   l.Es = take((size_t)cfg->max_records * R * 4);
   l.Ms = take((size_t)cfg->max_records * R * 4);
   l.counter = take(16);
-  l.mailbox = take(8 * kMaxParts * R * 8);
-  l.halo = take(split_halo_words(g) * 8);
   l.field = take(R * kFieldDigits * 8);
   l.fsign = take(R * 4);
+  l.scratch = o;
+  l.acc3 = take(kMaxSweepsPerLaunch * R * 16);
+  l.mailbox = take(8 * kMaxParts * R * 8);
+  l.halo = take(split_halo_words(g) * 8);
   l.total = o;
   return l;
 }
@@ -491,6 +494,13 @@ pt_status ctx_advance(pt_ctx *c, uint32_t n, uint32_t every) {
     return fail(PT_EINVAL, "%u more records would exceed max_records = %u", need, c->cfg.max_records);
   if (c->sweeps + n > 0xFFFFFFFFull) return fail(PT_EINVAL, "sweep counter would exceed 2^32");
   const Geometry &g = c->d.geo;
+  if (c->static_scratch && n) {
+    // the fixed array is shared by every such context on this device: tallies
+    // must start at zero, and no post or mailbox word of another context may
+    // carry a tag this run waits for
+    const hipError_t err = launch_zero(c->static_scratch, c->lay.total - c->lay.scratch, c->stream);
+    if (err != hipSuccess) return device_fail(c, err, "scratch clear");
+  }
   uint32_t left = n;
   while (left) {
     Schedule sch{};
@@ -537,7 +547,7 @@ pt_status ctx_advance(pt_ctx *c, uint32_t n, uint32_t every) {
 }  // namespace ptmi
 
 pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d_workspace,
-                           size_t ws_bytes, bool sync, pt_ctx **out) {
+                           size_t ws_bytes, bool sync, uint8_t *static_scratch, pt_ctx **out) {
   if (!out) return fail(PT_EINVAL, "out is NULL");
   *out = nullptr;
   Derived d;
@@ -568,15 +578,25 @@ pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d
   c->keys = {cfg->seed, cfg->stream_id, cfg->coupling_seed};
   // Laid out from the caller's config: its upload pointers size the staging area.
   c->lay = layout(cfg, d);
-  if (ws_bytes < c->lay.total) {
-    const size_t need = c->lay.total;
+  const size_t need = static_scratch ? c->lay.scratch : c->lay.total;
+  if (ws_bytes < need) {
     delete c;
     return fail(PT_ENOMEM, "workspace of %zu bytes, need %zu", ws_bytes, need);
   }
+  if (static_scratch && c->lay.total - c->lay.scratch > kStaticScratchBytes) {
+    const size_t sb = c->lay.total - c->lay.scratch;
+    delete c;
+    return fail(PT_ENOMEM, "this configuration needs %zu bytes of scratch, the fixed array holds %zu",
+                sb, kStaticScratchBytes);
+  }
+  c->static_scratch = static_scratch;
   c->tab = shared_tables(&c->cfg, d);
   c->stream = hip_stream;
 
   uint8_t *base = (uint8_t *)d_workspace;
+  // scratch regions: in the workspace, or at the same offsets from the start
+  // of the fixed array
+  uint8_t *sbase = static_scratch ? static_scratch - c->lay.scratch : base;
   const Layout &l = c->lay;
   DevState &st = c->st;
   st.spins[0] = (uint32_t *)(base + l.spins[0]);
@@ -594,14 +614,14 @@ pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d
   st.slot_of = (uint32_t *)(base + l.sof);
   st.E = (int32_t *)(base + l.E);
   st.M = (int32_t *)(base + l.M);
-  st.acc3 = (int32_t *)(base + l.acc3);
+  st.acc3 = (int32_t *)(sbase + l.acc3);
   st.att = (uint32_t *)(base + l.att);
   st.acc = (uint32_t *)(base + l.acc);
   st.E_series = (int32_t *)(base + l.Es);
   st.M_series = (int32_t *)(base + l.Ms);
   st.counter = (uint32_t *)(base + l.counter);
-  st.mailbox = (uint64_t *)(base + l.mailbox);
-  st.halo = (uint64_t *)(base + l.halo);
+  st.mailbox = (uint64_t *)(sbase + l.mailbox);
+  st.halo = (uint64_t *)(sbase + l.halo);
   st.staging = base + l.staging;
 
   hipError_t e = hipSuccess;
@@ -644,7 +664,31 @@ size_t pt_workspace_bytes(const pt_config *cfg) {
 
 pt_status pt_create(const pt_config *cfg, void *hip_stream, void *d_workspace, size_t ws_bytes,
                     pt_ctx **out) {
-  return ctx_create(cfg, (hipStream_t)hip_stream, d_workspace, ws_bytes, true, out);
+  return ctx_create(cfg, (hipStream_t)hip_stream, d_workspace, ws_bytes, true, nullptr, out);
+}
+
+pt_status pt_create_static(const pt_config *cfg, void *hip_stream, void *d_state,
+                           size_t *state_bytes, pt_ctx **out) {
+  if (out) *out = nullptr;
+  if (!state_bytes) return fail(PT_EINVAL, "state_bytes is NULL");
+  Derived d;
+  pt_status s = derive(cfg, &d);
+  if (s != PT_OK) return s;
+  const Layout l = layout(cfg, d);
+  if (l.total - l.scratch > kStaticScratchBytes)
+    return fail(PT_ENOMEM, "this configuration needs %zu bytes of scratch, the fixed array holds %zu",
+                l.total - l.scratch, kStaticScratchBytes);
+  if (!d_state) { // size query
+    *state_bytes = l.scratch;
+    return PT_OK;
+  }
+  if ((uintptr_t)d_state % kAlign) return fail(PT_EINVAL, "workspace must be 256-byte aligned");
+  if (*state_bytes < l.scratch)
+    return fail(PT_ENOMEM, "workspace of %zu bytes, need %zu", *state_bytes, l.scratch);
+  uint8_t *scr = nullptr;
+  const hipError_t e = static_scratch(&scr);
+  if (e != hipSuccess) return fail(PT_EDEVICE, "scratch array address: %s", hipGetErrorString(e));
+  return ctx_create(cfg, (hipStream_t)hip_stream, d_state, *state_bytes, true, scr, out);
 }
 
 pt_status pt_set_plan(pt_ctx *ctx, const pt_plan *plan) {

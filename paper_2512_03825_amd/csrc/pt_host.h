@@ -31,9 +31,13 @@ struct Tables {
   std::vector<int32_t> fsign;  // [R]
 };
 
+// Byte offsets in a context's workspace.  The scratch of the sweep kernels
+// (per-sweep tallies, exchange mailboxes, boundary posts) comes last, from
+// offset `scratch` to `total`, so that a context whose scratch lives in the
+// library's fixed array (pt_create_static) needs only the first `scratch` bytes.
 struct Layout {
   size_t spins[2], bonds, staging, flip, swap_tab, swap_off, swap_D, swap_sat, wat, sof, E, M,
-      acc3, att, acc, Es, Ms, counter, mailbox, halo, field, fsign, total;
+      att, acc, Es, Ms, counter, field, fsign, scratch, acc3, mailbox, halo, total;
 };
 
 struct Derived {
@@ -67,14 +71,19 @@ struct pt_ctx {
   // persistent launch gives up: orders of magnitude above any legitimate wait
   uint32_t wait_limit = 1u << 24;
   bool poisoned = false;
+  // pt_create_static: the device's fixed scratch array holds acc3, mailbox and
+  // halo (cleared before every sweep call); NULL: they are in the workspace
+  uint8_t *static_scratch = nullptr;
 };
 
 namespace ptmi {
 
 // pt_create with a choice: sync = false leaves the initialisation kernels
-// queued on the stream (errors then surface at the next synchronisation).
+// queued on the stream (errors then surface at the next synchronisation);
+// static_scratch != NULL places the scratch regions there instead of in the
+// workspace (which then needs only Layout::scratch bytes).
 pt_status ctx_create(const pt_config *cfg, hipStream_t stream, void *d_workspace, size_t ws_bytes,
-                     bool sync, pt_ctx **out);
+                     bool sync, uint8_t *static_scratch, pt_ctx **out);
 // Queue n sweeps of the context's plan; exchange after sweep s when every > 0
 // and (s+1) % every == 0.
 pt_status ctx_advance(pt_ctx *c, uint32_t n, uint32_t every);

@@ -17,6 +17,8 @@ constexpr uint32_t kClasses = 16;      // flip-threshold classes per slot: 8*b +
 constexpr uint32_t kFieldDigits = 32;  // binary digits of |dM|/2 with a field swap factor
 constexpr uint32_t kMaxSweepsPerLaunch = 8;
 constexpr uint32_t kMaxParts = 8;            // workgroups per walker of the split persistent plan
+// Size of the library's fixed per-GPU scratch array (contexts of pt_create_static).
+constexpr size_t kStaticScratchBytes = (size_t)4u << 20;
 
 // Device pointers into the caller's workspace.
 struct DevState {
@@ -187,5 +189,13 @@ size_t persist_lds_bytes(const Geometry &g, uint32_t parts);
 // Workgroups of the persistent kernel that can be co-resident (0 if unknown).
 uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads, uint32_t parts);
 size_t max_lds_bytes();
+
+// The current device's copy of the library's fixed scratch array
+// (kStaticScratchBytes, 256-byte aligned): its device address, looked up once
+// per device with that device current.
+hipError_t static_scratch(uint8_t **out);
+// Zero `bytes` (a multiple of 8) of device memory at p with a fill kernel (no
+// memset node, so the call may be captured in a graph).
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream);
 
 }  // namespace ptmi

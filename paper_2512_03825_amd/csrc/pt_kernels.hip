@@ -46,7 +46,15 @@
 #include "pt_internal.h"
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
+#include <vector>
+
+// Scratch of the contexts made by pt_create_static (per-sweep tallies, exchange
+// mailboxes, boundary posts): one copy per GPU, resident until the process
+// ends.  In host code this name is not a device address; the address is taken
+// once per device with hipGetSymbolAddress (static_scratch below).
+static __device__ __align__(256) uint8_t scratch[ptmi::kStaticScratchBytes];
 
 namespace ptmi {
 namespace {
@@ -2800,6 +2808,40 @@ hipError_t launch_batch_target(const BatchInst *insts, uint32_t n, uint32_t add,
   hipLaunchKernelGGL(k_batch_target, dim3((n + 255u) / 256u), dim3(256), 0, stream, insts, n, add,
                      every);
   return hipGetLastError();
+}
+
+namespace {
+__global__ void k_zero_words(uint64_t *p, size_t n) {
+  for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (size_t)gridDim.x * blockDim.x)
+    p[q] = 0;
+}
+}  // namespace
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t stream) {
+  const size_t n = bytes / 8u;
+  if (n == 0) return hipSuccess;
+  const uint32_t blocks = (uint32_t)std::min<size_t>((n + 255u) / 256u, 1024u);
+  hipLaunchKernelGGL(k_zero_words, dim3(blocks), dim3(256), 0, stream, (uint64_t *)p, n);
+  return hipGetLastError();
+}
+
+hipError_t static_scratch(uint8_t **out) {
+  static std::mutex mu;
+  static std::vector<uint8_t *> addr; // per device, filled on first use
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((size_t)dev >= addr.size()) addr.resize((size_t)dev + 1u, nullptr);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p || (uintptr_t)p % 256u) return hipErrorInvalidSymbol;
+    addr[dev] = (uint8_t *)p;
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 }  // namespace ptmi

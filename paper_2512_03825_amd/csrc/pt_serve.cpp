@@ -349,7 +349,7 @@ pt_status admit(pt_server *sv) {
     sv->pending.pop_front();
     j.off = off;
     j.lane = lane;
-    pt_status s = ctx_create(&j.cfg, ln.s, sv->arena_base + off, j.bytes, false, &j.ctx);
+    pt_status s = ctx_create(&j.cfg, ln.s, sv->arena_base + off, j.bytes, false, nullptr, &j.ctx);
     if (s != PT_OK) {
       sv->poisoned = true;
       return s;

@@ -23,7 +23,7 @@ STATUS = {0: "PT_OK", -1: "PT_EINVAL", -2: "PT_ENOMEM", -3: "PT_EDEVICE", -4: "P
           -5: "PT_EUNSUPPORTED"}
 
 # Every symbol include/pt.h declares.
-EXPORTS = ("pt_workspace_bytes", "pt_create", "pt_set_plan", "pt_get_plan", "pt_set_wait_limit", "pt_sweep",
+EXPORTS = ("pt_workspace_bytes", "pt_create", "pt_create_static", "pt_set_plan", "pt_get_plan", "pt_set_wait_limit", "pt_sweep",
            "pt_exchange", "pt_run", "pt_observables", "pt_flip_thresholds", "pt_swap_threshold",
            "pt_destroy", "pt_last_error", "pt_batch_workspace_bytes", "pt_batch_create",
            "pt_batch_run", "pt_batch_observables", "pt_batch_group_plan", "pt_batch_destroy",
@@ -31,6 +31,7 @@ EXPORTS = ("pt_workspace_bytes", "pt_create", "pt_set_plan", "pt_get_plan", "pt_
            "pt_server_done", "pt_server_result", "pt_server_release", "pt_server_stats_get",
            "pt_server_clock", "pt_server_destroy")
 PT_JOB_KEEP_SPINS = 1
+PT_STATIC_SCRATCH_BYTES = 4 << 20
 
 
 class PTError(RuntimeError):
@@ -93,6 +94,7 @@ def _load():
     sig = {
         "pt_workspace_bytes": (C.c_size_t, [P(pt_config)]),
         "pt_create": (st, [P(pt_config), vp, vp, C.c_size_t, P(vp)]),
+        "pt_create_static": (st, [P(pt_config), vp, vp, P(C.c_size_t), P(vp)]),
         "pt_set_plan": (st, [vp, P(pt_plan)]),
         "pt_get_plan": (st, [vp, P(pt_plan)]),
         "pt_set_wait_limit": (st, [vp, C.c_uint32]),
@@ -187,6 +189,21 @@ def pt_create(cfg: Config, hip_stream: int, workspace_ptr: int, workspace_bytes:
     return out
 
 
+def pt_static_state_bytes(cfg: Config) -> int:
+    """Size query of pt_create_static (d_state = NULL)."""
+    n = C.c_size_t(0)
+    _check(_lib.pt_create_static(C.byref(cfg.c), None, None, C.byref(n), None))
+    return int(n.value)
+
+
+def pt_create_static(cfg: Config, hip_stream: int, state_ptr: int, state_bytes: int):
+    out = C.c_void_p()
+    n = C.c_size_t(state_bytes)
+    _check(_lib.pt_create_static(C.byref(cfg.c), C.c_void_p(hip_stream), C.c_void_p(state_ptr),
+                                 C.byref(n), C.byref(out)))
+    return out
+
+
 def pt_set_plan(ctx, mode, tile_planes=0, sweeps_per_launch=0, block_threads=0):
     p = pt_plan(int(mode), int(tile_planes), int(sweeps_per_launch), int(block_threads))
     _check(_lib.pt_set_plan(ctx, C.byref(p)))
@@ -275,17 +292,21 @@ def pt_last_error() -> str:
 
 
 class Simulation:
-    """A context plus a torch-owned device workspace on the current torch stream."""
+    """A context plus a torch-owned device workspace on the current torch stream.
 
-    def __init__(self, cfg: Config, device="cuda", stream=None):
+    static_scratch=True creates it with pt_create_static: the workspace then
+    holds only the state, and the sweep scratch is the library's fixed array."""
+
+    def __init__(self, cfg: Config, device="cuda", stream=None, static_scratch=False):
         import torch
         self.cfg = cfg
-        self.nbytes = pt_workspace_bytes(cfg)
+        self.nbytes = pt_static_state_bytes(cfg) if static_scratch else pt_workspace_bytes(cfg)
         self.workspace = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
         ptr = self.workspace.data_ptr()
         ptr = (ptr + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
-        self.ctx = pt_create(cfg, self.stream.cuda_stream, ptr, self.nbytes)
+        create = pt_create_static if static_scratch else pt_create
+        self.ctx = create(cfg, self.stream.cuda_stream, ptr, self.nbytes)
 
     def set_plan(self, mode, tile_planes=0, sweeps_per_launch=0, block_threads=0):
         pt_set_plan(self.ctx, mode, tile_planes, sweeps_per_launch, block_threads)

@@ -114,3 +114,26 @@ def test_server_options_are_checked(pt):
                     (dict(max_jobs=0), "max_jobs")]:
         with pytest.raises(pt.PTError, match=msg):
             pt.pt_server_overhead_bytes(pt.server_opts(**kw))
+
+
+def test_static_scratch_sizes(pt):
+    """pt_create_static: the size query gives the workspace less its sweep
+    scratch (tallies, mailboxes, boundary posts), configurations whose scratch
+    exceeds the fixed array are refused, and so is a workspace below the
+    queried size -- all before any device call."""
+    beta = np.linspace(0.3, 0.55, 64)
+    cfg = pt.Config(0, 1024, 64, beta, record_every=1, max_records=100)
+    full, state = pt.pt_workspace_bytes(cfg), pt.pt_static_state_bytes(cfg)
+    posts = 2 * 64 * 8 * (4 * 1024 // 32 + 2) * 8       # split-plan posts of 1024^2 x 64
+    assert state + posts < full <= state + pt.PT_STATIC_SCRATCH_BYTES
+    big = pt.Config(0, 1024, 512, np.full(512, 0.4))   # posts alone exceed 4 MiB
+    with pytest.raises(pt.PTError, match="scratch") as e:
+        pt.pt_static_state_bytes(big)
+    assert e.value.status == -2
+    with pytest.raises(pt.PTError, match="workspace of 1024 bytes") as e:
+        pt.pt_create_static(cfg, 0, 256, 1024)
+    assert e.value.status == -2
+    with pytest.raises(pt.PTError, match="aligned"):
+        pt.pt_create_static(cfg, 0, 0x1001, state)
+    with pytest.raises(pt.PTError, match="L = 13"):
+        pt.pt_static_state_bytes(pt.Config(0, 13, 2, np.array([0.3, 0.4])))

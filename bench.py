@@ -25,16 +25,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X: 256 compute units x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 VALU lane
-# slots per second for 32-bit integer operations.  On gfx950 the 32x32->64
-# multiply-add (v_mad_u64_u32) and the three-input XOR (v_bitop3_b32) both issue
-# at that full rate (measured: 34.8e12 and 33.4e12 lane ops/s in dependent-free
-# probe loops).
+# slots per second for 32-bit integer operations (one wave64 instruction per SIMD
+# every four clocks).  On gfx950 the 32x32->64 multiply-add (v_mad_u64_u32) and
+# the three-input XOR (v_bitop3_b32) are full-rate instructions (their measured
+# issue rates are what `--form probe` reports).
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# Algorithmic VALU slots per flip attempt: a quarter of one Philox4x32-10 block
-# (20 multiplies + 20 three-input XORs = 40 slots per block of 4 draws) plus the
-# stencil and decision (2D: 10 -- neighbour sum, spin product, class, threshold
-# compare, conditional flip, E/M update; 3D +-J: 20 with the six couplings).
-SLOTS_PER_ATTEMPT = {2: 10 + 10, 3: 10 + 20}
+# LDS: 128 bytes per clock per compute unit.
+LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
+HBM_PEAK_TBPS = 8.0
+# Least VALU work of one flip attempt under the method's draw contract, the
+# roofline's algorithmic figure: a quarter of a Philox4x32-10 block -- per round
+# two 32x32->64 products and two three-input XORs, one instruction each; the
+# counter words 1-3 (sweep, slot, colour) and the key are the same for every
+# lane, so the first round's second product, the second round's first product
+# and the XORs they feed are scalar work, leaving 18 products + 19 XORs = 37
+# vector instructions per block of four draws -- and one compare of each draw
+# with its threshold.  No kernel that consumes one Philox word per attempt
+# issues fewer, whatever its stencil, tallies and layout cost on top (the
+# kernels issue ~17.5 per attempt in all; the counters give the exact figure).
+PHILOX_VALU_PER_BLOCK = 37
+SLOTS_PER_ATTEMPT = PHILOX_VALU_PER_BLOCK / 4 + 1
+# LDS bytes one attempt moves in the dominant kernels (loads and stores per item,
+# counted from the code): 2D span of 8 nibble dwords (32 attempts): the row, the
+# rows above and below (32 B each), one edge dword, 32 threshold reads, the
+# store (32 B) = 260 B; 3D span of 4 dwords (16 attempts): spins and x bonds
+# (16 B each), edge spin and bond, rows y -+ 1 and their y bonds, planes z -+ 1
+# and their z bonds (8 x 16 B), 16 threshold reads, the store = 248 B.
+LDS_BYTES_PER_ATTEMPT = {2: 260 / 32, 3: 248 / 16}
 
 
 def parse():
@@ -53,11 +70,12 @@ def parse():
                          "(0: no exchange steps; -1: the workload's own)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=4)
-    ap.add_argument("--form", choices=["plain", "batched", "served", "physics"], default="plain",
+    ap.add_argument("--form", choices=["plain", "batched", "served", "physics", "probe"], default="plain",
                     help="plain: one PT instance (the default workload); batched: 2048 "
                          "independent instances advanced together, against the per-instance path; "
                          "served: a Poisson stream of jobs through the request loop; physics: "
-                         "|M|/N and E/N against T and sweeps-to-equilibrium against L")
+                         "|M|/N and E/N against T and sweeps-to-equilibrium against L; probe: "
+                         "issue rates of the VALU instructions the sweep kernels are built from")
     ap.add_argument("--batch-instances", type=int, default=2048)
     ap.add_argument("--batch-sweeps", type=int, default=2000)
     ap.add_argument("--jobs", type=int, default=400, help="served form: jobs in the stream")
@@ -86,12 +104,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, workload, plan, per_launch):
-    """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE passes
-    summarised under profiles/ (each counter scaled by what it reads for a plain
-    copy of known size).  None when there is no such summary, or when it was
-    taken on other kernel sources, another plan or another launch length."""
-    path = os.path.join(ROOT, "profiles", "%s_%s.md" % (kernel, workload))
+def profile_fields(kernel, workload, plan, per_launch, suffix=""):
+    """The `- key: value` lines of profiles/<kernel>_<workload><suffix>.md when
+    that summary was taken on these kernel sources, this plan and this launch
+    length; None otherwise (or when there is no such summary)."""
+    path = os.path.join(ROOT, "profiles", "%s_%s%s.md" % (kernel, workload, suffix))
     if not os.path.exists(path):
         return None
     fields = {}
@@ -104,22 +121,71 @@ def measured_traffic(kernel, workload, plan, per_launch):
             "plan": "mode=%d tile_planes=%d sweeps_per_launch=%d block_threads=%d" % (
                 plan["mode"], plan["tile_planes"], plan["sweeps_per_launch"], plan["block_threads"]),
             "sweeps_per_launch_measured": str(per_launch)}
-    if any(fields.get(k) != v for k, v in want.items()) or "traffic_bytes_per_launch" not in fields:
+    if any(fields.get(k) != v for k, v in want.items()):
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return fields
+
+
+def measured_traffic(kernel, workload, plan, per_launch):
+    """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE passes
+    summarised under profiles/ (each counter scaled by what it reads for a plain
+    copy of known size), or None."""
+    f = profile_fields(kernel, workload, plan, per_launch)
+    return int(f["traffic_bytes_per_launch"]) if f and "traffic_bytes_per_launch" in f else None
+
+
+def measured_valu_insts(kernel, workload, plan, per_launch):
+    """VALU wave-instructions per launch (SQ_INSTS_VALU) from the SQ counter
+    summary under profiles/, or None."""
+    f = profile_fields(kernel, workload, plan, per_launch, "_sq")
+    return float(f["valu_insts_per_launch"]) if f and "valu_insts_per_launch" in f else None
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model
+
+
+def pinned(fn):
+    """Run fn() with this process pinned to one host core (the oracle is
+    single-threaded); returns (result, core)."""
+    try:
+        before = os.sched_getaffinity(0)
+    except (AttributeError, OSError):
+        return fn(), None
+    core = min(before)
+    os.sched_setaffinity(0, {core})
+    try:
+        return fn(), core
+    finally:
+        os.sched_setaffinity(0, before)
 
 
 def cpu_baseline(w, sweeps, every):
-    """The CPU oracle, as it stands, on a bounded prefix of the same workload."""
+    """The CPU oracle, as it stands, on a bounded prefix of the same workload,
+    on one host core."""
     import oracle
     o = oracle.Oracle(w.model, w.L, w.R, w.beta, seed=w.seed, coupling_seed=w.coupling_seed)
-    t0 = time.perf_counter()
-    o.run(sweeps, every)
-    dt = time.perf_counter() - t0
+
+    def go():
+        t0 = time.perf_counter()
+        o.run(sweeps, every)
+        return time.perf_counter() - t0
+
+    dt, core = pinned(go)
     attempts = sweeps * w.attempts_per_sweep
     return {"value": attempts / dt, "unit": "flip attempts/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu(), "host_cpus": os.cpu_count(), "pinned_core": core,
             "sample": "%s: first %d sweeps after initialisation (%.3g flip attempts, %.1f s, "
-                      "single thread)" % (w.name, sweeps, attempts, dt)}
+                      "single thread pinned to one core)" % (w.name, sweeps, attempts, dt)}
 
 
 def bench_batched(args):
@@ -173,16 +239,16 @@ def bench_batched(args):
                                  "sample": "same %d instances one after another, %d sweeps each"
                                            % (len(ws), per_sweeps)},
            "speedup_vs_per_instance": (attempts / dt) / single,
-           "roofline": batched_roofline(attempts / dt, SLOTS_PER_ATTEMPT[2])}
+           "roofline": batched_roofline(attempts / dt)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_instances(ws[:16], 20)
     print(json.dumps(out), flush=True)
 
 
-def batched_roofline(rate, slots):
+def batched_roofline(rate, slots=SLOTS_PER_ATTEMPT):
     """Whole-cycle VALU roofline of a batched or served run: attempts/s times
-    the algorithmic lane slots per attempt (attempt-weighted over the mix),
-    against the VALU peak (exchange and counter launches are inside the time)."""
+    the algorithmic lane slots per attempt, against the VALU peak (exchange
+    and counter launches are inside the time)."""
     achieved = rate * slots / 1e12
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
             "unit": "Tops/s (int32 VALU lane slots)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
@@ -194,19 +260,25 @@ def cpu_baseline_instances(ws, sweeps):
     """The CPU oracle on a bounded sample: the first instances of the list, a
     prefix of each one's schedule, one after another on one core."""
     import oracle
-    t = 0.0
-    attempts = 0
-    for w in ws:
-        o = oracle.Oracle(w.model, w.L, w.R, w.beta, J=w.J, h=w.h, seed=w.seed,
-                          stream_id=w.stream_id, coupling_seed=w.coupling_seed)
-        n = min(sweeps, w.sweeps)
-        t0 = time.perf_counter()
-        o.run(n, w.exchange_every)
-        t += time.perf_counter() - t0
-        attempts += n * w.attempts_per_sweep
+
+    def go():
+        t = 0.0
+        attempts = 0
+        for w in ws:
+            o = oracle.Oracle(w.model, w.L, w.R, w.beta, J=w.J, h=w.h, seed=w.seed,
+                              stream_id=w.stream_id, coupling_seed=w.coupling_seed)
+            n = min(sweeps, w.sweeps)
+            t0 = time.perf_counter()
+            o.run(n, w.exchange_every)
+            t += time.perf_counter() - t0
+            attempts += n * w.attempts_per_sweep
+        return t, attempts
+
+    (t, attempts), core = pinned(go)
     return {"value": attempts / t, "unit": "flip attempts/s", "cores": 1, "kind": "oracle",
+            "host_cpu": host_cpu(), "host_cpus": os.cpu_count(), "pinned_core": core,
             "sample": "first %d instances, %d sweeps each (%.3g flip attempts, %.1f s, single "
-                      "thread)" % (len(ws), sweeps, attempts, t)}
+                      "thread pinned to one core)" % (len(ws), sweeps, attempts, t)}
 
 
 def _serve(pt, srv, cfgs, ws, arrivals, t_label):
@@ -319,9 +391,7 @@ def bench_served(args):
            "plain_fifo_latency_s": {"p50": float(np.percentile(plain_lat, 50)),
                                     "p99": float(np.percentile(plain_lat, 99))},
            "speedup_vs_per_instance": C / plain_capacity,
-           "roofline": batched_roofline(C, sum(w.attempts_per_sweep * w.sweeps * SLOTS_PER_ATTEMPT[w.dim]
-                                               for w in cut) /
-                                           sum(w.attempts_per_sweep * w.sweeps for w in cut))}
+           "roofline": batched_roofline(C)}
     out["roofline"]["kernel"] = "served capacity (batched and tiled lanes)"
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_instances(ws[:8], 20)
@@ -424,8 +494,59 @@ def bench_physics(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_probe(args):
+    """Issue rates of the VALU instructions the sweep kernels are built from
+    (dependency-free loops over the whole chip, libptprobe.so), against the
+    peak derived from the unit counts and the 2.4 GHz clock."""
+    import ctypes as C
+
+    import torch
+    lib = C.CDLL(os.path.join(ROOT, "paper_2512_03825_amd", "libptprobe.so"))
+    lib.ptprobe_run.restype = C.c_int
+    lib.ptprobe_run.argtypes = [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p, C.c_size_t,
+                                C.c_void_p, C.POINTER(C.c_float)]
+    torch.cuda.set_device(0)
+    blocks, threads = 2048, 256           # 8 waves per SIMD
+    out = torch.empty(blocks * threads, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+    # kind, what, VALU instructions per thread and iteration, iterations
+    kinds = [(0, "v_mad_u64_u32 + v_bitop3_b32 (Philox round pair)", 16, 200_000),
+             (1, "v_bitop3_b32", 8, 400_000),
+             (2, "v_add_u32", 8, 400_000),
+             (3, "Philox4x32-10 blocks, one compare per word", None, 30_000)]
+    res = []
+    for kind, what, per_iter, iters in kinds:
+        ms = C.c_float()
+        rc = lib.ptprobe_run(kind, blocks, threads, max(1, iters // 10), C.c_void_p(out.data_ptr()),
+                             out.numel(), C.c_void_p(stream), C.byref(ms))
+        if rc != 0:
+            raise RuntimeError("ptprobe_run(%d) returned hipError %d" % (kind, rc))
+        times = []
+        for _ in range(3):
+            rc = lib.ptprobe_run(kind, blocks, threads, iters, C.c_void_p(out.data_ptr()), out.numel(),
+                                 C.c_void_p(stream), C.byref(ms))
+            if rc != 0:
+                raise RuntimeError("ptprobe_run(%d) returned hipError %d" % (kind, rc))
+            times.append(ms.value * 1e-3)
+        t = min(times)
+        r = {"kind": kind, "what": what, "seconds": t, "threads": blocks * threads, "iters": iters}
+        if per_iter:
+            rate = blocks * threads * per_iter * iters / t / 1e12
+            r.update({"lane_ops_per_s_1e12": round(rate, 3), "frac_of_peak": round(rate / VALU_PEAK_TOPS, 4)})
+        else:
+            words = blocks * threads * 2 * 4 * iters / t
+            r.update({"philox_words_per_s": words,
+                      "frac_of_peak_at_lower_bound": round(words * SLOTS_PER_ATTEMPT / 1e12 / VALU_PEAK_TOPS, 4)})
+        res.append(r)
+        print("[probe] %s: %.3f ms" % (what, t * 1e3), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "VALU issue-rate probe", "peak_lane_ops_per_s_1e12": round(VALU_PEAK_TOPS, 3),
+                      "slots_per_attempt_lower_bound": SLOTS_PER_ATTEMPT, "results": res}), flush=True)
+
+
 def main():
     args = parse()
+    if args.form == "probe" and args.gpus == 1:
+        return bench_probe(args)
     if args.form == "physics" and args.gpus == 1:
         return bench_physics(args)
     if args.form == "batched" and args.gpus == 1:
@@ -499,8 +620,9 @@ def main():
     torch.cuda.synchronize()
     durs = sorted(s.elapsed_time(e) for s, e in zip(starts, ends))
     avg_ms = sum(durs) / len(durs)
-    slots = SLOTS_PER_ATTEMPT[w.dim] * per_launch * w.attempts_per_sweep
-    achieved = slots / (avg_ms * 1e-3) / 1e12
+    attempts_launch = per_launch * w.attempts_per_sweep
+    launch_s = avg_ms * 1e-3
+    achieved = SLOTS_PER_ATTEMPT * attempts_launch / launch_s / 1e12
     # algorithmic HBM bytes of one launch: every walker's packed lattice read
     # (interior plus 2 halo planes per sweep per side and tile) and written once
     tiles = -(-w.L // plan["tile_planes"]) if plan["mode"] == pt.PT_PLAN_TILED else 1
@@ -513,15 +635,27 @@ def main():
     kernel = {pt.PT_PLAN_TILED: "k_tiled_n" if w.dim == 2 else "k_tiled", pt.PT_PLAN_FUSED: "k_fused",
               pt.PT_PLAN_PERSISTENT: "k_persist_split" if split else "k_persist",
               pt.PT_PLAN_LANES: "k_lanes", pt.PT_PLAN_WAVE: "k_wave"}[plan["mode"]]
+    traffic = measured_traffic(kernel, w.name, plan, per_launch)
+    valu_insts = measured_valu_insts(kernel, w.name, plan, per_launch)
+    lds_bytes = LDS_BYTES_PER_ATTEMPT[w.dim] * attempts_launch
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 VALU lane slots)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
-                "traffic": measured_traffic(kernel, w.name, plan, per_launch), "kernel": kernel,
-                "slots_per_attempt": SLOTS_PER_ATTEMPT[w.dim],
+                "traffic": traffic, "kernel": kernel,
+                "slots_per_attempt": SLOTS_PER_ATTEMPT,
                 "avg_launch_ms": round(avg_ms, 5), "median_launch_ms": round(durs[len(durs) // 2], 5),
                 "sweeps_per_launch": per_launch,
-                "attempts_per_s_in_kernel": per_launch * w.attempts_per_sweep / (avg_ms * 1e-3),
+                "attempts_per_s_in_kernel": attempts_launch / launch_s,
+                # VALU instructions the kernel actually issues (SQ counters of this
+                # build), as lane slots against the same peak
+                "valu_insts_per_attempt": (round(valu_insts * 64 / attempts_launch, 3)
+                                           if valu_insts else None),
+                "issue_frac": (round(valu_insts * 64 / launch_s / 1e12 / VALU_PEAK_TOPS, 4)
+                               if valu_insts else None),
+                "lds_bytes_per_attempt": LDS_BYTES_PER_ATTEMPT[w.dim],
+                "lds_frac": round(lds_bytes / launch_s / 1e12 / LDS_PEAK_TBPS, 4),
+                "hbm_frac": (round(traffic / launch_s / 1e12 / HBM_PEAK_TBPS, 5) if traffic else None),
                 "hbm_algorithmic_bytes_per_launch": int(hbm_bytes),
-                "hbm_algorithmic_GBps": round(hbm_bytes / (avg_ms * 1e-3) / 1e9, 1)}
+                "hbm_algorithmic_GBps": round(hbm_bytes / launch_s / 1e9, 1)}
     if split:
         # each of the P workgroups of a walker posts its two lowest and two
         # highest planes (rows in 2D) and its energy shares every sweep as 64-bit
@@ -529,6 +663,37 @@ def main():
         parts = w.L // plan["tile_planes"]
         post_bytes = 8 * (4 * plane_bits // 32 + 2)
         roofline["boundary_post_bytes_per_launch"] = 2 * post_bytes * parts * w.R * per_launch
+
+    if plan["mode"] in (pt.PT_PLAN_FUSED, pt.PT_PLAN_WAVE, pt.PT_PLAN_LANES):
+        # One workgroup runs every walker: a sweep is a chain of dependent steps
+        # (cross-lane reads, LDS round trips, barriers), far from any throughput
+        # roof.  Its floor here: the same plan and schedule with a single walker,
+        # whose chain is the same but contends with nothing.
+        cfg1 = pt.Config(w.model, w.L, 1, w.beta[:1], J=w.J, seed=w.seed,
+                         coupling_seed=w.coupling_seed, record_every=w.record_every,
+                         max_records=(roof_launches + 1) * per_launch // w.record_every)
+        one = pt.Simulation(cfg1, device="cuda:0")
+        one.set_plan(plan["mode"], plan["tile_planes"], plan["sweeps_per_launch"], plan["block_threads"])
+        one.run(per_launch, every)
+        s1 = [torch.cuda.Event(enable_timing=True) for _ in range(roof_launches)]
+        e1 = [torch.cuda.Event(enable_timing=True) for _ in range(roof_launches)]
+        with torch.cuda.stream(one.stream):
+            for i in range(roof_launches):
+                s1[i].record(one.stream)
+                one.run(per_launch, every)
+                e1[i].record(one.stream)
+        torch.cuda.synchronize()
+        floor_ms = sum(a.elapsed_time(b) for a, b in zip(s1, e1)) / roof_launches
+        one.close()
+        us, floor_us = avg_ms * 1e3 / per_launch, floor_ms * 1e3 / per_launch
+        throughput = roofline
+        roofline = {"bound": "latency", "achieved": round(us, 4), "peak": round(floor_us, 4),
+                    "unit": "us per sweep (lower is better)", "frac": round(floor_us / us, 4),
+                    "traffic": None, "kernel": kernel,
+                    "floor": "the same plan and schedule with one walker (no contention)",
+                    "avg_launch_ms": throughput["avg_launch_ms"], "sweeps_per_launch": per_launch,
+                    "attempts_per_s_in_kernel": throughput["attempts_per_s_in_kernel"],
+                    "alu_frac": throughput["frac"]}
 
     if args.copy_calibration:
         a = torch.empty(64 << 20, dtype=torch.uint8, device="cuda:0").fill_(1)

@@ -137,3 +137,18 @@ def test_static_scratch_sizes(pt):
         pt.pt_create_static(cfg, 0, 0x1001, state)
     with pytest.raises(pt.PTError, match="L = 13"):
         pt.pt_static_state_bytes(pt.Config(0, 13, 2, np.array([0.3, 0.4])))
+
+
+def test_probe_library_exports_its_entry_point(pt):
+    """The VALU issue-rate probe (bench.py --form probe) is built beside the
+    library and rejects launch shapes that do not fit its output buffer."""
+    path = os.path.join(os.path.dirname(pt.LIB_PATH), "libptprobe.so")
+    lib = C.CDLL(path)
+    f = lib.ptprobe_run
+    f.restype = C.c_int
+    f.argtypes = [C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.c_void_p, C.c_size_t, C.c_void_p,
+                  C.POINTER(C.c_float)]
+    ms = C.c_float()
+    assert f(0, 4, 256, 1, C.c_void_p(256), 1023, None, C.byref(ms)) != 0   # 1024 threads, 1023 words
+    assert f(4, 1, 64, 1, C.c_void_p(256), 64, None, C.byref(ms)) != 0      # no such kind
+    assert f(0, 1, 96, 1, C.c_void_p(256), 96, None, C.byref(ms)) != 0      # not whole waves

@@ -63,3 +63,41 @@ def test_random_start_orders_below_t_c():
     e = sim.observables()["E_series"][-2000:, 0].mean() / (L * L)
     sim.close()
     assert abs(e - onsager_energy(1 / 1.8)) < 0.02, e
+
+
+def sweeps_to_equilibrium(pt, L, seed, cap=20_000, window=200, tol=0.005):
+    """First sweep s of the T = 2.0 slot (8-slot ladder over T in [2.0, 2.7],
+    exchange every 10 sweeps, random start) after which the mean E/N over the
+    next `window` sweeps is within `tol` (relative) of Onsager's value."""
+    R = 8
+    T = np.array([2.0 + 0.7 * k / (R - 1) for k in range(R)])
+    cfg = pt.Config(pt.PT_ISING2D, L, R, 1.0 / T, seed=100 + seed, record_every=1, max_records=cap)
+    sim = pt.Simulation(cfg)
+    sim.run(cap, 10)
+    e = sim.observables()["E_series"][:, 0].astype(np.float64) / (L * L)
+    sim.close()
+    target = onsager_energy(0.5)
+    w = np.convolve(e, np.ones(window) / window, mode="valid")
+    hit = np.nonzero(np.abs(w - target) < tol * abs(target))[0]
+    return int(hit[0]) if len(hit) else None
+
+
+def test_sweeps_to_equilibrium_grow_as_L_squared():
+    """The paper's convergence figure (Sec. 4.1): the iterations a random start
+    needs to reach equilibrium grow with the lattice, about as L^2.  Here: at
+    T = 2.0 (below T_c), four seeds per L in {16, 32, 64, 128}; every start
+    equilibrates, the median grows with L, and a least-squares fit of log
+    median against log L has a slope between 1.5 and 3 (domain coarsening
+    predicts 2).  The criterion (mean E/N over 200 sweeps within 0.5% of
+    Onsager's value) is ours: the paper does not state its own."""
+    from paper_2512_03825_amd import pt
+    med = []
+    Ls = (16, 32, 64, 128)
+    for L in Ls:
+        found = [sweeps_to_equilibrium(pt, L, s) for s in range(4)]
+        say("equilibrium L", L, "sweeps", found)
+        assert all(f is not None for f in found), (L, found)
+        med.append(float(np.median(found)))
+    assert all(a < b for a, b in zip(med, med[1:])), med
+    slope = np.polyfit(np.log(Ls), np.log(med), 1)[0]
+    assert 1.5 <= slope <= 3.0, (med, slope)

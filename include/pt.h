@@ -265,8 +265,10 @@ void pt_destroy(pt_ctx *ctx);
  * ends, then a device-side counter update -- so the whole cycle is a fixed
  * sequence of launches, captured once in a HIP graph and replayed.  The first
  * cycles of a run time candidate decompositions (walkers per workgroup, block
- * size) per lattice-size group and keep the fastest; decompositions never
- * change results, so every instance is bit-identical to running it alone. */
+ * size) per lattice-size group, then candidate cycle lengths K, and keep the
+ * fastest (the analogue of the paper's block-size study, Sec. 4.2); choices
+ * never change results, so every instance is bit-identical to running it
+ * alone. */
 typedef struct pt_batch pt_batch;
 
 /* Workspace for the batch (the instances' workspaces plus the batch's tables). */
@@ -281,9 +283,16 @@ pt_status pt_batch_run(pt_batch *b, uint32_t n_sweeps, uint32_t exchange_every);
 /* Observables of instance i (synchronises). */
 pt_status pt_batch_observables(pt_batch *b, uint32_t i, pt_obs *obs);
 /* Decomposition chosen for lattice-size group g (0 .. groups-1): walkers per
- * workgroup and block size; returns PT_EINVAL past the last group. */
+ * workgroup, block size, and the sweeps per cycle of the last run (0 before
+ * any); returns PT_EINVAL past the last group.  Output pointers may be NULL.
+ * The choices come from the online tuner, which keeps them in a text file
+ * keyed by device, model, lattice side and replica count (rounded up to a
+ * power of two) -- and, for the sweeps per cycle, the batch's mix of lattice
+ * sizes and its exchange interval -- so that later processes start tuned:
+ * $PTMI_TUNE_CACHE, else $XDG_CACHE_HOME/ptmi/batch_tuning.txt or
+ * ~/.cache/ptmi/batch_tuning.txt (PTMI_TUNE_CACHE set but empty: no file). */
 pt_status pt_batch_group_plan(const pt_batch *b, uint32_t g, uint32_t *L, uint32_t *walkers_per_wg,
-                              uint32_t *block_threads);
+                              uint32_t *block_threads, uint32_t *sweeps_per_cycle);
 void pt_batch_destroy(pt_batch *b);
 
 /* ---- served form: a request loop over jobs that arrive at any time ----------

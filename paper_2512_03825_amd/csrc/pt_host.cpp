@@ -7,12 +7,16 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <new>
 #include <string>
 #include <vector>
+
+#include <sys/stat.h>
+#include <unistd.h>
 
 using namespace ptmi;
 
@@ -862,9 +866,92 @@ struct BatchGroup {
   bool tuned = false;
 };
 
-// Decompositions found fastest, per (model dim, L), for this process.
-std::map<std::pair<uint32_t, uint32_t>, std::pair<uint32_t, uint32_t>> g_tuned;
+// Decompositions found fastest by the online tuner, keyed by what decides
+// them -- the device (architecture and compute units), the model, the lattice
+// side and the replica count rounded up to a power of two -- and kept in a
+// text file so that later processes start tuned: $PTMI_TUNE_CACHE, else
+// $XDG_CACHE_HOME/ptmi/batch_tuning.txt or ~/.cache/ptmi/batch_tuning.txt
+// (PTMI_TUNE_CACHE set but empty: this process only).  One "key = value" line
+// per entry; unreadable or malformed files are ignored, write failures too.
+// The entries in memory follow the file: when the path changes (a process
+// that sets PTMI_TUNE_CACHE anew) they are dropped and the new file is read.
+// Decompositions never change results, so a stale entry only costs speed.
 std::mutex g_tuned_mu;
+std::map<std::string, std::string> g_tuned; // guarded by g_tuned_mu
+bool g_tuned_loaded = false;
+std::string g_tuned_path;
+
+std::string tune_cache_path() {
+  const char *p = std::getenv("PTMI_TUNE_CACHE");
+  if (p) return p;
+  const char *x = std::getenv("XDG_CACHE_HOME");
+  if (x && *x) return std::string(x) + "/ptmi/batch_tuning.txt";
+  const char *h = std::getenv("HOME");
+  if (h && *h) return std::string(h) + "/.cache/ptmi/batch_tuning.txt";
+  return "";
+}
+
+// Called with g_tuned_mu held.
+void tune_cache_load() {
+  const std::string path = tune_cache_path();
+  if (g_tuned_loaded && path == g_tuned_path) return;
+  g_tuned_loaded = true;
+  g_tuned_path = path;
+  g_tuned.clear();
+  if (path.empty()) return;
+  FILE *f = std::fopen(path.c_str(), "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    std::string l(line);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+    const size_t eq = l.find(" = ");
+    if (eq == std::string::npos || eq == 0) continue;
+    g_tuned[l.substr(0, eq)] = l.substr(eq + 3);
+  }
+  std::fclose(f);
+}
+
+// Called with g_tuned_mu held: record an entry and rewrite the file (written
+// to a temporary name and renamed, so readers never see half a file).
+void tune_cache_put(const std::string &key, const std::string &value) {
+  g_tuned[key] = value;
+  const std::string path = tune_cache_path();
+  if (path.empty()) return;
+  for (size_t i = 1; i < path.size(); ++i) // create the directories on the way
+    if (path[i] == '/') (void)mkdir(path.substr(0, i).c_str(), 0755);
+  const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+  FILE *f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (const auto &kv : g_tuned) std::fprintf(f, "%s = %s\n", kv.first.c_str(), kv.second.c_str());
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), path.c_str()) != 0) (void)std::remove(tmp.c_str());
+}
+
+// The current device, as the cache keys name it.
+std::string device_key() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::string arch(prop.gcnArchName);
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  return arch + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+}
+
+uint32_t pow2_at_least(uint32_t v) {
+  uint32_t p = 1;
+  while (p < v) p *= 2u;
+  return p;
+}
+
+std::string group_key(const std::string &dev, const Geometry &g, uint32_t max_R) {
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "group %s %s L=%u R<=%u", dev.c_str(), g.dim == 3 ? "ea3d" : "ising2d",
+                g.L, pow2_at_least(max_R));
+  return buf;
+}
 
 std::vector<std::pair<uint32_t, uint32_t>> batch_candidates(const Geometry &g, uint32_t max_R) {
   std::vector<std::pair<uint32_t, uint32_t>> c;
@@ -904,10 +991,15 @@ BatchInst batch_inst(const pt_ctx *c, uint32_t *ctr) {
 bool batch_fits(const Geometry &g) { return batch_lds_bytes(g, 1) <= max_lds_bytes(); }
 
 std::pair<uint32_t, uint32_t> batch_decomposition(const Geometry &g, uint32_t max_R) {
+  const std::string key = group_key(device_key(), g, max_R);
   {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
-    auto it = g_tuned.find({g.dim, g.L});
-    if (it != g_tuned.end()) return {std::min(it->second.first, max_R), it->second.second};
+    tune_cache_load();
+    auto it = g_tuned.find(key);
+    unsigned W = 0, T = 0;
+    if (it != g_tuned.end() && std::sscanf(it->second.c_str(), "W=%u threads=%u", &W, &T) == 2 &&
+        W >= 1 && T >= 64 && T <= 1024 && T % 64 == 0)
+      return {std::min<uint32_t>(W, max_R), T};
   }
   return batch_candidates(g, max_R)[0];
 }
@@ -931,6 +1023,11 @@ struct pt_batch {
   uint32_t graph_K = 0;
   bool graph_dirty = true;
   bool poisoned = false;
+  std::string dev;       // device key of the tuning cache
+  // sweeps per cycle: tuned per (device, mix of groups, exchange interval) over
+  // the divisors of the interval up to 16, one timed cycle each
+  uint32_t K = 0;        // the value of the last run
+  std::map<uint32_t, uint32_t> K_best; // exchange interval -> tuned K
 };
 
 namespace {
@@ -1060,18 +1157,21 @@ pt_status pt_batch_create(const pt_config *cfgs, uint32_t n, void *hip_stream, v
   std::sort(b->groups.begin(), b->groups.end(),
             [](const BatchGroup &x, const BatchGroup &y) { return x.g.N * (x.g.dim == 3 ? 4 : 1) > y.g.N * (y.g.dim == 3 ? 4 : 1); });
   uint32_t off = 0;
+  b->dev = device_key();
   {
     std::lock_guard<std::mutex> lk(g_tuned_mu);
+    tune_cache_load();
     for (auto &G : b->groups) {
       G.cand = batch_candidates(G.g, G.max_R);
-      auto it = g_tuned.find({G.g.dim, G.g.L});
-      if (it != g_tuned.end()) {
-        G.W = std::min(it->second.first, G.max_R);
-        G.threads = it->second.second;
+      G.W = G.cand[0].first;
+      G.threads = G.cand[0].second;
+      auto it = g_tuned.find(group_key(b->dev, G.g, G.max_R));
+      unsigned W = 0, T = 0;
+      if (it != g_tuned.end() && std::sscanf(it->second.c_str(), "W=%u threads=%u", &W, &T) == 2 &&
+          W >= 1 && T >= 64 && T <= 1024 && T % 64 == 0 && batch_lds_bytes(G.g, W) <= max_lds_bytes()) {
+        G.W = std::min<uint32_t>(W, G.max_R);
+        G.threads = T;
         G.tuned = true;
-      } else {
-        G.W = G.cand[0].first;
-        G.threads = G.cand[0].second;
       }
       G.item_off = off;
       uint32_t sumR = 0;
@@ -1102,6 +1202,45 @@ pt_status pt_batch_create(const pt_config *cfgs, uint32_t n, void *hip_stream, v
   return PT_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Key of the sweeps-per-cycle choice: the device, the exchange interval and
+// every lattice-size group of the batch.
+std::string mix_key(const pt_batch *b, uint32_t every) {
+  std::string k = "cycle " + b->dev + " every=" + std::to_string(every);
+  for (const auto &G : b->groups)
+    k += std::string(" ") + (G.g.dim == 3 ? "ea3d" : "ising2d") + ":" + std::to_string(G.g.L) + ":" +
+         std::to_string(pow2_at_least(G.max_R));
+  return k;
+}
+
+// (Re)capture one cycle of K sweeps in the batch's graph if needed.
+hipError_t batch_graph(pt_batch *b, uint32_t K) {
+  if (!b->graph_dirty && b->graph_K == K) return hipSuccess;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = launch_cycle(b, K, b->own);
+    e = hipStreamEndCapture(b->own, &b->graph);
+    if (e == hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) {
+    b->graph_K = K;
+    b->graph_dirty = false;
+  }
+  return e;
+}
+
+}  // namespace
+
+extern "C" {
+
 pt_status pt_batch_run(pt_batch *b, uint32_t n_sweeps, uint32_t exchange_every) {
   if (!b) return fail(PT_EINVAL, "batch is NULL");
   if (b->poisoned) return fail(PT_ESTATE, "batch is poisoned by an earlier device error");
@@ -1112,30 +1251,50 @@ pt_status pt_batch_run(pt_batch *b, uint32_t n_sweeps, uint32_t exchange_every) 
       return fail(PT_EINVAL, "%u more records would exceed max_records = %u", need, c->cfg.max_records);
     if (c->sweeps + n_sweeps > 0xFFFFFFFFull) return fail(PT_EINVAL, "sweep counter would exceed 2^32");
   }
-  // cycle length: the largest divisor of the exchange interval up to 16 sweeps
-  uint32_t K = 16;
-  if (exchange_every) {
-    K = 1;
-    for (uint32_t d = 1; d <= 16 && d <= exchange_every; ++d)
-      if (exchange_every % d == 0) K = d;
+  // sweeps-per-cycle candidates: the divisors of the exchange interval up to
+  // 16 (any count up to 16 without exchanges), largest first -- the default
+  std::vector<uint32_t> Ks;
+  for (uint32_t d = 16; d >= 1; --d)
+    if (exchange_every ? exchange_every % d == 0 : (d & (d - 1u)) == 0) Ks.push_back(d);
+  uint32_t K = Ks[0];
+  bool K_tuned = false;
+  auto kb = b->K_best.find(exchange_every);
+  if (kb != b->K_best.end()) {
+    K = kb->second;
+    K_tuned = true;
+  } else {
+    std::lock_guard<std::mutex> lk(g_tuned_mu);
+    tune_cache_load();
+    auto it = g_tuned.find(mix_key(b, exchange_every));
+    unsigned k = 0;
+    if (it != g_tuned.end() && std::sscanf(it->second.c_str(), "K=%u", &k) == 1 &&
+        std::find(Ks.begin(), Ks.end(), k) != Ks.end()) {
+      K = k;
+      K_tuned = true;
+      b->K_best[exchange_every] = K;
+    }
   }
   const uint32_t n = (uint32_t)b->ctx.size();
   hipError_t e = hipEventRecord(b->ev_sync, b->user);
   if (e == hipSuccess) e = hipStreamWaitEvent(b->own, b->ev_sync, 0);
   if (e == hipSuccess) e = launch_batch_target(b->d_insts, n, n_sweeps, exchange_every, b->own);
   if (e != hipSuccess) return batch_fail(b, e, "batch start");
-  // cycles needed: each runs up to K sweeps and ends on the next exchange point
-  uint32_t cycles = 0;
-  for (uint64_t s = b->ctx[0]->sweeps, t = s + n_sweeps; s < t; ++cycles) {
-    uint64_t step = std::min<uint64_t>(K, t - s);
+  // every instance runs the same schedule: the host replays the sweep count
+  // that the device counters reach (a cycle of K runs up to K sweeps and stops
+  // at the target and at the next exchange point)
+  uint64_t s = b->ctx[0]->sweeps;
+  const uint64_t t = s + n_sweeps;
+  auto cycle_len = [&](uint32_t k) {
+    uint64_t step = std::min<uint64_t>(k, t - s);
     if (exchange_every) step = std::min<uint64_t>(step, exchange_every - s % exchange_every);
-    s += step;
-  }
+    return step;
+  };
 
-  // online tuning: untuned groups try one candidate per cycle, timed by events
+  // online tuning of the decompositions: untuned groups try one candidate per
+  // cycle, timed by events around their sweep launch
   bool tuning = false;
   for (auto &G : b->groups) tuning |= !G.tuned;
-  while (tuning && cycles > 0) {
+  while (tuning && s < t) {
     // groups timing a candidate this cycle: their index and event pair
     std::vector<size_t> timed_groups;
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
@@ -1166,7 +1325,7 @@ pt_status pt_batch_run(pt_batch *b, uint32_t n_sweeps, uint32_t exchange_every) 
     if ((e = launch_batch_exchange(b->d_insts, b->d_pairs, b->n_pairs, K, b->own)) != hipSuccess ||
         (e = launch_batch_advance(b->d_insts, nullptr, n, K, b->own)) != hipSuccess)
       return batch_fail(b, e, "batch cycle launch");
-    --cycles;
+    s += cycle_len(K);
     if ((e = hipStreamSynchronize(b->own)) != hipSuccess) return batch_fail(b, e, "batch tuning");
     for (size_t gi : timed_groups) {
       float ms = 0.f;
@@ -1184,31 +1343,47 @@ pt_status pt_batch_run(pt_batch *b, uint32_t n_sweeps, uint32_t exchange_every) 
         build_items(b, G);
         if ((e = upload_items(b, G, b->own)) != hipSuccess) return batch_fail(b, e, "batch items");
         std::lock_guard<std::mutex> lk(g_tuned_mu);
-        g_tuned[{G.g.dim, G.g.L}] = {G.W, G.threads};
+        tune_cache_put(group_key(b->dev, G.g, G.max_R),
+                       "W=" + std::to_string(G.W) + " threads=" + std::to_string(G.threads));
         b->graph_dirty = true;
       }
       tuning |= !G.tuned;
     }
   }
-  if (cycles > 0) {
-    if (b->graph_dirty || b->graph_K != K) {
-      if (b->exec) (void)hipGraphExecDestroy(b->exec);
-      if (b->graph) (void)hipGraphDestroy(b->graph);
-      b->exec = nullptr;
-      b->graph = nullptr;
-      e = hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal);
-      if (e == hipSuccess) {
-        hipError_t le = launch_cycle(b, K, b->own);
-        e = hipStreamEndCapture(b->own, &b->graph);
-        if (e == hipSuccess) e = le;
-      }
-      if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-      if (e != hipSuccess) return batch_fail(b, e, "batch graph capture");
-      b->graph_K = K;
-      b->graph_dirty = false;
+
+  // online tuning of the sweeps per cycle: one whole graph-replayed cycle per
+  // candidate, timed per sweep; only full-length cycles count
+  if (!K_tuned && Ks.size() > 1) {
+    std::vector<float> per_sweep(Ks.size(), -1.f);
+    for (size_t ci = 0; ci < Ks.size() && s < t; ++ci) {
+      const uint64_t len = cycle_len(Ks[ci]);
+      if (len < Ks[ci]) break; // the rest of the run is shorter than this cycle
+      if ((e = batch_graph(b, Ks[ci])) != hipSuccess) return batch_fail(b, e, "batch graph capture");
+      if ((e = hipEventRecord(b->tune_ev[0], b->own)) != hipSuccess ||
+          (e = hipGraphLaunch(b->exec, b->own)) != hipSuccess ||
+          (e = hipEventRecord(b->tune_ev[1], b->own)) != hipSuccess ||
+          (e = hipStreamSynchronize(b->own)) != hipSuccess)
+        return batch_fail(b, e, "batch cycle timing");
+      s += len;
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, b->tune_ev[0], b->tune_ev[1])) != hipSuccess)
+        return batch_fail(b, e, "batch cycle timing");
+      per_sweep[ci] = ms / (float)len;
     }
-    for (uint32_t c = 0; c < cycles; ++c)
+    if (std::all_of(per_sweep.begin(), per_sweep.end(), [](float v) { return v >= 0.f; })) {
+      K = Ks[std::min_element(per_sweep.begin(), per_sweep.end()) - per_sweep.begin()];
+      b->K_best[exchange_every] = K;
+      std::lock_guard<std::mutex> lk(g_tuned_mu);
+      tune_cache_put(mix_key(b, exchange_every), "K=" + std::to_string(K));
+    }
+  }
+  b->K = K;
+  if (s < t) {
+    if ((e = batch_graph(b, K)) != hipSuccess) return batch_fail(b, e, "batch graph capture");
+    while (s < t) {
       if ((e = hipGraphLaunch(b->exec, b->own)) != hipSuccess) return batch_fail(b, e, "batch graph launch");
+      s += cycle_len(K);
+    }
   }
   if ((e = hipEventRecord(b->ev_sync, b->own)) != hipSuccess ||
       (e = hipStreamWaitEvent(b->user, b->ev_sync, 0)) != hipSuccess)
@@ -1241,11 +1416,12 @@ pt_status pt_batch_observables(pt_batch *b, uint32_t i, pt_obs *obs) {
 }
 
 pt_status pt_batch_group_plan(const pt_batch *b, uint32_t g, uint32_t *L, uint32_t *W,
-                              uint32_t *threads) {
+                              uint32_t *threads, uint32_t *sweeps_per_cycle) {
   if (!b || g >= b->groups.size()) return fail(PT_EINVAL, "group %u out of range", g);
   if (L) *L = b->groups[g].g.L;
   if (W) *W = b->groups[g].W;
   if (threads) *threads = b->groups[g].threads;
+  if (sweeps_per_cycle) *sweeps_per_cycle = b->K;
   return PT_OK;
 }
 

@@ -110,7 +110,8 @@ def _load():
         "pt_batch_create": (st, [P(pt_config), C.c_uint32, vp, vp, C.c_size_t, P(vp)]),
         "pt_batch_run": (st, [vp, C.c_uint32, C.c_uint32]),
         "pt_batch_observables": (st, [vp, C.c_uint32, P(pt_obs)]),
-        "pt_batch_group_plan": (st, [vp, C.c_uint32, P(C.c_uint32), P(C.c_uint32), P(C.c_uint32)]),
+        "pt_batch_group_plan": (st, [vp, C.c_uint32, P(C.c_uint32), P(C.c_uint32), P(C.c_uint32),
+                                     P(C.c_uint32)]),
         "pt_batch_destroy": (None, [vp]),
         "pt_server_overhead_bytes": (C.c_size_t, [P(pt_server_opts)]),
         "pt_server_create": (st, [P(pt_server_opts), vp, C.c_size_t, P(vp)]),
@@ -377,10 +378,11 @@ class Batch:
     def group_plans(self):
         out, g = [], 0
         while True:
-            L, W, T = C.c_uint32(), C.c_uint32(), C.c_uint32()
-            if _lib.pt_batch_group_plan(self.b, g, C.byref(L), C.byref(W), C.byref(T)) != 0:
+            L, W, T, K = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()
+            if _lib.pt_batch_group_plan(self.b, g, C.byref(L), C.byref(W), C.byref(T), C.byref(K)) != 0:
                 return out
-            out.append({"L": L.value, "walkers_per_wg": W.value, "block_threads": T.value})
+            out.append({"L": L.value, "walkers_per_wg": W.value, "block_threads": T.value,
+                        "sweeps_per_cycle": K.value})
             g += 1
 
     def close(self):

@@ -94,3 +94,73 @@ def test_batched2048_shapes_match_oracle(oracle_mod):
         orc.run(second, w.exchange_every)
         compare(_Obs(batch, i), orc, "%s L %d R %d" % (w.name, w.L, w.R))
     batch.close()
+
+
+def _tuning_batch(pt):
+    from paper_2512_03825_amd.workloads import beta_linear
+    cfgs = []
+    for i, (L, R) in enumerate([(32, 4), (64, 8), (64, 3), (128, 4), (32, 6), (128, 2)]):
+        cfgs.append(pt.Config(0, L, R, beta_linear(0.30, 0.55, R), h=0.03 * (i - 2), seed=4,
+                              stream_id=i, record_every=5, max_records=40))
+    return pt.Batch(cfgs), len(cfgs)
+
+
+def _digest(batch, n):
+    import hashlib
+    h = hashlib.sha256()
+    for i in range(n):
+        o = batch.observables(i, spins="all")
+        for k in ("spins", "E_series", "M_series", "walker_at", "swap_acc"):
+            h.update(np.ascontiguousarray(o[k]).tobytes())
+    return h.hexdigest()
+
+
+def test_tuning_cache_file_decides_the_next_batch(tmp_path, monkeypatch):
+    """The online tuner's choices (walkers per workgroup and block size per
+    lattice-size group, sweeps per cycle per mix of groups and interval) are
+    written to the cache file, and a cache file alone decides a new batch's
+    decompositions: pointing PTMI_TUNE_CACHE at a copy of the file (the
+    library then drops what it holds and reads the copy, as a new process
+    would) gives a batch that starts with the first batch's final
+    decompositions, runs the same cycle length without tuning, and ends bit
+    for bit where the first one did; a hand-written entry is taken as given."""
+    from paper_2512_03825_amd import pt
+    first = tmp_path / "first.txt"
+    monkeypatch.setenv("PTMI_TUNE_CACHE", str(first))
+    b1, n = _tuning_batch(pt)
+    b1.run(100, 5)
+    after = b1.group_plans()
+    d1 = _digest(b1, n)
+    b1.close()
+    text = first.read_text()
+    say("tuning cache:\n" + text)
+    assert "group gfx" in text and "cycle gfx" in text and "every=5" in text, text
+    for p in after:
+        assert ("L=%d" % p["L"]) in text and ("W=%d threads=%d" % (p["walkers_per_wg"], p["block_threads"])) in text
+    assert all(p["sweeps_per_cycle"] in (1, 5) for p in after)
+    assert ("K=%d" % after[0]["sweeps_per_cycle"]) in text
+
+    copy = tmp_path / "copy.txt"
+    copy.write_text(text)
+    monkeypatch.setenv("PTMI_TUNE_CACHE", str(copy))
+    b2, _ = _tuning_batch(pt)
+    strip = lambda plans: [{k: q[k] for k in ("L", "walkers_per_wg", "block_threads")} for q in plans]
+    before = b2.group_plans()
+    assert strip(before) == strip(after) and all(q["sweeps_per_cycle"] == 0 for q in before)
+    b2.run(100, 5)
+    assert b2.group_plans() == after
+    assert _digest(b2, n) == d1
+    b2.close()
+
+    # an entry written by hand (one walker per workgroup of 64 threads for the
+    # 64^2 group) is used as given, and changes no result
+    hand = tmp_path / "hand.txt"
+    hand.write_text("\n".join(l if " L=64 " not in l else l.split(" = ")[0] + " = W=1 threads=64"
+                              for l in text.splitlines()) + "\n")
+    monkeypatch.setenv("PTMI_TUNE_CACHE", str(hand))
+    b3, _ = _tuning_batch(pt)
+    p64 = [q for q in b3.group_plans() if q["L"] == 64][0]
+    assert (p64["walkers_per_wg"], p64["block_threads"]) == (1, 64)
+    b3.run(100, 5)
+    assert _digest(b3, n) == d1
+    b3.close()

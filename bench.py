@@ -79,6 +79,16 @@ def parse():
     ap.add_argument("--batch-instances", type=int, default=2048)
     ap.add_argument("--batch-sweeps", type=int, default=2000)
     ap.add_argument("--jobs", type=int, default=400, help="served form: jobs in the stream")
+    ap.add_argument("--job-range", default="",
+                    help="served form: serve only jobs a..b-1 of the stream ('a:b'), arriving at their "
+                         "times in the whole stream shifted so that job a arrives first")
+    ap.add_argument("--rate", type=float, default=0.0,
+                    help="served form: arrival rate in jobs/s (0: rho x measured capacity / mean job)")
+    ap.add_argument("--plain-sample", type=int, default=100,
+                    help="served form: jobs of the stream also served one at a time by the plain "
+                         "path, end to end at their arrival times")
+    ap.add_argument("--latencies-out", default="",
+                    help="served form: write every job's arrival, finish and size to this JSON file")
     ap.add_argument("--rho", type=float, default=0.8, help="served form: offered load / capacity")
     ap.add_argument("--arena-gib", type=float, default=8.0, help="served form: job arena (GiB)")
     ap.add_argument("--tiled-lanes", type=int, default=1, help="served form: streams for large lattices")
@@ -308,11 +318,40 @@ def _serve(pt, srv, cfgs, ws, arrivals, t_label):
     return out
 
 
+def _plain_fifo(pt, cfgs, ws, arrivals):
+    """The plain per-instance path on the same arrivals, one job at a time in
+    arrival order (first come, first served), each job created and run with
+    pt_run at its full length when the previous one has finished; returns the
+    latencies (finish - arrival) and the summed service time."""
+    import torch
+    lat, busy = [], 0.0
+    t0 = time.perf_counter()
+    last_note = time.time()
+    for i, (w, c) in enumerate(zip(ws, cfgs)):
+        now = time.perf_counter() - t0
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        t1 = time.perf_counter()
+        sim = pt.Simulation(c, device="cuda:0")
+        sim.run(w.sweeps, w.exchange_every)
+        torch.cuda.synchronize()
+        sim.close()
+        del sim
+        t2 = time.perf_counter()
+        busy += t2 - t1
+        lat.append(t2 - t0 - arrivals[i])
+        if time.time() - last_note > 10:
+            print("[plain per-instance] %d of %d jobs, t=%.1fs" % (i + 1, len(ws), t2 - t0),
+                  file=sys.stderr, flush=True)
+            last_note = time.time()
+    return lat, busy
+
+
 def bench_served(args):
     """Served form: a Poisson stream of PT jobs through the request loop at
     offered load rho of the server's measured capacity; p50/p99 latency and
-    aggregate flips/s, beside the plain per-instance path serving the same
-    stream one job at a time (first come, first served)."""
+    aggregate flips/s, beside the plain per-instance path serving a sample of
+    the same stream one job at a time (first come, first served), end to end."""
     import numpy as np
     import torch
 
@@ -320,76 +359,77 @@ def bench_served(args):
     from paper_2512_03825_amd.workloads import poisson_arrivals, served_jobs
 
     torch.cuda.set_device(0)
-    ws = served_jobs(n=args.jobs)
-    cfgs = [pt.Config(w.model, w.L, w.R, w.beta, J=w.J, h=w.h, seed=w.seed, stream_id=w.stream_id,
-                      coupling_seed=w.coupling_seed, record_every=w.record_every,
-                      max_records=w.sweeps // w.record_every) for w in ws]
-    att = np.array([w.attempts_per_sweep * w.sweeps for w in ws], dtype=np.float64)
+    all_ws = served_jobs(n=args.jobs)
+    a, b = 0, len(all_ws)
+    if args.job_range:
+        a, b = (int(x) for x in args.job_range.split(":"))
+        if not 0 <= a < b <= len(all_ws):
+            raise SystemExit("--job-range %s outside the %d-job stream" % (args.job_range, len(all_ws)))
+
+    def config(w):
+        return pt.Config(w.model, w.L, w.R, w.beta, J=w.J, h=w.h, seed=w.seed, stream_id=w.stream_id,
+                         coupling_seed=w.coupling_seed, record_every=w.record_every,
+                         max_records=w.sweeps // w.record_every)
+
+    att_all = np.array([w.attempts_per_sweep * w.sweeps for w in all_ws], dtype=np.float64)
     opts = dict(max_jobs=4096, max_walkers=1 << 20, tiled_lanes=args.tiled_lanes, depth=2,
                 cycle_sweeps=10, tiled_sweeps=5, class_sites=[int(x) for x in args.class_sites.split(",") if x])
     srv = pt.Server(int(args.arena_gib * (1 << 30)), device="cuda:0", **opts)
-    # capacity: the first 200 jobs cut to 2000 sweeps, all submitted at once
-    cap_ws = [w for w in ws[:200]]
-    cap_cfgs = cfgs[:200]
+    # capacity: the first 200 jobs of the stream cut to 2000 sweeps, all submitted at once
     import copy
     cut = []
-    for w in cap_ws:
+    for w in all_ws[:200]:
         w2 = copy.copy(w)
         w2.sweeps = min(w.sweeps, 2000)
         cut.append(w2)
     t = time.perf_counter()
-    _serve(pt, srv, cap_cfgs, cut, np.zeros(len(cut)), "capacity")
+    _serve(pt, srv, [config(w) for w in cut], cut, np.zeros(len(cut)), "capacity")
     cap_dt = time.perf_counter() - t
     C = sum(w.attempts_per_sweep * w.sweeps for w in cut) / cap_dt
-    lam = args.rho * C / att.mean()
-    arrivals = poisson_arrivals(lam, len(ws))
+    lam = args.rate if args.rate > 0 else args.rho * C / att_all.mean()
+    arrivals_all = poisson_arrivals(lam, len(all_ws))
+    ws = all_ws[a:b]
+    cfgs = [config(w) for w in ws]
+    att = att_all[a:b]
+    arrivals = arrivals_all[a:b] - arrivals_all[a]
     t = time.perf_counter()
     fin = _serve(pt, srv, cfgs, ws, arrivals, "served rho=%.2f" % args.rho)
     dt = time.perf_counter() - t
     srv.close()
+    fin.sort(key=lambda f: f["job_id"])
     lat = np.array([f["finished"] - f["arrival"] for f in fin])
     span = max(f["finished"] for f in fin) - min(f["arrival"] for f in fin)
     value = att.sum() / span
+    if args.latencies_out:
+        with open(args.latencies_out, "w") as fh:
+            json.dump({"jobs": [a, b], "rate": lam, "arrival": [f["arrival"] for f in fin],
+                       "finished": [f["finished"] for f in fin], "attempts": att.tolist(),
+                       "lane": [f["lane"] for f in fin]}, fh)
 
-    # the plain per-instance path: each job's service time from a short timed
-    # run of the same configuration (100 sweeps, after creation), then the
-    # same arrivals served first come, first served
-    svc = np.zeros(len(ws))
-    last_note = time.time()
-    for i, (w, c) in enumerate(zip(ws, cfgs)):
-        if time.time() - last_note > 10:
-            print("[plain per-instance] timed %d of %d jobs" % (i, len(ws)), file=sys.stderr, flush=True)
-            last_note = time.time()
-        sim = pt.Simulation(c, device="cuda:0")
-        n = min(w.sweeps, 100)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        sim.run(n, w.exchange_every)
-        torch.cuda.synchronize()
-        svc[i] = (time.perf_counter() - t1) * w.sweeps / n
-        sim.close()
-        del sim
-    free_at, plain_lat = 0.0, np.zeros(len(ws))
-    for i in range(len(ws)):
-        start = max(free_at, arrivals[i])
-        free_at = start + svc[i]
-        plain_lat[i] = free_at - arrivals[i]
-    plain_capacity = att.sum() / svc.sum()
+    # the plain per-instance path, end to end on a sample: the first jobs of
+    # the segment at the same arrival times, one at a time
+    m = min(args.plain_sample, len(ws))
+    plain_lat, busy = _plain_fifo(pt, cfgs[:m], ws[:m], arrivals[:m])
+    plain_capacity = att[:m].sum() / busy
     out = {"metric": "served-job latency p50/p99 + flip attempts/s", "value": value,
            "unit": "flip attempts/s", "n_gpus": 1, "steps": len(ws), "warmup": 0,
            "ms_per_step": dt / len(ws) * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-           "config": {"workload": "served%d" % len(ws), "jobs": len(ws), "rho": args.rho,
-                      "arrival_rate_per_s": lam, "mean_attempts_per_job": float(att.mean()),
+           "config": {"workload": "served%d" % len(all_ws), "jobs": [a, b], "rho": args.rho,
+                      "arrival_rate_per_s": lam, "mean_attempts_per_job": float(att_all.mean()),
                       "server": opts, "arena_bytes": int(args.arena_gib * (1 << 30)),
                       "parallelism": "single GPU"},
            "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                          "max": float(lat.max())},
            "capacity": {"served": C, "plain_per_instance": plain_capacity,
                         "sample": "served: first %d jobs cut to 2000 sweeps, all at t=0 (%.1f s); "
-                                  "plain: every job's 100-sweep run scaled to its length" % (len(cut), cap_dt)},
-           "plain_fifo_latency_s": {"p50": float(np.percentile(plain_lat, 50)),
-                                    "p99": float(np.percentile(plain_lat, 99))},
+                                  "plain: the segment's first %d jobs run end to end one at a time "
+                                  "(%.1f s of service)" % (len(cut), cap_dt, m, busy)},
+           "plain_fifo_latency_s": {"jobs": m, "p50": float(np.percentile(plain_lat, 50)),
+                                    "p99": float(np.percentile(plain_lat, 99)),
+                                    "max": float(max(plain_lat))},
+           "served_latency_same_jobs_s": {"p50": float(np.percentile(lat[:m], 50)),
+                                          "p99": float(np.percentile(lat[:m], 99))},
            "speedup_vs_per_instance": C / plain_capacity,
            "roofline": batched_roofline(C)}
     out["roofline"]["kernel"] = "served capacity (batched and tiled lanes)"

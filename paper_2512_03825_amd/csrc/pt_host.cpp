@@ -164,6 +164,7 @@ Layout layout(const pt_config *cfg, const Derived &d) {
   if (cfg->couplings && g.dim == 3) stage = std::max(stage, 3 * N);
   l.staging = take(stage);
   l.flip = take(R * kClasses * 4);
+  l.flipc = take(R * kClasses * 8);
   l.swap_tab = take(std::max<size_t>(swap_entries(cfg, d), 1) * 8);
   l.swap_off = take(R * 4);
   l.swap_D = take(R * 4);
@@ -201,6 +202,9 @@ void build_tables(const pt_config *cfg, const Derived &d, Tables *t) {
                               : (2.0 * (double)s) * (double)F;
         t->flip[(size_t)k * kClasses + 8u * b + u] = flip_threshold(cfg->beta[k], dE);
       }
+  t->flipc.resize(t->flip.size());
+  for (size_t i = 0; i < t->flip.size(); ++i)
+    t->flipc[i] = (0xFFFFFFFFull << 32) | (uint64_t)(~t->flip[i]);
   t->off.assign(R, 0u);
   t->D.assign(R, 0u);
   t->sat.assign(2 * (size_t)R, 0u);
@@ -611,6 +615,7 @@ pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d
   st.spins[1] = (uint32_t *)(base + l.spins[1]);
   st.bonds = (uint32_t *)(base + l.bonds);
   st.flip_thr = (uint32_t *)(base + l.flip);
+  st.flip_cmp = (uint64_t *)(base + l.flipc);
   st.swap_tab = (uint64_t *)(base + l.swap_tab);
   st.swap_off = (uint32_t *)(base + l.swap_off);
   st.swap_D = (uint32_t *)(base + l.swap_D);
@@ -638,6 +643,7 @@ pt_status ptmi::ctx_create(const pt_config *cfg, hipStream_t hip_stream, void *d
     if (e == hipSuccess && n) e = hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, sm);
   };
   H2D(st.flip_thr, c->tab->flip.data(), c->tab->flip.size() * 4);
+  H2D(st.flip_cmp, c->tab->flipc.data(), c->tab->flipc.size() * 8);
   H2D(st.swap_tab, c->tab->swap.data(), c->tab->swap.size() * 8);
   H2D(st.swap_off, c->tab->off.data(), R * 4);
   H2D(st.swap_D, c->tab->D.data(), R * 4);

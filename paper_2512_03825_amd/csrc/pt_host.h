@@ -23,6 +23,7 @@ uint32_t lg2(uint32_t v);
 
 struct Tables {
   std::vector<uint32_t> flip; // [R][16]
+  std::vector<uint64_t> flipc; // [R][16] the kernels' form of flip: (2^32 - 1) << 32 | ~T
   std::vector<uint64_t> swap; // concatenated pair tables
   std::vector<uint32_t> off;  // [R]
   std::vector<uint32_t> D;    // [R]
@@ -36,7 +37,7 @@ struct Tables {
 // offset `scratch` to `total`, so that a context whose scratch lives in the
 // library's fixed array (pt_create_static) needs only the first `scratch` bytes.
 struct Layout {
-  size_t spins[2], bonds, staging, flip, swap_tab, swap_off, swap_D, swap_sat, wat, sof, E, M,
+  size_t spins[2], bonds, staging, flip, flipc, swap_tab, swap_off, swap_D, swap_sat, wat, sof, E, M,
       att, acc, Es, Ms, counter, field, fsign, scratch, acc3, mailbox, halo, total;
 };
 

@@ -25,6 +25,8 @@ struct DevState {
   uint32_t *spins[2];  // [R][N/32] bit-packed, bit set = down (s = -1); walker-indexed
   uint32_t *bonds;     // [3][N/32] bit-packed, bit set = J -1 (EA), bond (i, i+e_d)
   uint32_t *flip_thr;  // [R][16] accept iff r <= T
+  uint64_t *flip_cmp;  // [R][16] the same test as an addend: (2^32 - 1) << 32 | ~T, so that
+                       // r + entry keeps its high word all ones iff r <= T (else it wraps to 0)
   uint64_t *swap_tab;  // concatenated per-pair tables, accept iff r < T
   uint32_t *swap_off;  // [R] index in swap_tab of pair k's entry d = -D[k]
   uint32_t *swap_D;    // [R] half-width D[k]

@@ -400,22 +400,56 @@ struct TallyN {
   uint32_t n, sb, sc;
 };
 
+// High word of r + c (64-bit): one v_mad_u64_u32 (r * 1 + c).  With a table
+// entry c = (2^32 - 1) << 32 | ~T it is all ones iff r <= T and 0 otherwise,
+// so the flip test leaves its outcome as a mask in a vector register.
+__device__ __forceinline__ uint32_t carry_mask(uint32_t r, uint64_t c) {
+  // a multiplier of 1 the compiler cannot see through (else it would fold the
+  // product away and add in two instructions); set once, kept in a scalar register
+  uint32_t one;
+  asm("s_mov_b32 %0, 1" : "=s"(one));
+  return (uint32_t)(((uint64_t)r * one + c) >> 32);
+}
+
 // Metropolis decision for the four colour sites of one dword (nibble layout):
-// w = spins, u = unsatisfied-bond counts per nibble, r = the group's draws.
-// Returns the new spins and adds the accepted flips to the tallies.
+// w = spins, u = unsatisfied-bond counts per nibble, r = the group's draws,
+// tb = the slot's 16 table entries.  Returns the new spins and adds the
+// accepted flips to the tallies.
+//   WIDE: 8-byte entries in the flip_cmp form, tested by the carry of r + entry
+//         (4 multiply-adds, 2 byte permutes and one three-input op for the four
+//         sites: 7 instructions, against 10 for compares and selects);
+//   else: 4-byte thresholds T, tested by r <= T (half the LDS bytes; measured
+//         faster in the 2D split kernel, whose 16 waves per compute unit hide
+//         less LDS latency than the tiled, phased and 3D kernels' 24).
+template <bool WIDE>
 __device__ __forceinline__ uint32_t decide_n(uint32_t w, uint32_t u, uint32_t off, const Words &r,
                                              const uint8_t *tb, TallyN &t) {
   const uint32_t M = off ? 0xF0F0F0F0u : 0x0F0F0F0Fu;   // colour nibbles
-  const uint32_t rot = off ? 2u : 30u;                  // class * 4 to bits 8m .. 8m+5
-  const uint32_t b0 = 1u << (4u * off);
   const uint32_t cls = ((w << 3) | u) & M;              // 8b + u in each colour nibble
-  const uint32_t c4 = __builtin_amdgcn_alignbit(cls, cls, rot);
-  const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tb + (c4 & 63u));
-  const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 8u, 6u));
-  const uint32_t t2 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 16u, 6u));
-  const uint32_t t3 = *reinterpret_cast<const uint32_t *>(tb + (c4 >> 24));
-  const uint32_t f = (r.x <= t0 ? b0 : 0u) | (r.y <= t1 ? (b0 << 8) : 0u) |
-                     (r.z <= t2 ? (b0 << 16) : 0u) | (r.w <= t3 ? (b0 << 24) : 0u);
+  uint32_t f;
+  if constexpr (WIDE) {
+    const uint32_t rot = off ? 1u : 29u;                // class * 8 to bits 8m .. 8m+6
+    const uint32_t c8 = __builtin_amdgcn_alignbit(cls, cls, rot);
+    const uint64_t t0 = *reinterpret_cast<const uint64_t *>(tb + (c8 & 0xFFu));
+    const uint64_t t1 = *reinterpret_cast<const uint64_t *>(tb + __builtin_amdgcn_ubfe(c8, 8u, 8u));
+    const uint64_t t2 = *reinterpret_cast<const uint64_t *>(tb + __builtin_amdgcn_ubfe(c8, 16u, 8u));
+    const uint64_t t3 = *reinterpret_cast<const uint64_t *>(tb + (c8 >> 24));
+    // accept masks (all ones or 0) of the four sites, their low bytes gathered
+    // into bytes 0..3, then the colour nibbles' low bits kept
+    const uint32_t a01 = __builtin_amdgcn_perm(carry_mask(r.y, t1), carry_mask(r.x, t0), 0x0C0C0400u);
+    const uint32_t a23 = __builtin_amdgcn_perm(carry_mask(r.w, t3), carry_mask(r.z, t2), 0x04000C0Cu);
+    f = __builtin_amdgcn_bitop3_b32(a01, a23, 0x01010101u << (4u * off), 0xA8); // (a | b) & c
+  } else {
+    const uint32_t rot = off ? 2u : 30u;                // class * 4 to bits 8m .. 8m+5
+    const uint32_t b0 = 1u << (4u * off);
+    const uint32_t c4 = __builtin_amdgcn_alignbit(cls, cls, rot);
+    const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tb + (c4 & 63u));
+    const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 8u, 6u));
+    const uint32_t t2 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 16u, 6u));
+    const uint32_t t3 = *reinterpret_cast<const uint32_t *>(tb + (c4 >> 24));
+    f = (r.x <= t0 ? b0 : 0u) | (r.y <= t1 ? (b0 << 8) : 0u) | (r.z <= t2 ? (b0 << 16) : 0u) |
+        (r.w <= t3 ? (b0 << 24) : 0u);
+  }
   t.n += __builtin_popcount(f);
   t.sb = __builtin_amdgcn_udot8(w, f, t.sb, false);
   t.sc = __builtin_amdgcn_udot8(cls, f, t.sc, false);
@@ -424,10 +458,10 @@ __device__ __forceinline__ uint32_t decide_n(uint32_t w, uint32_t u, uint32_t of
 
 // 2D Ising, nibble layout: update the colour sites of the V groups (dwords)
 // g0 .. g0+V-1 of one row.
-template <int V>
+template <int V, bool WIDE = true>
 __device__ __forceinline__ void span2d_n(uint32_t *row, const uint32_t *up, const uint32_t *dn,
                                          uint32_t g0, uint32_t gmask, uint32_t off,
-                                         const Words (&r)[V], const uint32_t *thr, TallyN &t) {
+                                         const Words (&r)[V], const void *thr, TallyN &t) {
   uint32_t w[V], a[V], b[V], nw[V];
   lds_load_n<V>(w, row + g0);
   lds_load_n<V>(a, up + g0);
@@ -444,7 +478,7 @@ __device__ __forceinline__ void span2d_n(uint32_t *row, const uint32_t *up, cons
     u = xad(l, w[v], u);
     u = xad(b[v], w[v], u);
     u = xad(a[v], w[v], u);
-    nw[v] = decide_n(w[v], u, off, r[v], tb, t);
+    nw[v] = decide_n<WIDE>(w[v], u, off, r[v], tb, t);
   }
   lds_store_n<V>(row + g0, nw);
 }
@@ -453,12 +487,12 @@ __device__ __forceinline__ void span2d_n(uint32_t *row, const uint32_t *up, cons
 // at site i, bit set = J -1) are dword arrays with plane p, row y at dword
 // (p << lgPl) + (y << lgG).  Updates the colour sites of V dwords g0.. of row
 // y of plane pl; a bond is unsatisfied iff s_i ^ s_j ^ J_ij = 1.
-template <int V>
+template <int V, bool WIDE = true>
 __device__ __forceinline__ void span3d_n(uint32_t *sp, const uint32_t *bx, const uint32_t *by,
                                          const uint32_t *bz, uint32_t lgG, uint32_t lgPl,
                                          uint32_t pl, uint32_t pu, uint32_t pd, uint32_t y,
                                          uint32_t yu, uint32_t yd, uint32_t g0, uint32_t gmask,
-                                         uint32_t off, const Words (&r)[V], const uint32_t *thr,
+                                         uint32_t off, const Words (&r)[V], const void *thr,
                                          TallyN &t) {
   const uint32_t rowb = (pl << lgPl) + (y << lgG);
   uint32_t w[V], jx[V], u[V], nw[V];
@@ -491,7 +525,7 @@ __device__ __forceinline__ void span3d_n(uint32_t *sp, const uint32_t *bx, const
   }
   const uint8_t *tb = reinterpret_cast<const uint8_t *>(thr);
 #pragma unroll
-  for (int v = 0; v < V; ++v) nw[v] = decide_n(w[v], u[v], off, r[v], tb, t);
+  for (int v = 0; v < V; ++v) nw[v] = decide_n<WIDE>(w[v], u[v], off, r[v], tb, t);
   lds_store_n<V>(sp + rowb + g0, nw);
 }
 
@@ -499,7 +533,7 @@ __device__ __forceinline__ void span3d_n(uint32_t *sp, const uint32_t *bx, const
 // sp (LDS), k sweeps, interior written back; per-sweep tallies to acc3.
 template <int V>
 __device__ __forceinline__ void tiled_n_body(const TiledArgs &a, uint32_t tile, uint32_t w,
-                                             uint32_t *sp, uint32_t *s_thr,
+                                             uint32_t *sp, uint64_t *s_thr,
                                              int (*s_red)[2]) {
   const Geometry &G = a.geo;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
@@ -510,7 +544,7 @@ __device__ __forceinline__ void tiled_n_body(const TiledArgs &a, uint32_t tile, 
   const uint32_t np = Ht + 2u * halo;                  // LDS rows
   const uint32_t base = (y0 + L - halo) & (L - 1u);   // global row of LDS row 0
   const uint32_t slot = a.st.slot_of[w];
-  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+  if (tid < kClasses) s_thr[tid] = a.st.flip_cmp[slot * kClasses + tid];
 
   // rows [base, base+np) mod L of this walker, four bits per site; a packed
   // word (32 sites) becomes four LDS dwords (rows shorter than a word only
@@ -598,7 +632,7 @@ __device__ __forceinline__ void tiled_n_body(const TiledArgs &a, uint32_t tile, 
 template <int V>
 __global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ uint32_t s_thr[kClasses];
+  __shared__ uint64_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
   __shared__ uint32_t s_last;
   tiled_n_body<V>(a, blockIdx.x, blockIdx.y, reinterpret_cast<uint32_t *>(smem), s_thr, s_red);
@@ -615,7 +649,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_tiled(const BatchInst *in
                                                              const BatchTileItem *items,
                                                              uint32_t H, uint32_t K) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ uint32_t s_thr[kClasses];
+  __shared__ uint64_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
   __shared__ uint32_t s_last;
   const BatchTileItem it = items[blockIdx.x];
@@ -651,7 +685,7 @@ template <int DIM, int V>
 __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
   static_assert(DIM == 3, "2D lattices use k_tiled_n");
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ uint32_t s_thr[kClasses];
+  __shared__ uint64_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
   __shared__ uint32_t s_last;
 
@@ -667,7 +701,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled(TiledArgs a) {
   const uint32_t np = Ht + 2u * halo;                  // LDS planes
   const uint32_t base = (y0 + L - halo) & (L - 1u);   // global plane of LDS plane 0
   const uint32_t slot = a.st.slot_of[w];
-  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+  if (tid < kClasses) s_thr[tid] = a.st.flip_cmp[slot * kClasses + tid];
 
   // four bits per site: spins, then the x, y, z bond planes of the tile
   uint32_t *sp = reinterpret_cast<uint32_t *>(smem);
@@ -802,7 +836,7 @@ __device__ __forceinline__ uint4 phased_row_info(uint32_t y, uint32_t L, uint32_
 template <int V>
 __device__ __forceinline__ void span_phased(uint32_t *lds, uint32_t base, uint32_t g0, uint32_t vu,
                                             uint32_t shu, uint32_t vd, uint32_t shd, uint32_t off,
-                                            const Words (&r)[V], const uint32_t *thr, TallyN &t) {
+                                            const Words (&r)[V], const uint64_t *thr, TallyN &t) {
   uint32_t *row = lds + base;
   uint32_t w[V], a[V + 1], b[V + 1], nw[V];
   lds_load_n<V>(w, row + g0);
@@ -824,7 +858,7 @@ __device__ __forceinline__ void span_phased(uint32_t *lds, uint32_t base, uint32
     u = xad(l, w[v], u);
     u = xad(dn, w[v], u);
     u = xad(up, w[v], u);
-    nw[v] = decide_n(w[v], u, off, r[v], tb, t);
+    nw[v] = decide_n<true>(w[v], u, off, r[v], tb, t);
   }
   lds_store_n<V>(row + g0, nw);
 }
@@ -834,7 +868,7 @@ __device__ __forceinline__ void span_phased(uint32_t *lds, uint32_t base, uint32
 __device__ __forceinline__ void edge_phased(uint32_t *lds, uint32_t base, uint32_t g, uint32_t ph,
                                             uint32_t L, uint32_t vu, uint32_t shu, uint32_t vd,
                                             uint32_t shd, uint32_t off, const Words &r,
-                                            const uint32_t *thr, TallyN &t) {
+                                            const uint64_t *thr, TallyN &t) {
   uint32_t *row = lds + base;
   const uint32_t w = row[g];
   uint32_t l = __builtin_amdgcn_alignbit(w, row[(int)g - 1], 28); // g = 0: the dword before the row
@@ -861,17 +895,17 @@ __device__ __forceinline__ void edge_phased(uint32_t *lds, uint32_t base, uint32
   u = xad(up, w, u);
   // decide_n with the padding nibbles excluded: a nibble flips only if it is a site
   const uint32_t M = off ? 0xF0F0F0F0u : 0x0F0F0F0Fu;
-  const uint32_t rot = off ? 2u : 30u;
-  const uint32_t b0 = 1u << (4u * off);
+  const uint32_t rot = off ? 1u : 29u;
   const uint32_t cls = ((w << 3) | u) & M;
-  const uint32_t c4 = __builtin_amdgcn_alignbit(cls, cls, rot);
+  const uint32_t c8 = __builtin_amdgcn_alignbit(cls, cls, rot);
   const uint8_t *tb = reinterpret_cast<const uint8_t *>(thr);
-  const uint32_t t0 = *reinterpret_cast<const uint32_t *>(tb + (c4 & 63u));
-  const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 8u, 6u));
-  const uint32_t t2 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 16u, 6u));
-  const uint32_t t3 = *reinterpret_cast<const uint32_t *>(tb + (c4 >> 24));
-  const uint32_t f = ((r.x <= t0 ? b0 : 0u) | (r.y <= t1 ? (b0 << 8) : 0u) |
-                      (r.z <= t2 ? (b0 << 16) : 0u) | (r.w <= t3 ? (b0 << 24) : 0u)) & vm;
+  const uint64_t t0 = *reinterpret_cast<const uint64_t *>(tb + (c8 & 0xFFu));
+  const uint64_t t1 = *reinterpret_cast<const uint64_t *>(tb + __builtin_amdgcn_ubfe(c8, 8u, 8u));
+  const uint64_t t2 = *reinterpret_cast<const uint64_t *>(tb + __builtin_amdgcn_ubfe(c8, 16u, 8u));
+  const uint64_t t3 = *reinterpret_cast<const uint64_t *>(tb + (c8 >> 24));
+  const uint32_t a01 = __builtin_amdgcn_perm(carry_mask(r.y, t1), carry_mask(r.x, t0), 0x0C0C0400u);
+  const uint32_t a23 = __builtin_amdgcn_perm(carry_mask(r.w, t3), carry_mask(r.z, t2), 0x04000C0Cu);
+  const uint32_t f = __builtin_amdgcn_bitop3_b32(a01, a23, 0x01010101u << (4u * off), 0xA8) & vm;
   t.n += __builtin_popcount(f);
   t.sb = __builtin_amdgcn_udot8(w, f, t.sb, false);
   t.sc = __builtin_amdgcn_udot8(cls, f, t.sc, false);
@@ -882,7 +916,7 @@ __device__ __forceinline__ void edge_phased(uint32_t *lds, uint32_t base, uint32
 template <int V>
 __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ uint32_t s_thr[kClasses];
+  __shared__ uint64_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
   __shared__ uint32_t s_last;
   const TiledArgs &a = pa.t;
@@ -892,7 +926,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
   uint32_t *lds = reinterpret_cast<uint32_t *>(smem);
   uint4 *rows = reinterpret_cast<uint4 *>(lds + pa.lds_rows);
   const uint32_t slot = a.st.slot_of[w];
-  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+  if (tid < kClasses) s_thr[tid] = a.st.flip_cmp[slot * kClasses + tid];
 
   // stage: LDS dword (y, g) <- byte G0(y) + g of the walker's packed sites
   // (one byte = one group of 8 sites), padding dwords zero
@@ -1024,7 +1058,7 @@ __host__ __device__ inline FusedLayout fused_layout(uint32_t R, uint32_t N, uint
                                                     uint32_t ntab) {
   FusedLayout f;
   f.thr = 0;
-  f.wat = f.thr + R * kClasses * 4u;
+  f.wat = f.thr + R * kClasses * 8u;
   f.sof = f.wat + R * 4u;
   f.E = f.sof + R * 4u;
   f.M = f.E + R * 4u;
@@ -1043,14 +1077,15 @@ __host__ __device__ inline FusedLayout fused_layout(uint32_t R, uint32_t N, uint
 
 // The LDS tables of the single-workgroup kernels (fused and wave plans).
 struct FusedTables {
-  uint32_t *thr, *wat, *sof, *xoff, *xD, *xatt, *xacc;
+  uint64_t *thr;
+  uint32_t *wat, *sof, *xoff, *xD, *xatt, *xacc;
   int32_t *E, *M, *xfs;
   uint64_t *xsat, *xtab;
 };
 
 __device__ __forceinline__ FusedTables fused_tables(uint8_t *smem, const FusedLayout &F) {
   FusedTables t;
-  t.thr = reinterpret_cast<uint32_t *>(smem + F.thr);
+  t.thr = reinterpret_cast<uint64_t *>(smem + F.thr);
   t.wat = reinterpret_cast<uint32_t *>(smem + F.wat);
   t.sof = reinterpret_cast<uint32_t *>(smem + F.sof);
   t.E = reinterpret_cast<int32_t *>(smem + F.E);
@@ -1071,7 +1106,7 @@ __device__ __forceinline__ FusedTables fused_tables(uint8_t *smem, const FusedLa
 __device__ __forceinline__ void fused_stage(const FusedArgs &a, const FusedTables &t, uint32_t tid,
                                             uint32_t nt) {
   const uint32_t R = a.geo.R;
-  for (uint32_t q = tid; q < R * kClasses; q += nt) t.thr[q] = a.st.flip_thr[q];
+  for (uint32_t q = tid; q < R * kClasses; q += nt) t.thr[q] = a.st.flip_cmp[q];
   for (uint32_t q = tid; q < R; q += nt) {
     t.wat[q] = a.st.walker_at[q];
     t.sof[q] = a.st.slot_of[q];
@@ -1140,7 +1175,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_fused(FusedArgs a) {
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const FusedLayout F = fused_layout(R, N, DIM, a.ntab);
   const FusedTables T = fused_tables(smem, F);
-  uint32_t *thr = T.thr, *sof = T.sof;
+  uint64_t *thr = T.thr;
+  uint32_t *sof = T.sof;
   int32_t *E = T.E, *M = T.M;
   uint32_t *sp = reinterpret_cast<uint32_t *>(smem + F.spins);   // [R][N/8] nibble dwords
   uint32_t *bx = reinterpret_cast<uint32_t *>(smem + F.bonds), *by = bx + (N >> 3), *bz = by + (N >> 3);
@@ -1348,7 +1384,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_wave(FusedArgs a) {
       u = xad(l, sw, u);
       u = xad(dn, sw, u);
       u = xad(up, sw, u);
-      sw = decide_n(sw, u, off, rc[c], tb, t);
+      sw = decide_n<true>(sw, u, off, rc[c], tb, t);
     }
     rc[0] = rn[0];
     rc[1] = rn[1];
@@ -1424,7 +1460,7 @@ struct PersistArgs {
 template <int DIM, int V>
 __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ uint32_t s_thr[kClasses];
+  __shared__ uint64_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
   __shared__ uint32_t s_slot, s_stop;
   const Geometry &G = a.geo;
@@ -1437,12 +1473,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
   uint32_t *bx = sp + (N >> 3), *by = bx + (N >> 3), *bz = by + (N >> 3);
   // every slot's thresholds stay in LDS, so a slot change never waits on memory;
   // the current slot's row is copied to a fixed LDS address for the lookups
-  uint32_t *thr = sp + (N >> 3) * (DIM == 3 ? 4u : 1u);
-  for (uint32_t q = tid; q < R * kClasses; q += nt) thr[q] = a.st.flip_thr[q];
+  uint64_t *thr = reinterpret_cast<uint64_t *>(sp + (N >> 3) * (DIM == 3 ? 4u : 1u));
+  for (uint32_t q = tid; q < R * kClasses; q += nt) thr[q] = a.st.flip_cmp[q];
 
   uint32_t slot = a.st.slot_of[w];
   int32_t E = a.st.E[w], M = a.st.M[w];
-  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+  if (tid < kClasses) s_thr[tid] = a.st.flip_cmp[slot * kClasses + tid];
   unpack_tile_n(sp, a.spins + (size_t)w * (N >> 5), 0u, N >> 5, 0xFFFFFFFFu, tid, nt);
   if (DIM == 3) unpack_tile_n(bx, a.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
   __syncthreads();
@@ -1605,7 +1641,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist(PersistArgs a) {
 template <int DIM, int V, int NPARTS>
 __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
-  __shared__ uint32_t s_thr[kClasses];
+  __shared__ uint64_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
   __shared__ uint32_t s_slot, s_stop;
   const Geometry &G = a.geo;
@@ -1624,15 +1660,21 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
   const uint32_t pdw = NP << lgPl;
   uint32_t *sp = reinterpret_cast<uint32_t *>(smem);
   uint32_t *bx = sp + pdw, *by = bx + pdw, *bz = by + pdw;  // 3D only
+  // every slot's table; 3D: 8-byte compare entries, 2D: 4-byte thresholds
+  // (the two forms of the decision, see decide_n)
+  constexpr bool WIDE = DIM == 3;
   uint32_t *thr = DIM == 3 ? bz + pdw : bx;
-  for (uint32_t q = tid; q < R * kClasses; q += nt) thr[q] = a.st.flip_thr[q];
+  uint32_t *s_tab = reinterpret_cast<uint32_t *>(s_thr); // the current slot's entries
+  constexpr uint32_t EW = WIDE ? 2u : 1u;                // dwords per entry
+  const uint32_t *src_tab = WIDE ? reinterpret_cast<const uint32_t *>(a.st.flip_cmp) : a.st.flip_thr;
+  for (uint32_t q = tid; q < R * kClasses * EW; q += nt) thr[q] = src_tab[q];
 
   uint32_t slot = a.st.slot_of[w];
   // this part's shares of the walker's E_int and M: part 0 starts from the
   // totals, each part adds the changes of its own sites
   int32_t Es = p ? 0 : a.st.E[w], Ms = p ? 0 : a.st.M[w];
   int32_t Et = a.st.E[w], Mt = a.st.M[w]; // walker totals after the last sweep
-  if (tid < kClasses) s_thr[tid] = a.st.flip_thr[slot * kClasses + tid];
+  if (tid < kClasses * EW) s_tab[tid] = src_tab[slot * kClasses * EW + tid];
   {
     // planes z0 - 2 .. z0 + Lp + 1, periodic
     const uint32_t f = ((z0 + L - 2u) & lmask) * wpp, cnt = NP * wpp, m = nwr - 1u;
@@ -1664,11 +1706,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
         for (int v = 0; v < V; ++v)
           r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
         if constexpr (DIM == 3)
-          span3d_n<V>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
-                      (y + 1u) & lmask, g0, gmask, off, r, s_thr, t);
+          span3d_n<V, WIDE>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
+                            (y + 1u) & lmask, g0, gmask, off, r, s_thr, t);
         else
-          span2d_n<V>(sp + (lp << lgPl), sp + ((lp - 1u) << lgPl), sp + ((lp + 1u) << lgPl), g0,
-                      gmask, off, r, s_thr, t);
+          span2d_n<V, WIDE>(sp + (lp << lgPl), sp + ((lp - 1u) << lgPl), sp + ((lp + 1u) << lgPl), g0,
+                            gmask, off, r, s_thr, t);
       }
       if (c == 0u) {
         // the inner halo planes (local 1 and Lp + 2), one group per item on
@@ -1686,11 +1728,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
           r[0] = philox(ctr, s, slot, kPurposeFlip, a.key.k0, a.key.k1);
           TallyN tl = {0u, 0u, 0u};
           if constexpr (DIM == 3)
-            span3d_n<1>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
-                        (y + 1u) & lmask, g0, gmask, off, r, s_thr, tl);
+            span3d_n<1, WIDE>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
+                              (y + 1u) & lmask, g0, gmask, off, r, s_thr, tl);
           else
-            span2d_n<1>(sp + (lp << lgPl), sp + ((lp - 1u) << lgPl), sp + ((lp + 1u) << lgPl), g0,
-                        gmask, off, r, s_thr, tl);
+            span2d_n<1, WIDE>(sp + (lp << lgPl), sp + ((lp - 1u) << lgPl), sp + ((lp + 1u) << lgPl), g0,
+                              gmask, off, r, s_thr, tl);
         }
       } else {
         // this wave's energy and magnetisation changes over the sweep, ready
@@ -1872,7 +1914,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
             }
             if (accept) {
               nslot = partner;
-              for (uint32_t q = 0; q < kClasses; ++q) s_thr[q] = thr[nslot * kClasses + q];
+              for (uint32_t q = 0; q < kClasses * EW; ++q) s_tab[q] = thr[nslot * kClasses * EW + q];
             }
           }
         }
@@ -2002,7 +2044,7 @@ struct BatchLayout {
 __host__ __device__ inline BatchLayout batch_layout(uint32_t W, uint32_t N, uint32_t dim) {
   BatchLayout b;
   b.thr = 0;
-  b.slot = b.thr + W * kClasses * 4u;
+  b.slot = b.thr + W * kClasses * 8u;
   b.E = b.slot + W * 4u;
   b.M = b.E + W * 4u;
   b.acc = b.M + W * 4u;
@@ -2033,7 +2075,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_sweep(const BatchInst *in
   const uint32_t nw = min(W, R - it.w0);
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const BatchLayout B = batch_layout(W, N, DIM);
-  uint32_t *thr = reinterpret_cast<uint32_t *>(smem + B.thr);
+  uint64_t *thr = reinterpret_cast<uint64_t *>(smem + B.thr);
   uint32_t *slot = reinterpret_cast<uint32_t *>(smem + B.slot);
   int32_t *E = reinterpret_cast<int32_t *>(smem + B.E);
   int32_t *M = reinterpret_cast<int32_t *>(smem + B.M);
@@ -2050,7 +2092,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_batch_sweep(const BatchInst *in
   }
   __syncthreads();
   for (uint32_t q = tid; q < nw * kClasses; q += nt)
-    thr[q] = I.st.flip_thr[slot[q / kClasses] * kClasses + (q % kClasses)];
+    thr[q] = I.st.flip_cmp[slot[q / kClasses] * kClasses + (q % kClasses)];
   unpack_tile_n(sp, I.st.spins[0] + (size_t)it.w0 * (N >> 5), 0u, (nw * N) >> 5, 0xFFFFFFFFu, tid, nt);
   if (DIM == 3) unpack_tile_n(bx, I.st.bonds, 0u, (3u * N) >> 5, 0xFFFFFFFFu, tid, nt);
   __syncthreads();
@@ -2473,10 +2515,10 @@ size_t persist_lds_bytes(const Geometry &g, uint32_t parts) {
     // slot's thresholds; at least 96 KB, so that one part holds a compute
     // unit alone (all parts of a walker must advance at the same rate)
     const size_t need = (size_t)(g.L / parts + 4u) * g.plane / 2u * (g.dim == 3 ? 4u : 1u) +
-                        (size_t)g.R * kClasses * 4u;
+                        (size_t)g.R * kClasses * 8u;
     return std::max<size_t>(need, 96u * 1024u);
   }
-  return (size_t)g.N / 2u * (g.dim == 3 ? 4u : 1u) + (size_t)g.R * kClasses * 4u; // four bits per site
+  return (size_t)g.N / 2u * (g.dim == 3 ? 4u : 1u) + (size_t)g.R * kClasses * 8u; // four bits per site
 }
 
 uint32_t persist_max_workgroups(const Geometry &g, uint32_t threads, uint32_t parts) {

@@ -45,13 +45,19 @@ HBM_PEAK_TBPS = 8.0
 # kernels issue ~17.5 per attempt in all; the counters give the exact figure).
 PHILOX_VALU_PER_BLOCK = 37
 SLOTS_PER_ATTEMPT = PHILOX_VALU_PER_BLOCK / 4 + 1
-# LDS bytes one attempt moves in the dominant kernels (loads and stores per item,
-# counted from the code): 2D span of 8 nibble dwords (32 attempts): the row, the
-# rows above and below (32 B each), one edge dword, 32 threshold reads, the
-# store (32 B) = 260 B; 3D span of 4 dwords (16 attempts): spins and x bonds
-# (16 B each), edge spin and bond, rows y -+ 1 and their y bonds, planes z -+ 1
-# and their z bonds (8 x 16 B), 16 threshold reads, the store = 248 B.
-LDS_BYTES_PER_ATTEMPT = {2: 260 / 32, 3: 248 / 16}
+# LDS bytes one attempt moves in the main kernels (loads and stores per item,
+# counted from the code).  2D span of 8 nibble dwords (32 attempts): the row,
+# the rows above and below (32 B each), one edge dword, 32 table reads, the
+# store (32 B): 260 B with 4-byte thresholds (the 2D split kernel), 388 B with
+# the 8-byte compare entries (tiled kernels).  Phased span of 4 dwords (16
+# attempts): the row (16 B), 5 dwords of each neighbour row, an edge dword, 16
+# 8-byte entries, the store: 204 B.  3D span of 4 dwords (16 attempts): spins
+# and x bonds (16 B each), edge spin and bond, rows y -+ 1 and their y bonds,
+# planes z -+ 1 and their z bonds (8 x 16 B), 16 8-byte entries, the store:
+# 312 B.
+LDS_BYTES_PER_ATTEMPT = {"k_persist_split/2": 260 / 32, "k_tiled_n/2": 388 / 32,
+                         "k_phased/2": 204 / 16, "k_persist_split/3": 312 / 16,
+                         "k_tiled/3": 312 / 16, "k_persist/2": 388 / 32, "k_persist/3": 312 / 16}
 
 
 def parse():
@@ -672,12 +678,15 @@ def main():
     if w.dim == 3:
         hbm_bytes += 3 * w.sites / 8 * (tiles if tiles > 1 else 1)  # packed couplings, read once per tile
     split = plan["mode"] == pt.PT_PLAN_PERSISTENT and plan["tile_planes"] < w.L
-    kernel = {pt.PT_PLAN_TILED: "k_tiled_n" if w.dim == 2 else "k_tiled", pt.PT_PLAN_FUSED: "k_fused",
+    phased = w.dim == 2 and (w.L & (w.L - 1) or w.L < 8)  # sides that are not powers of two
+    kernel = {pt.PT_PLAN_TILED: ("k_phased" if phased else "k_tiled_n") if w.dim == 2 else "k_tiled",
+              pt.PT_PLAN_FUSED: "k_fused",
               pt.PT_PLAN_PERSISTENT: "k_persist_split" if split else "k_persist",
               pt.PT_PLAN_LANES: "k_lanes", pt.PT_PLAN_WAVE: "k_wave"}[plan["mode"]]
     traffic = measured_traffic(kernel, w.name, plan, per_launch)
     valu_insts = measured_valu_insts(kernel, w.name, plan, per_launch)
-    lds_bytes = LDS_BYTES_PER_ATTEMPT[w.dim] * attempts_launch
+    lds_per = LDS_BYTES_PER_ATTEMPT.get("%s/%d" % (kernel, w.dim))
+    lds_bytes = lds_per * attempts_launch if lds_per else None
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2),
                 "unit": "Tops/s (int32 VALU lane slots)", "frac": round(achieved / VALU_PEAK_TOPS, 4),
                 "traffic": traffic, "kernel": kernel,
@@ -691,8 +700,8 @@ def main():
                                            if valu_insts else None),
                 "issue_frac": (round(valu_insts * 64 / launch_s / 1e12 / VALU_PEAK_TOPS, 4)
                                if valu_insts else None),
-                "lds_bytes_per_attempt": LDS_BYTES_PER_ATTEMPT[w.dim],
-                "lds_frac": round(lds_bytes / launch_s / 1e12 / LDS_PEAK_TBPS, 4),
+                "lds_bytes_per_attempt": lds_per,
+                "lds_frac": round(lds_bytes / launch_s / 1e12 / LDS_PEAK_TBPS, 4) if lds_bytes else None,
                 "hbm_frac": (round(traffic / launch_s / 1e12 / HBM_PEAK_TBPS, 5) if traffic else None),
                 "hbm_algorithmic_bytes_per_launch": int(hbm_bytes),
                 "hbm_algorithmic_GBps": round(hbm_bytes / launch_s / 1e9, 1)}

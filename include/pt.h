@@ -56,7 +56,7 @@ extern "C" {
 
 #define PT_ABI_VERSION 1u
 #define PT_ALL_SLOTS 0xFFFFFFFFu
-#define PT_MAX_SWEEPS_PER_LAUNCH 8u
+#define PT_MAX_SWEEPS_PER_LAUNCH 16u
 
 typedef enum {
   PT_OK = 0,

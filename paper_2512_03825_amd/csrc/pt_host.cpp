@@ -53,6 +53,7 @@ namespace {
 bool is_pow2(uint32_t v) { return v && !(v & (v - 1u)); }
 
 static_assert(kStaticScratchBytes == PT_STATIC_SCRATCH_BYTES, "scratch array size and its ABI constant differ");
+static_assert(kMaxSweepsPerLaunch == PT_MAX_SWEEPS_PER_LAUNCH, "sweeps per launch and its ABI constant differ");
 
 constexpr uint32_t kMaxR = 4096;
 constexpr uint32_t kFusedChunk = 4096;   // sweeps per fused or persistent launch

@@ -15,7 +15,7 @@ constexpr uint32_t kPurposeBond = 3u << 8;
 
 constexpr uint32_t kClasses = 16;      // flip-threshold classes per slot: 8*b + u
 constexpr uint32_t kFieldDigits = 32;  // binary digits of |dM|/2 with a field swap factor
-constexpr uint32_t kMaxSweepsPerLaunch = 8;
+constexpr uint32_t kMaxSweepsPerLaunch = 16;
 constexpr uint32_t kMaxParts = 8;            // workgroups per walker of the split persistent plan
 // Size of the library's fixed per-GPU scratch array (contexts of pt_create_static).
 constexpr size_t kStaticScratchBytes = (size_t)4u << 20;

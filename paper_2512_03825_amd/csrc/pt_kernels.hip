@@ -421,9 +421,12 @@ __device__ __forceinline__ uint32_t carry_mask(uint32_t r, uint64_t c) {
 //   else: 4-byte thresholds T, tested by r <= T (half the LDS bytes; measured
 //         faster in the 2D split kernel, whose 16 waves per compute unit hide
 //         less LDS latency than the tiled, phased and 3D kernels' 24).
+// vm: nibbles that are sites (low bit of each nibble set); padding nibbles
+// never flip.
 template <bool WIDE>
 __device__ __forceinline__ uint32_t decide_n(uint32_t w, uint32_t u, uint32_t off, const Words &r,
-                                             const uint8_t *tb, TallyN &t) {
+                                             const uint8_t *tb, TallyN &t,
+                                             uint32_t vm = 0xFFFFFFFFu) {
   const uint32_t M = off ? 0xF0F0F0F0u : 0x0F0F0F0Fu;   // colour nibbles
   const uint32_t cls = ((w << 3) | u) & M;              // 8b + u in each colour nibble
   uint32_t f;
@@ -438,7 +441,7 @@ __device__ __forceinline__ uint32_t decide_n(uint32_t w, uint32_t u, uint32_t of
     // into bytes 0..3, then the colour nibbles' low bits kept
     const uint32_t a01 = __builtin_amdgcn_perm(carry_mask(r.y, t1), carry_mask(r.x, t0), 0x0C0C0400u);
     const uint32_t a23 = __builtin_amdgcn_perm(carry_mask(r.w, t3), carry_mask(r.z, t2), 0x04000C0Cu);
-    f = __builtin_amdgcn_bitop3_b32(a01, a23, 0x01010101u << (4u * off), 0xA8); // (a | b) & c
+    f = __builtin_amdgcn_bitop3_b32(a01, a23, (0x01010101u << (4u * off)) & vm, 0xA8); // (a | b) & c
   } else {
     const uint32_t rot = off ? 2u : 30u;                // class * 4 to bits 8m .. 8m+5
     const uint32_t b0 = 1u << (4u * off);
@@ -447,8 +450,8 @@ __device__ __forceinline__ uint32_t decide_n(uint32_t w, uint32_t u, uint32_t of
     const uint32_t t1 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 8u, 6u));
     const uint32_t t2 = *reinterpret_cast<const uint32_t *>(tb + __builtin_amdgcn_ubfe(c4, 16u, 6u));
     const uint32_t t3 = *reinterpret_cast<const uint32_t *>(tb + (c4 >> 24));
-    f = (r.x <= t0 ? b0 : 0u) | (r.y <= t1 ? (b0 << 8) : 0u) | (r.z <= t2 ? (b0 << 16) : 0u) |
-        (r.w <= t3 ? (b0 << 24) : 0u);
+    f = ((r.x <= t0 ? b0 : 0u) | (r.y <= t1 ? (b0 << 8) : 0u) | (r.z <= t2 ? (b0 << 16) : 0u) |
+         (r.w <= t3 ? (b0 << 24) : 0u)) & vm;
   }
   t.n += __builtin_popcount(f);
   t.sb = __builtin_amdgcn_udot8(w, f, t.sb, false);
@@ -912,6 +915,79 @@ __device__ __forceinline__ void edge_phased(uint32_t *lds, uint32_t base, uint32
   row[g] = w ^ f;
 }
 
+// Edge item of a row whose two ends lie in different dwords (at least two
+// groups per row): dword g is the row's first (g = 0, x = 0 at nibble ph), one
+// between the interior spans and the last (all nibbles sites), the last (g =
+// pl >> 3 with pl = ph + L - 1, x = L - 1 at nibble pl & 7) or past it (all
+// padding).  The periodic wrap is one nibble patched into the left view of the
+// first dword or the right view of the last; padding nibbles are masked out
+// of the decision.  The same instructions serve every kind, selected per lane.
+__device__ __forceinline__ void edge_phased_2(uint32_t *lds, uint32_t base, uint32_t g, uint32_t ph,
+                                              uint32_t pl, uint32_t vu, uint32_t shu, uint32_t vd,
+                                              uint32_t shd, uint32_t off, const Words &r,
+                                              const uint64_t *thr, TallyN &t) {
+  uint32_t *row = lds + base;
+  const uint32_t w = row[g];
+  uint32_t l = __builtin_amdgcn_alignbit(w, row[(int)g - 1], 28u); // g = 0: the dword before the row
+  uint32_t rr = __builtin_amdgcn_alignbit(row[g + 1u], w, 4u);
+  const uint32_t gl = pl >> 3;
+  const bool first = g == 0u, last = g == gl;
+  // x = 0's left neighbour is x = L - 1 (nibble pl), x = L - 1's right one x = 0 (nibble ph)
+  const uint32_t src = first ? pl : ph;
+  const uint32_t xv = (row[src >> 3] >> (4u * (src & 7u))) & 0xFu;
+  const uint32_t sh = 4u * (first ? ph : (pl & 7u));
+  const uint32_t pm = (first || last) ? (0xFu << sh) : 0u;
+  const uint32_t x = (pm & (xv << sh)) | (~pm & (first ? l : rr));
+  l = first ? x : l;
+  rr = first ? rr : x;
+  const uint32_t vm = first ? (0x11111111u << (4u * ph))
+                    : g < gl ? 0x11111111u
+                    : last   ? (0x11111111u >> (28u - 4u * (pl & 7u)))
+                             : 0u;
+  const uint32_t up = __builtin_amdgcn_alignbit(lds[vu + g + 1u], lds[vu + g], shu);
+  const uint32_t dn = __builtin_amdgcn_alignbit(lds[vd + g + 1u], lds[vd + g], shd);
+  uint32_t u = rr ^ w;
+  u = xad(l, w, u);
+  u = xad(dn, w, u);
+  u = xad(up, w, u);
+  row[g] = decide_n<true>(w, u, off, r, reinterpret_cast<const uint8_t *>(thr), t, vm);
+}
+
+// The first and last dwords of a row whose ends lie in different dwords, as
+// one item: x = 0 (nibble ph of dword 0) and x = L - 1 (nibble pl & 7 of dword
+// gl = pl >> 3) are each other's periodic neighbours, so each patches the
+// other's view straight from registers.
+__device__ __forceinline__ void edge_pair_phased(uint32_t *lds, uint32_t base, uint32_t gl,
+                                                 uint32_t ph, uint32_t pl, uint32_t vu, uint32_t shu,
+                                                 uint32_t vd, uint32_t shd, uint32_t off,
+                                                 const Words &r0, const Words &rl,
+                                                 const uint64_t *thr, TallyN &t) {
+  uint32_t *row = lds + base;
+  const uint32_t w0 = row[0], wl = row[gl];
+  uint32_t l0 = __builtin_amdgcn_alignbit(w0, row[-1], 28u); // the dword before the row: padding
+  const uint32_t r0v = __builtin_amdgcn_alignbit(row[1], w0, 4u);
+  const uint32_t ll = __builtin_amdgcn_alignbit(wl, row[gl - 1u], 28u);
+  uint32_t rlv = __builtin_amdgcn_alignbit(row[gl + 1u], wl, 4u);
+  const uint32_t s0 = 4u * ph, sl = 4u * (pl & 7u);
+  l0 = (l0 & ~(0xFu << s0)) | (((wl >> sl) & 0xFu) << s0);
+  rlv = (rlv & ~(0xFu << sl)) | (((w0 >> s0) & 0xFu) << sl);
+  const uint32_t up0 = __builtin_amdgcn_alignbit(lds[vu + 1u], lds[vu], shu);
+  const uint32_t dn0 = __builtin_amdgcn_alignbit(lds[vd + 1u], lds[vd], shd);
+  const uint32_t upl = __builtin_amdgcn_alignbit(lds[vu + gl + 1u], lds[vu + gl], shu);
+  const uint32_t dnl = __builtin_amdgcn_alignbit(lds[vd + gl + 1u], lds[vd + gl], shd);
+  uint32_t u0 = r0v ^ w0;
+  u0 = xad(l0, w0, u0);
+  u0 = xad(dn0, w0, u0);
+  u0 = xad(up0, w0, u0);
+  uint32_t ul = rlv ^ wl;
+  ul = xad(ll, wl, ul);
+  ul = xad(dnl, wl, ul);
+  ul = xad(upl, wl, ul);
+  const uint8_t *tb = reinterpret_cast<const uint8_t *>(thr);
+  row[0] = decide_n<true>(w0, u0, off, r0, tb, t, 0x11111111u << s0);
+  row[gl] = decide_n<true>(wl, ul, off, rl, tb, t, 0x11111111u >> (28u - sl));
+}
+
 // Whole-replica sweep of phased rows: grid (1, R), one workgroup per walker.
 template <int V>
 __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
@@ -929,25 +1005,44 @@ __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
   if (tid < kClasses) s_thr[tid] = a.st.flip_cmp[slot * kClasses + tid];
 
   // stage: LDS dword (y, g) <- byte G0(y) + g of the walker's packed sites
-  // (one byte = one group of 8 sites), padding dwords zero
+  // (one byte = one group of 8 sites), padding dwords zero.  Each thread steps
+  // through (y, g) by nt dwords at a time (no divisions in the loop) and
+  // issues four loads before it spreads any of them.
   {
     const uint8_t *src = reinterpret_cast<const uint8_t *>(a.src + (size_t)w * nwr);
-    const uint32_t nbytes = 4u * nwr, total = kPhasedLead + L * S + 4u;
-    for (uint32_t q = tid; q < total; q += nt) {
-      uint32_t v = 0u;
-      if (q >= kPhasedLead && q < kPhasedLead + L * S) {
-        const uint32_t y = (q - kPhasedLead) / S, g = (q - kPhasedLead) - y * S;
+    const uint32_t nbytes = 4u * nwr, Gmax = pa.Gmax;
+    if (tid < kPhasedLead) lds[tid] = 0u;
+    if (tid < 4u) lds[kPhasedLead + L * S + tid] = 0u;
+    const uint32_t sy = nt / S, sg = nt - sy * S;
+    uint32_t y = tid / S, g = tid - y * S;
+    while (y < L) {
+      constexpr int kBatch = 4;
+      uint32_t q[kBatch], b[kBatch];
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j) {
         const uint32_t byte = ((y * L) >> 3) + g;
-        if (g < pa.Gmax && byte < nbytes) v = spread8(src[byte]);
+        q[j] = y < L ? kPhasedLead + y * S + g : 0xFFFFFFFFu;
+        b[j] = (y < L && g < Gmax && byte < nbytes) ? src[byte] : 0u;
+        g += sg;
+        y += sy;
+        if (g >= S) {
+          g -= S;
+          ++y;
+        }
       }
-      lds[q] = v;
+#pragma unroll
+      for (int j = 0; j < kBatch; ++j)
+        if (q[j] != 0xFFFFFFFFu) lds[q[j]] = spread8(b[j]);
     }
-    for (uint32_t y = tid; y < L; y += nt) rows[y] = phased_row_info(y, L, S);
+    for (uint32_t yy = tid; yy < L; yy += nt) rows[yy] = phased_row_info(yy, L, S);
   }
   __syncthreads();
 
   // each thread's first items, stepped by nt items per round without divisions
-  const uint32_t nI = pa.nI, nE = pa.nE;
+  const uint32_t nI = pa.nI;
+  // edge items per row: with at least 6 groups per row (V > 1) the row's first
+  // and last dwords are one item, the other edge dwords one item each
+  const uint32_t nE = V > 1 ? pa.nE - 1u : pa.nE;
   const uint32_t iy0 = nI ? tid / nI : L, ik0 = nI ? tid - iy0 * nI : 0u; // no interior spans: skip
   const uint32_t idy = nI ? nt / nI : 0u, idk = nI ? nt - idy * nI : 0u;
   const uint32_t ey0 = tid / nE, ek0 = tid - ey0 * nE;
@@ -977,10 +1072,25 @@ __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
     for (uint32_t y = ey0, k = ek0; y < L;) {
       const uint4 ri = rows[y];
       const uint32_t base = ri.y & 0xFFFFu, shu = (ri.y >> 16) & 31u, shd = (ri.y >> 21) & 31u;
-      const uint32_t ph = ri.y >> 26;
-      const uint32_t g = k ? nI * V + k : 0u, off = (c + y) & 1u;
-      const Words r = philox(ri.x + g, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
-      edge_phased(lds, base, g, ph, L, ri.z, shu, ri.w, shd, off, r, s_thr, t);
+      const uint32_t ph = ri.y >> 26, off = (c + y) & 1u;
+      if constexpr (V > 1) {
+        // at least 6 groups per row: the two ends lie in different dwords
+        const uint32_t pl = ph + L - 1u, gl = pl >> 3;
+        if (k == 0u) {
+          const Words r0 = philox(ri.x, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+          const Words rl = philox(ri.x + gl, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+          edge_pair_phased(lds, base, gl, ph, pl, ri.z, shu, ri.w, shd, off, r0, rl, s_thr, t);
+        } else {
+          uint32_t g = nI * V + k; // the other edge dwords, the last one skipped
+          g += g >= gl ? 1u : 0u;
+          const Words r = philox(ri.x + g, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+          edge_phased_2(lds, base, g, ph, pl, ri.z, shu, ri.w, shd, off, r, s_thr, t);
+        }
+      } else {
+        const uint32_t g = k ? nI * V + k : 0u;
+        const Words r = philox(ri.x + g, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+        edge_phased(lds, base, g, ph, L, ri.z, shu, ri.w, shd, off, r, s_thr, t);
+      }
       k += edk;
       y += edy;
       if (k >= nE) {
@@ -1643,7 +1753,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint64_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
-  __shared__ uint32_t s_slot, s_stop;
+  __shared__ uint32_t s_slot, s_stop, s_ready;
   const Geometry &G = a.geo;
   const uint32_t R = G.R, L = G.L, lgL = a.lg_L, lmask = L - 1u;
   const uint32_t lgG = lgL - 3u, gmask = (1u << lgG) - 1u;  // nibble dwords per row
@@ -1689,244 +1799,294 @@ __global__ __launch_bounds__(kMaxThreads) void k_persist_split(PersistArgs a) {
 
   const uint32_t smask = (1u << a.lg_spr) - 1u;
   uint32_t rec = a.sch.rec_base, e = a.sch.ex_step;
+  // Own-plane item q of colour c in sweep s: V groups of plane 2 + (q >> lg_ipp).
+  auto own_item = [&](uint32_t q, uint32_t s, uint32_t c, TallyN &t) {
+    const uint32_t lp = 2u + (q >> a.lg_ipp);
+    const uint32_t g0 = (q & smask) * V;
+    const uint32_t y = DIM == 3 ? (q >> a.lg_spr) & lmask : 0u;
+    const uint32_t z = (z0 + lp + L - 2u) & lmask; // global plane
+    const uint32_t off = (c + lp + y) & 1u;         // z0 is even
+    const uint32_t ctr0 = DIM == 3 ? (((z << lgL) + y) << lgG) + g0 : (z << lgG) + g0;
+    Words r[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
+    if constexpr (DIM == 3)
+      span3d_n<V, WIDE>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
+                        (y + 1u) & lmask, g0, gmask, off, r, s_thr, t);
+    else
+      span2d_n<V, WIDE>(sp + (lp << lgPl), sp + ((lp - 1u) << lgPl), sp + ((lp + 1u) << lgPl), g0,
+                        gmask, off, r, s_thr, t);
+  };
+  // The end of sweep s for wave 0 (tid < 64): post this part's boundary planes
+  // and shares, wait for the neighbours' and (exchange step) the partner's,
+  // receive the halo planes, record, decide.  Leaves s_slot and s_stop.
+  auto handshake = [&](uint32_t s, bool do_rec, bool do_ex, uint32_t rec_i) {
+    for (uint32_t v = 0; v < (nt >> 6); ++v) {
+      Es += s_red[v][0];
+      Ms += s_red[v][1];
+    }
+    const uint64_t hi = 0xFFFFFFFF00000000ull;
+    const uint64_t tag = (uint64_t)(s + 1u) << 32, etag = (uint64_t)(e + 1u) << 32;
+    // the posts of this sweep's generation for walker w, one per part
+    uint64_t *posts = a.st.halo + ((size_t)(s & 1u) * R + w) * P * npost;
+    uint64_t *mine = posts + (size_t)p * npost;
+    uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * 2u * P * R; // [slot][part][E, M]
+    // post: words [0, 2 wpp) = own planes 2, 3; [2 wpp, 4 wpp) = planes Lp, Lp + 1
+    for (uint32_t q = tid; q < nb; q += 64u) {
+      const bool lo = q < 2u * wpp;
+      const uint4 x = reinterpret_cast<const uint4 *>(sp + ((lo ? 2u : Lp) << lgPl))[lo ? q : q - 2u * wpp];
+      const uint32_t word =
+          gather8(x.x) | (gather8(x.y) << 8) | (gather8(x.z) << 16) | (gather8(x.w) << 24);
+      __hip_atomic_store(mine + q, tag | word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    uint32_t partner = 0xFFFFFFFFu;
+    if (do_ex) {
+      const uint32_t par = e & 1u;
+      if ((slot & 1u) == par && slot + 1u < R) partner = slot + 1u;
+      else if ((slot & 1u) != par && slot >= 1u) partner = slot - 1u;
+    }
+    if (tid == 0u) {
+      if (do_ex) {
+        __hip_atomic_store(&mb[2u * (P * slot + p)], etag | (uint32_t)Es, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        if constexpr (DIM == 2) // M for the field factor (2D only)
+          __hip_atomic_store(&mb[2u * (P * slot + p) + 1u], etag | (uint32_t)Ms, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __hip_atomic_store(mine + nb, tag | (uint32_t)Es, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(mine + nb + 1u, tag | (uint32_t)Ms, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // everything of the swap test that does not need the energies, before waiting
+    uint32_t lo = 0u, rr = 0u;
+    int32_t sg = 0;
+    PairRow row{0, 0u, 0u, 0u};
+    if (tid == 0u && partner != 0xFFFFFFFFu) {
+      lo = min(slot, partner);
+      rr = philox(lo, e, 0u, kPurposeSwap, a.key.k0, a.key.k1).x;
+      row = pair_row(a.st, lo);
+      if constexpr (DIM == 2) sg = a.st.field_sign[lo];
+    }
+    // Word q of what this part reads: the lower boundary planes of the part
+    // above (q < 2 wpp, its post words q), the upper ones of the part below
+    // (2 wpp <= q < 4 wpp), then the E_int and M shares of the other parts.
+    uint32_t src[kSplitWordsPerLane]; // word offsets from posts
+    uint32_t pend = 0u;
+#pragma unroll
+    for (uint32_t k = 0; k < kSplitWordsPerLane; ++k) {
+      const uint32_t q = min(tid + 64u * k, nread - 1u);
+      if (tid + 64u * k < nread) pend |= 1u << k;
+      if (q < 2u * wpp) src[k] = pup * npost + q;
+      else if (q < nb) src[k] = pdn * npost + q;
+      else {
+        const uint32_t i = q - nb;
+        src[k] = ((p + 1u + (i >> 1)) & (P - 1u)) * npost + nb + (i & 1u);
+      }
+    }
+    // wait for those and, at an exchange step, the partner slot's E and M shares.
+    // Every round issues all of a lane's loads before testing any (one memory
+    // round trip per round); a word is consumed when its tag arrives and
+    // cannot change again before this part has posted its next sweep, so
+    // reloading a consumed word is harmless (loading only the words still
+    // pending was measured 0.7% slower: the masked loads cost more than the
+    // re-read words, which are a few MB per launch beside 8 TB/s).
+    // lane k < 2P reads word k of the partner slot's posts (E and M shares by
+    // part); in 3D, without a field, lane k < P reads part k's E share only
+    constexpr uint32_t NW = DIM == 2 ? 2u * P : P;
+    uint32_t ppend = (partner != 0xFFFFFFFFu && tid < NW) ? 1u : 0u;
+    const uint32_t pw = DIM == 2 ? (tid & (2u * P - 1u)) : 2u * (tid & (P - 1u));
+    const uint64_t *pmb = &mb[2u * P * (partner != 0xFFFFFFFFu ? partner : slot) + pw];
+    int32_t sE = 0, sM = 0, pE = 0;
+    uint32_t stop = 0u;
+    for (uint32_t n = 0;; ++n) {
+      uint64_t v[kSplitWordsPerLane];
+#pragma unroll
+      for (uint32_t k = 0; k < kSplitWordsPerLane; ++k)
+        v[k] = __hip_atomic_load(posts + src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint64_t pv = __hip_atomic_load(pmb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t ab =
+          __hip_atomic_load(&a.st.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+      for (uint32_t k = 0; k < kSplitWordsPerLane; ++k) {
+        if (!((pend >> k) & 1u) || (v[k] & hi) != tag) continue;
+        pend &= ~(1u << k);
+        const uint32_t q = tid + 64u * k, x = (uint32_t)v[k];
+        if (q < nb) {
+          // the part above's lowest planes are this part's upper halo, the
+          // part below's highest planes the lower halo
+          const bool lo = q < 2u * wpp;
+          reinterpret_cast<uint4 *>(sp + (lo ? ((Lp + 2u) << lgPl) : 0u))[lo ? q : q - 2u * wpp] =
+              make_uint4(spread8(x & 0xFFu), spread8(__builtin_amdgcn_ubfe(x, 8u, 8u)),
+                         spread8(__builtin_amdgcn_ubfe(x, 16u, 8u)), spread8(x >> 24));
+        } else if (((q - nb) & 1u) == 0u) {
+          sE += (int32_t)x;
+        } else {
+          sM += (int32_t)x;
+        }
+      }
+      if (ppend && (pv & hi) == etag) {
+        ppend = 0u;
+        pE = (int32_t)(uint32_t)pv;
+      }
+      // the bound and the abort flag first: a limit of 0 gives up at once
+      if (n >= a.spin_limit || __any(ab != 0u)) {
+        if (tid == 0u)
+          __hip_atomic_store(&a.st.counter[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        stop = 1u;
+        break;
+      }
+      if (!__any((pend | ppend) != 0u)) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    {
+      // the other parts' shares arrived in lanes sl .. sl + 2(P-1) - 1 of
+      // one load round (E at even offsets, M at odd; the launch checks that
+      // they do not wrap past lane 63): read them directly
+      const int sl = (int)(nb & 63u);
+      int32_t tE = 0, tM = 0;
+#pragma unroll
+      for (uint32_t i = 0; i + 1u < P; ++i) {
+        tE += __shfl(sE, sl + 2 * (int)i, 64);
+        tM += __shfl(sM, sl + 2 * (int)i + 1, 64);
+      }
+      sE = tE;
+      sM = tM;
+    }
+    // the partner slot's P shares of E (even lanes 0 .. 2P-2) and of M (odd
+    // lanes): independent reads
+    int32_t Ep = 0, Mp = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < P; ++k) {
+      if constexpr (DIM == 2) {
+        Ep += __shfl(pE, (int)(2u * k), 64);
+        Mp += __shfl(pE, (int)(2u * k + 1u), 64);
+      } else {
+        Ep += __shfl(pE, (int)k, 64);
+      }
+    }
+    if (tid == 0u) {
+      Et = Es + sE;
+      Mt = Ms + sM;
+      uint32_t nslot = slot;
+      if (!stop) {
+        if (do_rec && p == 0u) {
+          a.st.E_series[(size_t)rec_i * R + slot] = Et;
+          a.st.M_series[(size_t)rec_i * R + slot] = Mt;
+        }
+        if (partner != 0xFFFFFFFFu) {
+          const int32_t Elo = (slot == lo) ? Et : Ep, Ehi = (slot == lo) ? Ep : Et;
+          const int32_t Mlo = (slot == lo) ? Mt : Mp, Mhi = (slot == lo) ? Mp : Mt;
+          bool accept = (uint64_t)rr < pair_T(row, a.st.swap_tab, a.st.swap_n, Elo - Ehi);
+          if constexpr (DIM == 2)
+            accept = accept && field_factor(a.st, sg, lo, e, Mlo - Mhi, a.key.k0, a.key.k1);
+          if (slot == lo && p == 0u) {
+            atomicAdd(&a.st.att[lo], 1u);
+            if (accept) atomicAdd(&a.st.acc[lo], 1u);
+          }
+          if (accept) {
+            nslot = partner;
+            for (uint32_t q = 0; q < kClasses * EW; ++q) s_tab[q] = thr[nslot * kClasses * EW + q];
+          }
+        }
+      }
+      s_slot = nslot;
+      s_stop = stop;
+    }
+  };
+
+  // After a sweep that ends without an exchange step the handshake is not
+  // waited for: the next sweep's colour-0 pass starts at once on the planes
+  // that neither the post reads nor the halo feeds (4 .. Lp - 1) while wave 0
+  // posts and waits, and the other planes follow once wave 0 has received the
+  // halo (s_ready).  After an exchange step the next sweep needs the decision
+  // (its slot, its draws), so every wave waits for the handshake as before.
+  if (tid == 0u) s_ready = 0xFFFFFFFFu;
+  __syncthreads();
+  bool pending = false;
+  uint32_t ps = 0u, prec = 0u;
+  bool prec_do = false;
+  const uint32_t ipp = 1u << a.lg_ipp;
   for (uint32_t j = 0; j < a.sch.nsw; ++j) {
     const uint32_t s = a.sch.s0 + j;
     TallyN t = {0u, 0u, 0u};
-    for (uint32_t c = 0; c < 2u; ++c) {
-      // own planes 2 .. Lp + 1, V groups per item
-      for (uint32_t q = tid; q < (Lp << a.lg_ipp); q += nt) {
-        const uint32_t lp = 2u + (q >> a.lg_ipp);
-        const uint32_t g0 = (q & smask) * V;
-        const uint32_t y = DIM == 3 ? (q >> a.lg_spr) & lmask : 0u;
-        const uint32_t z = (z0 + lp + L - 2u) & lmask; // global plane
-        const uint32_t off = (c + lp + y) & 1u;         // z0 is even
-        const uint32_t ctr0 = DIM == 3 ? (((z << lgL) + y) << lgG) + g0 : (z << lgG) + g0;
-        Words r[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-          r[v] = philox(ctr0 + v, s, slot, c | kPurposeFlip, a.key.k0, a.key.k1);
-        if constexpr (DIM == 3)
-          span3d_n<V, WIDE>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
-                            (y + 1u) & lmask, g0, gmask, off, r, s_thr, t);
-        else
-          span2d_n<V, WIDE>(sp + (lp << lgPl), sp + ((lp - 1u) << lgPl), sp + ((lp + 1u) << lgPl), g0,
-                            gmask, off, r, s_thr, t);
+    // colour 0: own planes 2 .. Lp + 1, V groups per item
+    if (pending) {
+      if (tid < 64u) {
+        handshake(ps, prec_do, false, prec);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup"); // the halo planes, before the flag
+        if (tid == 0u) __hip_atomic_store(&s_ready, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
-      if (c == 0u) {
-        // the inner halo planes (local 1 and Lp + 2), one group per item on
-        // the first waves: one such wave per SIMD keeps the pass balanced.
-        // Their flips are their owners' to count.
-        const uint32_t gpp = 1u << lgPl; // groups per plane
-        for (uint32_t q = tid; q < 2u * gpp; q += nt) {
-          const uint32_t lp = q < gpp ? 1u : Lp + 2u;
-          const uint32_t g0 = q & gmask;
-          const uint32_t y = DIM == 3 ? (q >> lgG) & lmask : 0u;
-          const uint32_t z = (z0 + lp + L - 2u) & lmask;
-          const uint32_t off = (lp + y) & 1u;
-          const uint32_t ctr = DIM == 3 ? (((z << lgL) + y) << lgG) + g0 : (z << lgG) + g0;
-          Words r[1];
-          r[0] = philox(ctr, s, slot, kPurposeFlip, a.key.k0, a.key.k1);
-          TallyN tl = {0u, 0u, 0u};
-          if constexpr (DIM == 3)
-            span3d_n<1, WIDE>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
-                              (y + 1u) & lmask, g0, gmask, off, r, s_thr, tl);
-          else
-            span2d_n<1, WIDE>(sp + (lp << lgPl), sp + ((lp - 1u) << lgPl), sp + ((lp + 1u) << lgPl), g0,
-                              gmask, off, r, s_thr, tl);
-        }
-      } else {
-        // this wave's energy and magnetisation changes over the sweep, ready
-        // at the barrier that ends the sweep
-        int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb), dM = 4 * (int)t.sb - 2 * (int)t.n;
-        dE = wave_total(dE);
-        dM = wave_total(dM);
-        if ((tid & 63u) == 0u) {
-          s_red[tid >> 6][0] = dE;
-          s_red[tid >> 6][1] = dM;
-        }
+      for (uint32_t q = tid; q < ((Lp - 4u) << a.lg_ipp); q += nt) own_item(q + (2u << a.lg_ipp), s, 0u, t);
+      while (__hip_atomic_load(&s_ready, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != s)
+        __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      // own planes 0, 1, Lp - 2, Lp - 1 (local 2, 3, Lp, Lp + 1), from the last
+      // thread down: those have the fewest items above
+      for (uint32_t q = nt - 1u - tid; q < 4u * ipp; q += nt) {
+        const uint32_t k = q >> a.lg_ipp, own = k < 2u ? k : Lp - 4u + k;
+        own_item((own << a.lg_ipp) | (q & (ipp - 1u)), s, 0u, t);
       }
-      __syncthreads();
+    } else {
+      for (uint32_t q = tid; q < (Lp << a.lg_ipp); q += nt) own_item(q, s, 0u, t);
     }
+    {
+      // the inner halo planes (local 1 and Lp + 2), one group per item on
+      // the first waves: one such wave per SIMD keeps the pass balanced.
+      // Their flips are their owners' to count.
+      const uint32_t gpp = 1u << lgPl; // groups per plane
+      for (uint32_t q = tid; q < 2u * gpp; q += nt) {
+        const uint32_t lp = q < gpp ? 1u : Lp + 2u;
+        const uint32_t g0 = q & gmask;
+        const uint32_t y = DIM == 3 ? (q >> lgG) & lmask : 0u;
+        const uint32_t z = (z0 + lp + L - 2u) & lmask;
+        const uint32_t off = (lp + y) & 1u;
+        const uint32_t ctr = DIM == 3 ? (((z << lgL) + y) << lgG) + g0 : (z << lgG) + g0;
+        Words r[1];
+        r[0] = philox(ctr, s, slot, kPurposeFlip, a.key.k0, a.key.k1);
+        TallyN tl = {0u, 0u, 0u};
+        if constexpr (DIM == 3)
+          span3d_n<1, WIDE>(sp, bx, by, bz, lgG, lgPl, lp, lp - 1u, lp + 1u, y, (y + L - 1u) & lmask,
+                            (y + 1u) & lmask, g0, gmask, off, r, s_thr, tl);
+        else
+          span2d_n<1, WIDE>(sp + (lp << lgPl), sp + ((lp - 1u) << lgPl), sp + ((lp + 1u) << lgPl), g0,
+                            gmask, off, r, s_thr, tl);
+      }
+    }
+    __syncthreads();
+    if (pending) {
+      pending = false;
+      if (s_stop) break;
+    }
+    // colour 1
+    for (uint32_t q = tid; q < (Lp << a.lg_ipp); q += nt) own_item(q, s, 1u, t);
+    {
+      // this wave's energy and magnetisation changes over the sweep, ready
+      // at the barrier that ends the sweep
+      int dE = a.z2 * (int)t.n - 4 * ((int)t.sc - 8 * (int)t.sb), dM = 4 * (int)t.sb - 2 * (int)t.n;
+      dE = wave_total(dE);
+      dM = wave_total(dM);
+      if ((tid & 63u) == 0u) {
+        s_red[tid >> 6][0] = dE;
+        s_red[tid >> 6][1] = dM;
+      }
+    }
+    __syncthreads();
     const bool do_rec = a.sch.record_every && (s + 1u) % a.sch.record_every == 0u;
     const bool do_ex = a.sch.exchange_every && (s + 1u) % a.sch.exchange_every == 0u;
-    if (tid < 64u) { // wave 0 posts, waits, receives and decides; the rest wait below
-      for (uint32_t v = 0; v < (nt >> 6); ++v) {
-        Es += s_red[v][0];
-        Ms += s_red[v][1];
-      }
-      const uint64_t hi = 0xFFFFFFFF00000000ull;
-      const uint64_t tag = (uint64_t)(s + 1u) << 32, etag = (uint64_t)(e + 1u) << 32;
-      // the posts of this sweep's generation for walker w, one per part
-      uint64_t *posts = a.st.halo + ((size_t)(s & 1u) * R + w) * P * npost;
-      uint64_t *mine = posts + (size_t)p * npost;
-      uint64_t *mb = a.st.mailbox + (size_t)(e & 3u) * 2u * P * R; // [slot][part][E, M]
-      // post: words [0, 2 wpp) = own planes 2, 3; [2 wpp, 4 wpp) = planes Lp, Lp + 1
-      for (uint32_t q = tid; q < nb; q += 64u) {
-        const bool lo = q < 2u * wpp;
-        const uint4 x = reinterpret_cast<const uint4 *>(sp + ((lo ? 2u : Lp) << lgPl))[lo ? q : q - 2u * wpp];
-        const uint32_t word =
-            gather8(x.x) | (gather8(x.y) << 8) | (gather8(x.z) << 16) | (gather8(x.w) << 24);
-        __hip_atomic_store(mine + q, tag | word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      uint32_t partner = 0xFFFFFFFFu;
-      if (do_ex) {
-        const uint32_t par = e & 1u;
-        if ((slot & 1u) == par && slot + 1u < R) partner = slot + 1u;
-        else if ((slot & 1u) != par && slot >= 1u) partner = slot - 1u;
-      }
-      if (tid == 0u) {
-        if (do_ex) {
-          __hip_atomic_store(&mb[2u * (P * slot + p)], etag | (uint32_t)Es, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-          if constexpr (DIM == 2) // M for the field factor (2D only)
-            __hip_atomic_store(&mb[2u * (P * slot + p) + 1u], etag | (uint32_t)Ms, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __hip_atomic_store(mine + nb, tag | (uint32_t)Es, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(mine + nb + 1u, tag | (uint32_t)Ms, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      }
-      // everything of the swap test that does not need the energies, before waiting
-      uint32_t lo = 0u, rr = 0u;
-      int32_t sg = 0;
-      PairRow row{0, 0u, 0u, 0u};
-      if (tid == 0u && partner != 0xFFFFFFFFu) {
-        lo = min(slot, partner);
-        rr = philox(lo, e, 0u, kPurposeSwap, a.key.k0, a.key.k1).x;
-        row = pair_row(a.st, lo);
-        if constexpr (DIM == 2) sg = a.st.field_sign[lo];
-      }
-      // Word q of what this part reads: the lower boundary planes of the part
-      // above (q < 2 wpp, its post words q), the upper ones of the part below
-      // (2 wpp <= q < 4 wpp), then the E_int and M shares of the other parts.
-      uint32_t src[kSplitWordsPerLane]; // word offsets from posts
-      uint32_t pend = 0u;
-#pragma unroll
-      for (uint32_t k = 0; k < kSplitWordsPerLane; ++k) {
-        const uint32_t q = min(tid + 64u * k, nread - 1u);
-        if (tid + 64u * k < nread) pend |= 1u << k;
-        if (q < 2u * wpp) src[k] = pup * npost + q;
-        else if (q < nb) src[k] = pdn * npost + q;
-        else {
-          const uint32_t i = q - nb;
-          src[k] = ((p + 1u + (i >> 1)) & (P - 1u)) * npost + nb + (i & 1u);
-        }
-      }
-      // wait for those and, at an exchange step, the partner slot's E and M shares.
-      // Every round issues all of a lane's loads before testing any (one memory
-      // round trip per round); a word is consumed when its tag arrives and
-      // cannot change again before this part has posted its next sweep, so
-      // reloading a consumed word is harmless (loading only the words still
-      // pending was measured 0.7% slower: the masked loads cost more than the
-      // re-read words, which are a few MB per launch beside 8 TB/s).
-      // lane k < 2P reads word k of the partner slot's posts (E and M shares by
-      // part); in 3D, without a field, lane k < P reads part k's E share only
-      constexpr uint32_t NW = DIM == 2 ? 2u * P : P;
-      uint32_t ppend = (partner != 0xFFFFFFFFu && tid < NW) ? 1u : 0u;
-      const uint32_t pw = DIM == 2 ? (tid & (2u * P - 1u)) : 2u * (tid & (P - 1u));
-      const uint64_t *pmb = &mb[2u * P * (partner != 0xFFFFFFFFu ? partner : slot) + pw];
-      int32_t sE = 0, sM = 0, pE = 0;
-      uint32_t stop = 0u;
-      for (uint32_t n = 0;; ++n) {
-        uint64_t v[kSplitWordsPerLane];
-#pragma unroll
-        for (uint32_t k = 0; k < kSplitWordsPerLane; ++k)
-          v[k] = __hip_atomic_load(posts + src[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint64_t pv = __hip_atomic_load(pmb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t ab =
-            __hip_atomic_load(&a.st.counter[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-#pragma unroll
-        for (uint32_t k = 0; k < kSplitWordsPerLane; ++k) {
-          if (!((pend >> k) & 1u) || (v[k] & hi) != tag) continue;
-          pend &= ~(1u << k);
-          const uint32_t q = tid + 64u * k, x = (uint32_t)v[k];
-          if (q < nb) {
-            // the part above's lowest planes are this part's upper halo, the
-            // part below's highest planes the lower halo
-            const bool lo = q < 2u * wpp;
-            reinterpret_cast<uint4 *>(sp + (lo ? ((Lp + 2u) << lgPl) : 0u))[lo ? q : q - 2u * wpp] =
-                make_uint4(spread8(x & 0xFFu), spread8(__builtin_amdgcn_ubfe(x, 8u, 8u)),
-                           spread8(__builtin_amdgcn_ubfe(x, 16u, 8u)), spread8(x >> 24));
-          } else if (((q - nb) & 1u) == 0u) {
-            sE += (int32_t)x;
-          } else {
-            sM += (int32_t)x;
-          }
-        }
-        if (ppend && (pv & hi) == etag) {
-          ppend = 0u;
-          pE = (int32_t)(uint32_t)pv;
-        }
-        // the bound and the abort flag first: a limit of 0 gives up at once
-        if (n >= a.spin_limit || __any(ab != 0u)) {
-          if (tid == 0u)
-            __hip_atomic_store(&a.st.counter[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          stop = 1u;
-          break;
-        }
-        if (!__any((pend | ppend) != 0u)) break;
-        __builtin_amdgcn_s_sleep(1);
-      }
-      {
-        // the other parts' shares arrived in lanes sl .. sl + 2(P-1) - 1 of
-        // one load round (E at even offsets, M at odd; the launch checks that
-        // they do not wrap past lane 63): read them directly
-        const int sl = (int)(nb & 63u);
-        int32_t tE = 0, tM = 0;
-#pragma unroll
-        for (uint32_t i = 0; i + 1u < P; ++i) {
-          tE += __shfl(sE, sl + 2 * (int)i, 64);
-          tM += __shfl(sM, sl + 2 * (int)i + 1, 64);
-        }
-        sE = tE;
-        sM = tM;
-      }
-      // the partner slot's P shares of E (even lanes 0 .. 2P-2) and of M (odd
-      // lanes): independent reads
-      int32_t Ep = 0, Mp = 0;
-#pragma unroll
-      for (uint32_t k = 0; k < P; ++k) {
-        if constexpr (DIM == 2) {
-          Ep += __shfl(pE, (int)(2u * k), 64);
-          Mp += __shfl(pE, (int)(2u * k + 1u), 64);
-        } else {
-          Ep += __shfl(pE, (int)k, 64);
-        }
-      }
-      if (tid == 0u) {
-        Et = Es + sE;
-        Mt = Ms + sM;
-        uint32_t nslot = slot;
-        if (!stop) {
-          if (do_rec && p == 0u) {
-            a.st.E_series[(size_t)rec * R + slot] = Et;
-            a.st.M_series[(size_t)rec * R + slot] = Mt;
-          }
-          if (partner != 0xFFFFFFFFu) {
-            const int32_t Elo = (slot == lo) ? Et : Ep, Ehi = (slot == lo) ? Ep : Et;
-            const int32_t Mlo = (slot == lo) ? Mt : Mp, Mhi = (slot == lo) ? Mp : Mt;
-            bool accept = (uint64_t)rr < pair_T(row, a.st.swap_tab, a.st.swap_n, Elo - Ehi);
-            if constexpr (DIM == 2)
-              accept = accept && field_factor(a.st, sg, lo, e, Mlo - Mhi, a.key.k0, a.key.k1);
-            if (slot == lo && p == 0u) {
-              atomicAdd(&a.st.att[lo], 1u);
-              if (accept) atomicAdd(&a.st.acc[lo], 1u);
-            }
-            if (accept) {
-              nslot = partner;
-              for (uint32_t q = 0; q < kClasses * EW; ++q) s_tab[q] = thr[nslot * kClasses * EW + q];
-            }
-          }
-        }
-        s_slot = nslot;
-        s_stop = stop;
-      }
+    if (!do_ex && j + 1u < a.sch.nsw) {
+      pending = true;
+      ps = s;
+      prec = rec;
+      prec_do = do_rec;
+    } else {
+      if (tid < 64u) handshake(s, do_rec, do_ex, rec);
+      __syncthreads();
+      if (s_stop) break;
+      slot = s_slot;
     }
     if (do_rec) ++rec;
     if (do_ex) ++e;
-    __syncthreads();
-    if (s_stop) break;
-    slot = s_slot;
   }
   pack_tile_n(a.spins + (size_t)w * nwr + z0 * wpp, sp + (2u << lgPl), Lp * wpp, tid, nt);
   if (tid == 0u && p == 0u) {

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libptmi.so")
 
 PT_ABI_VERSION = 1
 PT_ALL_SLOTS = 0xFFFFFFFF
-PT_MAX_SWEEPS_PER_LAUNCH = 8
+PT_MAX_SWEEPS_PER_LAUNCH = 16
 PT_ISING2D, PT_EA3D = 0, 1
 PT_PLAN_AUTO, PT_PLAN_FUSED, PT_PLAN_TILED, PT_PLAN_PERSISTENT, PT_PLAN_LANES, PT_PLAN_WAVE = 0, 1, 2, 3, 4, 5
 STATUS = {0: "PT_OK", -1: "PT_EINVAL", -2: "PT_ENOMEM", -3: "PT_EDEVICE", -4: "PT_ESTATE",

@@ -112,11 +112,12 @@ def test_auto_plans_of_the_bench_workloads(pt):
         "ising2d_L16_R8": dict(mode=WAVE, block_threads=256),
         "ising2d_L1024_R64": dict(mode=PERSISTENT, tile_planes=256, block_threads=1024),
         "ea3d_L32_R128": dict(mode=PERSISTENT, tile_planes=16, block_threads=512),
-        "paper_shape_L256_R1500": dict(mode=TILED, tile_planes=256, sweeps_per_launch=8,
+        "paper_shape_L256_R1500": dict(mode=TILED, tile_planes=256, sweeps_per_launch=16,
                                        block_threads=256),
-        "paper_shape_L512_R1500": dict(mode=TILED, tile_planes=512, sweeps_per_launch=8,
+        "paper_shape_L512_R1500": dict(mode=TILED, tile_planes=512, sweeps_per_launch=16,
                                        block_threads=1024),
-        "paper_shape_L300_R1500": dict(mode=TILED, tile_planes=300, sweeps_per_launch=8),
+        "paper_shape_L300_R1500": dict(mode=TILED, tile_planes=300, sweeps_per_launch=16,
+                                       block_threads=512),
     }
     for name, plan in want.items():
         w = WORKLOADS[name]

@@ -44,7 +44,7 @@ def draw_case(i):
     threads = int(rng.integers(1, 17)) * 64
     plan = dict(mode=mode, block_threads=threads)
     if mode == TILED:
-        plan.update(tile_planes=int(rng.integers(1, L + 1)), sweeps_per_launch=int(rng.integers(1, 9)))
+        plan.update(tile_planes=int(rng.integers(1, L + 1)), sweeps_per_launch=int(rng.integers(1, 17)))
     elif mode == PERSISTENT:
         plan.update(tile_planes=int(rng.choice([L, L // 2, L // 2, L // 4, L // 8])))
     primitive = bool(rng.random() < 0.3)

@@ -169,6 +169,7 @@ def test_split_persistent_plan(pt, oracle_mod, L, R, every, rec, threads):
     (128, 4, 2, 1, 512, 4),
     (256, 3, 0, 1, 1024, 8),    # no exchange steps: boundary posts only
     (1024, 2, 1, 1, 1024, 4),   # the 1024^2 workload's decomposition
+    (1024, 3, 5, 2, 1024, 4),   # handshakes overlapped with the next sweep between exchanges
 ])
 def test_split_persistent_plan_2d(pt, oracle_mod, L, R, every, rec, threads, parts):
     """2D walkers split over P co-resident workgroups of L/P rows each."""
@@ -233,14 +234,17 @@ def test_split_persistent_plan_rejects_other_shapes(pt):
         sim.close()
 
 
-@pytest.mark.parametrize("model, L, R, plan", [
-    (1, 32, 6, dict(mode=PERSISTENT, tile_planes=16, block_threads=512)),   # two workgroups per walker
-    (1, 16, 5, dict(mode=PERSISTENT, tile_planes=16, block_threads=256)),   # one per walker
-    (0, 32, 8, dict(mode=PERSISTENT, block_threads=256)),
-    (0, 64, 4, dict(mode=PERSISTENT, tile_planes=16, block_threads=256)),   # 2D, four per walker
-    (0, 128, 3, dict(mode=PERSISTENT, tile_planes=64, block_threads=512)),  # 2D, two per walker
+@pytest.mark.parametrize("model, L, R, plan, every", [
+    (1, 32, 6, dict(mode=PERSISTENT, tile_planes=16, block_threads=512), 1),   # two workgroups per walker
+    (1, 16, 5, dict(mode=PERSISTENT, tile_planes=16, block_threads=256), 1),   # one per walker
+    (0, 32, 8, dict(mode=PERSISTENT, block_threads=256), 1),
+    (0, 64, 4, dict(mode=PERSISTENT, tile_planes=16, block_threads=256), 1),   # 2D, four per walker
+    (0, 128, 3, dict(mode=PERSISTENT, tile_planes=64, block_threads=512), 1),  # 2D, two per walker
+    # a handshake overlapped with the next sweep gives up (no exchange step, or one every 5)
+    (0, 64, 4, dict(mode=PERSISTENT, tile_planes=16, block_threads=256), 0),
+    (0, 128, 3, dict(mode=PERSISTENT, tile_planes=32, block_threads=1024), 5),
 ])
-def test_persistent_wait_bound_stops_the_launch(pt, oracle_mod, model, L, R, plan):
+def test_persistent_wait_bound_stops_the_launch(pt, oracle_mod, model, L, R, plan, every):
     """A wait limit of 0 makes every bounded wait give up at once: the launch
     ends early (every workgroup leaves its loop), the next observables call
     reports PT_EDEVICE and the context stays poisoned; a new context then runs
@@ -248,9 +252,9 @@ def test_persistent_wait_bound_stops_the_launch(pt, oracle_mod, model, L, R, pla
     PT_EDEVICE, PT_ESTATE = -3, -4
     beta = beta_geometric(0.5, 3.0, R) if model == 1 else beta_geometric(0.2, 0.6, R)
     sim = make_gpu(pt, model, L, R, beta, 29, 8, None, None, 1, 10, plan)
-    say("case wait bound", model, L, R, plan)
+    say("case wait bound", model, L, R, plan, "every", every)
     sim.set_wait_limit(0)
-    sim.run(10, 1)
+    sim.run(10, every)
     with pytest.raises(pt.PTError) as err:
         sim.observables()
     assert err.value.status == PT_EDEVICE

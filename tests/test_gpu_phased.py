@@ -2,8 +2,8 @@
 whole number of the 8-site groups one Philox block serves): the paper's own
 300 x 300 lattice (Sec. 4.2) and sides from 4 up, on the phased whole-replica
 kernel, compared bit for bit with the oracle (spins, E/M series, walker map,
-swap counts) over schedules with and without exchanges, fields, and every
-sweeps-per-launch and block size the plan allows."""
+swap counts) over schedules with and without exchanges, fields, and
+sweeps-per-launch counts and block sizes across what the plan allows."""
 import numpy as np
 import pytest
 
@@ -30,6 +30,12 @@ CASES = [
     (300, 4, 9, 3, 0.0, None),
     (300, 3, 8, 4, 0.0, dict(mode=2, tile_planes=300, sweeps_per_launch=2, block_threads=1024)),
     (520, 2, 6, 3, 0.0, None),
+    # rows whose last dword is past some rows' end (L = 46: phases 0..6), and
+    # runs of 16 sweeps per launch with a ragged last launch
+    (46, 3, 19, 4, 0.0, None),
+    (50, 4, 35, 0, 0.05, None),
+    (100, 5, 40, 8, 0.02, dict(mode=2, tile_planes=100, sweeps_per_launch=16, block_threads=512)),
+    (300, 3, 37, 0, 0.0, None),
 ]
 
 

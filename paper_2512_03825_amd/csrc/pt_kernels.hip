@@ -248,8 +248,11 @@ struct TiledArgs {
 // and magnetisation changes into E and M, writes the records, and runs the
 // exchange step; it then re-arms the arrival counter.
 // total = workgroups of the launch working on this walker set.
+// folded = true: every workgroup has already folded its own walker (whole
+// replicas, one workgroup per walker), so the last one only exchanges.
 __device__ __forceinline__ void tiled_epilogue(const TiledArgs &a, uint32_t tid, uint32_t nt,
-                                               uint32_t *s_last, uint32_t total) {
+                                               uint32_t *s_last, uint32_t total,
+                                               bool folded = false) {
   __syncthreads();
   if (tid == 0u) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); // publish this workgroup's tallies
@@ -266,7 +269,7 @@ __device__ __forceinline__ void tiled_epilogue(const TiledArgs &a, uint32_t tid,
   // memory round trip whatever the number of sweeps.  The slots do not change
   // before the exchange step, so walker v's record goes to column slot_of[v].
   const uint32_t R = a.geo.R, nsw = a.sch.nsw;
-  for (uint32_t v = tid; v < R; v += nt) {
+  for (uint32_t v = folded ? R : tid; v < R; v += nt) {
     int32_t dE[kMaxSweepsPerLaunch], dM[kMaxSweepsPerLaunch];
 #pragma unroll
     for (uint32_t j = 0; j < kMaxSweepsPerLaunch; ++j) {
@@ -305,6 +308,28 @@ __device__ __forceinline__ void tiled_epilogue(const TiledArgs &a, uint32_t tid,
 }
 
 
+
+// Whole replicas, one workgroup per walker: the walker is this workgroup's
+// alone, so thread 0 folds its per-sweep changes (s_sw) into E and M and writes
+// its records (its slot does not change before the exchange step); the last
+// workgroup then only exchanges (tiled_epilogue with folded = true).
+__device__ __forceinline__ void fold_own_walker(const TiledArgs &a, uint32_t w,
+                                                const int (*s_sw)[2]) {
+  const uint32_t R = a.geo.R, slot = a.st.slot_of[w];
+  int32_t E = a.st.E[w], M = a.st.M[w];
+  uint32_t rec = a.sch.rec_base;
+  for (uint32_t j = 0; j < a.sch.nsw; ++j) {
+    E += s_sw[j][0];
+    M += s_sw[j][1];
+    if (a.sch.record_every && (a.sch.s0 + j + 1u) % a.sch.record_every == 0u) {
+      a.st.E_series[(size_t)rec * R + slot] = E;
+      a.st.M_series[(size_t)rec * R + slot] = M;
+      ++rec;
+    }
+  }
+  a.st.E[w] = E;
+  a.st.M[w] = M;
+}
 
 // ---- the four-bit LDS layout -------------------------------------------------
 // Site 8g + j of a row sits at bits 4j .. 4j+3 of the row's dword g.  A dword
@@ -534,10 +559,12 @@ __device__ __forceinline__ void span3d_n(uint32_t *sp, const uint32_t *bx, const
 
 // One workgroup of the 2D tiled sweep: tile `tile` of walker `w`, staged in
 // sp (LDS), k sweeps, interior written back; per-sweep tallies to acc3.
+// s_sw != NULL (whole replicas, one workgroup per walker): the per-sweep
+// tallies go there instead.
 template <int V>
 __device__ __forceinline__ void tiled_n_body(const TiledArgs &a, uint32_t tile, uint32_t w,
                                              uint32_t *sp, uint64_t *s_thr,
-                                             int (*s_red)[2]) {
+                                             int (*s_red)[2], int (*s_sw)[2] = nullptr) {
   const Geometry &G = a.geo;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const uint32_t L = G.L, lgL = a.lg_L, lgG = lgL - 3u, gmask = (1u << lgG) - 1u;
@@ -621,9 +648,14 @@ __device__ __forceinline__ void tiled_n_body(const TiledArgs &a, uint32_t tile, 
         sE += s_red[v][0];
         sM += s_red[v][1];
       }
-      int32_t *acc = a.st.acc3 + ((size_t)(hs >> 1) * G.R + w) * 4u;
-      __hip_atomic_fetch_add(acc, sE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(acc + 1, sM, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (s_sw) {
+        s_sw[hs >> 1][0] = sE;
+        s_sw[hs >> 1][1] = sM;
+      } else {
+        int32_t *acc = a.st.acc3 + ((size_t)(hs >> 1) * G.R + w) * 4u;
+        __hip_atomic_fetch_add(acc, sE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(acc + 1, sM, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
 
@@ -637,9 +669,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint64_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
+  __shared__ int s_sw[kMaxSweepsPerLaunch][2];
   __shared__ uint32_t s_last;
-  tiled_n_body<V>(a, blockIdx.x, blockIdx.y, reinterpret_cast<uint32_t *>(smem), s_thr, s_red);
-  tiled_epilogue(a, threadIdx.x, blockDim.x, &s_last, gridDim.x * gridDim.y);
+  const bool whole = a.halo == 0u; // whole replicas: one workgroup per walker
+  tiled_n_body<V>(a, blockIdx.x, blockIdx.y, reinterpret_cast<uint32_t *>(smem), s_thr, s_red,
+                  whole ? s_sw : nullptr);
+  if (whole && threadIdx.x == 0u) fold_own_walker(a, blockIdx.y, s_sw);
+  tiled_epilogue(a, threadIdx.x, blockDim.x, &s_last, gridDim.x * gridDim.y, whole);
 }
 
 
@@ -994,6 +1030,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ uint64_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
+  __shared__ int s_sw[kMaxSweepsPerLaunch][2]; // this walker's dE, dM per sweep
   __shared__ uint32_t s_last;
   const TiledArgs &a = pa.t;
   const Geometry &G = a.geo;
@@ -1005,10 +1042,49 @@ __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
   if (tid < kClasses) s_thr[tid] = a.st.flip_cmp[slot * kClasses + tid];
 
   // stage: LDS dword (y, g) <- byte G0(y) + g of the walker's packed sites
-  // (one byte = one group of 8 sites), padding dwords zero.  Each thread steps
-  // through (y, g) by nt dwords at a time (no divisions in the loop) and
-  // issues four loads before it spreads any of them.
-  {
+  // (one byte = one group of 8 sites), every other nibble zero.
+  if constexpr (V > 1) {
+    // At least 6 groups per row: a group's sites lie in at most two rows.
+    // Packed words are loaded whole, all of a thread's loads issued together
+    // (one memory round trip), and each group's byte is spread to the row of
+    // its first site and, when it runs past that row's end, to dword 0 of the
+    // next row; the dwords past a row's last group, and those around the
+    // rows, are zeroed (no stencil may carry out of a padding nibble).
+    const uint32_t *src = a.src + (size_t)w * nwr;
+    const uint32_t N = G.N;
+    const float invL = 1.0f / (float)L;
+    constexpr uint32_t kBatch = 8;
+    for (uint32_t q0 = tid; q0 < nwr; q0 += kBatch * nt) {
+      uint32_t v[kBatch];
+#pragma unroll
+      for (uint32_t j = 0; j < kBatch; ++j) v[j] = q0 + j * nt < nwr ? src[q0 + j * nt] : 0u;
+#pragma unroll
+      for (uint32_t j = 0; j < kBatch; ++j) {
+        const uint32_t q = q0 + j * nt;
+        if (q >= nwr) break;
+#pragma unroll
+        for (uint32_t b = 0; b < 4u; ++b) {
+          const uint32_t gi = 4u * q + b, x0 = 8u * gi; // the group's first site
+          if (x0 >= N) break;
+          uint32_t y = (uint32_t)((float)x0 * invL); // within one of the row index
+          y -= y * L > x0 ? 1u : 0u;
+          y += (y + 1u) * L <= x0 ? 1u : 0u;
+          const uint32_t val = spread8((v[j] >> (8u * b)) & 0xFFu);
+          lds[kPhasedLead + y * S + (gi - ((y * L) >> 3))] = val;
+          if (x0 + 8u > (y + 1u) * L && y + 1u < L) lds[kPhasedLead + (y + 1u) * S] = val;
+        }
+      }
+    }
+    for (uint32_t y = tid; y < L; y += nt) {
+      const uint32_t gl = (((y * L) & 7u) + L - 1u) >> 3; // the row's last group
+      for (uint32_t g = gl + 1u; g < S; ++g) lds[kPhasedLead + y * S + g] = 0u;
+      rows[y] = phased_row_info(y, L, S);
+    }
+    if (tid < kPhasedLead) lds[tid] = 0u;
+    if (tid < 4u) lds[kPhasedLead + L * S + tid] = 0u;
+  } else {
+    // Each thread steps through (y, g) by nt dwords at a time (no divisions
+    // in the loop) and issues four loads before it spreads any of them.
     const uint8_t *src = reinterpret_cast<const uint8_t *>(a.src + (size_t)w * nwr);
     const uint32_t nbytes = 4u * nwr, Gmax = pa.Gmax;
     if (tid < kPhasedLead) lds[tid] = 0u;
@@ -1117,11 +1193,12 @@ __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
         sE += s_red[v][0];
         sM += s_red[v][1];
       }
-      int32_t *acc = a.st.acc3 + ((size_t)(hs >> 1) * G.R + w) * 4u;
-      __hip_atomic_fetch_add(acc, sE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(acc + 1, sM, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_sw[hs >> 1][0] = sE;
+      s_sw[hs >> 1][1] = sM;
     }
   }
+
+  if (tid == 0u) fold_own_walker(a, w, s_sw);
 
   // back to HBM: packed word q holds groups 4q .. 4q+3; a group's sites lie in
   // the row of its first site and, past that row's end, in the next row's group 0
@@ -1145,7 +1222,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
       dst[q] = word;
     }
   }
-  tiled_epilogue(a, tid, nt, &s_last, gridDim.x * gridDim.y);
+  tiled_epilogue(a, tid, nt, &s_last, gridDim.x * gridDim.y, true);
 }
 
 struct FusedArgs {

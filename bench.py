@@ -649,7 +649,9 @@ def main():
     value = attempts / dt
 
     # roofline of the sweep kernel: HIP events around single launches on the
-    # library's stream (each pt_run call below is exactly one kernel launch)
+    # library's stream (each pt_run call below is one sweep-kernel launch; with
+    # whole-replica tiles a launch that ends at an exchange point is followed by
+    # the exchange step's own small launch, inside the same events)
     if plan["mode"] == pt.PT_PLAN_TILED:
         per_launch = plan["sweeps_per_launch"]
         if every:

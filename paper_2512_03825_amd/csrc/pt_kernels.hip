@@ -248,11 +248,8 @@ struct TiledArgs {
 // and magnetisation changes into E and M, writes the records, and runs the
 // exchange step; it then re-arms the arrival counter.
 // total = workgroups of the launch working on this walker set.
-// folded = true: every workgroup has already folded its own walker (whole
-// replicas, one workgroup per walker), so the last one only exchanges.
 __device__ __forceinline__ void tiled_epilogue(const TiledArgs &a, uint32_t tid, uint32_t nt,
-                                               uint32_t *s_last, uint32_t total,
-                                               bool folded = false) {
+                                               uint32_t *s_last, uint32_t total) {
   __syncthreads();
   if (tid == 0u) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); // publish this workgroup's tallies
@@ -269,7 +266,7 @@ __device__ __forceinline__ void tiled_epilogue(const TiledArgs &a, uint32_t tid,
   // memory round trip whatever the number of sweeps.  The slots do not change
   // before the exchange step, so walker v's record goes to column slot_of[v].
   const uint32_t R = a.geo.R, nsw = a.sch.nsw;
-  for (uint32_t v = folded ? R : tid; v < R; v += nt) {
+  for (uint32_t v = tid; v < R; v += nt) {
     int32_t dE[kMaxSweepsPerLaunch], dM[kMaxSweepsPerLaunch];
 #pragma unroll
     for (uint32_t j = 0; j < kMaxSweepsPerLaunch; ++j) {
@@ -311,8 +308,8 @@ __device__ __forceinline__ void tiled_epilogue(const TiledArgs &a, uint32_t tid,
 
 // Whole replicas, one workgroup per walker: the walker is this workgroup's
 // alone, so thread 0 folds its per-sweep changes (s_sw) into E and M and writes
-// its records (its slot does not change before the exchange step); the last
-// workgroup then only exchanges (tiled_epilogue with folded = true).
+// its records (its slot does not change before the exchange step, which runs
+// as a launch of its own after the sweeps).
 __device__ __forceinline__ void fold_own_walker(const TiledArgs &a, uint32_t w,
                                                 const int (*s_sw)[2]) {
   const uint32_t R = a.geo.R, slot = a.st.slot_of[w];
@@ -674,8 +671,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_tiled_n(TiledArgs a) {
   const bool whole = a.halo == 0u; // whole replicas: one workgroup per walker
   tiled_n_body<V>(a, blockIdx.x, blockIdx.y, reinterpret_cast<uint32_t *>(smem), s_thr, s_red,
                   whole ? s_sw : nullptr);
-  if (whole && threadIdx.x == 0u) fold_own_walker(a, blockIdx.y, s_sw);
-  tiled_epilogue(a, threadIdx.x, blockDim.x, &s_last, gridDim.x * gridDim.y, whole);
+  // whole replicas fold themselves and leave the exchange step to a launch of
+  // its own (launch_tiled): no arrival counter for a last workgroup
+  if (whole) {
+    if (threadIdx.x == 0u) fold_own_walker(a, blockIdx.y, s_sw);
+  } else {
+    tiled_epilogue(a, threadIdx.x, blockDim.x, &s_last, gridDim.x * gridDim.y);
+  }
 }
 
 
@@ -1031,7 +1033,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
   __shared__ uint64_t s_thr[kClasses];
   __shared__ int s_red[kMaxThreads / 64][2];
   __shared__ int s_sw[kMaxSweepsPerLaunch][2]; // this walker's dE, dM per sweep
-  __shared__ uint32_t s_last;
   const TiledArgs &a = pa.t;
   const Geometry &G = a.geo;
   const uint32_t tid = threadIdx.x, nt = blockDim.x, w = blockIdx.y;
@@ -1222,7 +1223,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_phased(PhasedArgs pa) {
       dst[q] = word;
     }
   }
-  tiled_epilogue(a, tid, nt, &s_last, gridDim.x * gridDim.y, true);
+  // the exchange step, if any, is the next launch's (launch_tiled)
 }
 
 struct FusedArgs {
@@ -2442,8 +2443,8 @@ __global__ void k_batch_advance(const BatchInst *insts, const uint32_t *list, ui
 }
 
 __global__ void k_exchange(DevState st, uint32_t R, Keys key, uint32_t e) {
-  exchange_step(st, R, key.k0, key.k1, e, st.E, st.M, st.walker_at, st.slot_of, threadIdx.x,
-                blockDim.x);
+  exchange_step(st, R, key.k0, key.k1, e, st.E, st.M, st.walker_at, st.slot_of,
+                blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // Initial spins: site i of walker w takes word i mod 4 of block (i/4, w, 0, spin
@@ -2823,7 +2824,9 @@ hipError_t launch_recount(const DevState &st, const Geometry &g, uint32_t cur,
 
 hipError_t launch_exchange(const DevState &st, const Geometry &g, const Keys &k, uint32_t e,
                            hipStream_t stream) {
-  hipLaunchKernelGGL(k_exchange, dim3(1), dim3(256), 0, stream, st, g.R, k, e);
+  // one lane per pair of the step, all in flight together
+  const uint32_t blocks = (g.R / 2u + 255u) / 256u;
+  hipLaunchKernelGGL(k_exchange, dim3(blocks ? blocks : 1u), dim3(256), 0, stream, st, g.R, k, e);
   return hipGetLastError();
 }
 
@@ -2834,6 +2837,14 @@ uint32_t span_groups(const Geometry &g) {
 hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
                         uint32_t tile_planes, uint32_t halo, uint32_t threads,
                         const Schedule &sch, hipStream_t stream) {
+  if (halo == 0u && sch.do_exchange) {
+    // whole replicas: the sweeps, then the exchange step as a launch of its own
+    Schedule s2 = sch;
+    s2.do_exchange = 0u;
+    const hipError_t err = launch_tiled(st, g, k, cur, tile_planes, halo, threads, s2, stream);
+    if (err != hipSuccess) return err;
+    return launch_exchange(st, g, k, sch.ex_step, stream);
+  }
   TiledArgs a;
   a.st = st;
   a.geo = g;

@@ -250,6 +250,11 @@ def bench_batched(args):
            "config": {"workload": "batched%d" % len(ws), "instances": len(ws), "sweeps": sweeps,
                       "exchange_every": every, "L": sorted({w.L for w in ws}),
                       "R": sorted({w.R for w in ws}), "h": [-0.1, 0.1], "group_plans": plans,
+                      # with h != 0 the exchange is the paper's logistic test on the
+                      # h = 0 exponent times a Metropolis test on the field term
+                      # (detailed balance for the full exponent; the paper's rule at h = 0)
+                      "swap_rule": "h != 0: logistic(beta-difference x bond-energy difference)"
+                                   " x Metropolis(field term), not one logistic test",
                       "parallelism": "single GPU"},
            "per_instance_path": {"value": single, "unit": "flip attempts/s",
                                  "sample": "same %d instances one after another, %d sweeps each"

@@ -101,6 +101,24 @@ def test_paper_shape_300_matches_oracle(oracle_mod, pt):
     sim.close()
 
 
+def test_paper_shape_300_with_swaps_matches_oracle(oracle_mod, pt):
+    """The paper's shape with an exchange after every sweep (its own swap
+    intervals are shorter than a sweep of this lattice): one-sweep launches of
+    whole replicas, each followed by the exchange step as a launch of its own
+    over all 750 pairs."""
+    w = paper_shape(300)
+    sweeps = 3
+    say("paper shape with swaps", w.name, "sweeps", sweeps)
+    cfg = pt.Config(w.model, w.L, w.R, w.beta, seed=w.seed, record_every=1, max_records=sweeps)
+    sim = pt.Simulation(cfg)
+    sim.run(sweeps, 1)
+    orc = oracle_mod.Oracle(w.model, w.L, w.R, w.beta, seed=w.seed, record_every=1, max_records=sweeps)
+    orc.run(sweeps, 1)
+    obs = compare(sim, orc, w.name + " every sweep")
+    assert obs["swap_acc"].sum() > 0
+    sim.close()
+
+
 @pytest.fixture(scope="module")
 def pt():
     from paper_2512_03825_amd import pt as _pt

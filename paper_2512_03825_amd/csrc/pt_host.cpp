@@ -966,7 +966,7 @@ std::string group_key(const std::string &dev, const Geometry &g, uint32_t max_R)
 
 std::vector<std::pair<uint32_t, uint32_t>> batch_candidates(const Geometry &g, uint32_t max_R) {
   std::vector<std::pair<uint32_t, uint32_t>> c;
-  const uint32_t spans = g.N / (8u * span_groups(g));
+  const uint32_t spans = g.N / (8u * batch_span(g));
   for (uint32_t W = 1; W <= 32 && W <= max_R; W *= 2) {
     if (batch_lds_bytes(g, W) > 64u * 1024u) break;
     const uint32_t work = W * spans; // lanes' worth of work per half sweep
@@ -989,7 +989,7 @@ BatchInst batch_inst(const pt_ctx *c, uint32_t *ctr) {
   I.geo = g;
   I.key = c->keys;
   I.record_every = c->cfg.record_every;
-  const uint32_t V = span_groups(g);
+  const uint32_t V = batch_span(g);
   I.lg_L = lg2(g.L);
   I.lg_spr = lg2(g.gpr / V);
   I.lg_rows = lg2(g.rows);

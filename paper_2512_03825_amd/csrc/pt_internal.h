@@ -181,6 +181,8 @@ inline size_t split_halo_words(const Geometry &g) {
 
 // Groups of 8 sites one lane updates per item (V): 2D min(4, L/8), 3D min(2, L/8).
 uint32_t span_groups(const Geometry &g);
+// The same for the batched kernels: 2D min(8, L/8), 3D min(2, L/8).
+uint32_t batch_span(const Geometry &g);
 
 // LDS bytes needed by the kernels (host-side planning).
 size_t tiled_lds_bytes(const Geometry &g, uint32_t tile_planes, uint32_t halo);

@@ -2834,6 +2834,10 @@ uint32_t span_groups(const Geometry &g) {
   return std::min<uint32_t>(g.gpr, g.dim == 3 ? 2u : 4u);
 }
 
+uint32_t batch_span(const Geometry &g) {
+  return std::min<uint32_t>(g.gpr, g.dim == 3 ? 2u : kNibbleSpan);
+}
+
 hipError_t launch_tiled(const DevState &st, const Geometry &g, const Keys &k, uint32_t cur,
                         uint32_t tile_planes, uint32_t halo, uint32_t threads,
                         const Schedule &sch, hipStream_t stream) {
@@ -3052,11 +3056,12 @@ hipError_t launch_batch_sweep(const BatchInst *insts, const BatchItem *items, ui
                               const Geometry &g, uint32_t W, uint32_t threads, uint32_t K,
                               hipStream_t stream) {
   if (n_items == 0) return hipSuccess;
-  const uint32_t V = span_groups(g);
+  const uint32_t V = batch_span(g);
   const size_t lds = batch_lds_bytes(g, W);
   if (g.dim == 3)
     return V == 2 ? launch_batch_sweep_v<3, 2>(insts, items, n_items, W, threads, K, lds, stream)
                   : launch_batch_sweep_v<3, 1>(insts, items, n_items, W, threads, K, lds, stream);
+  if (V == 8) return launch_batch_sweep_v<2, 8>(insts, items, n_items, W, threads, K, lds, stream);
   return V == 4 ? launch_batch_sweep_v<2, 4>(insts, items, n_items, W, threads, K, lds, stream)
        : V == 2 ? launch_batch_sweep_v<2, 2>(insts, items, n_items, W, threads, K, lds, stream)
                 : launch_batch_sweep_v<2, 1>(insts, items, n_items, W, threads, K, lds, stream);

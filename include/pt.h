@@ -95,8 +95,9 @@ typedef struct {
  *   FUSED       one workgroup holds every walker in LDS; whole schedules run in
  *               one launch (small systems).
  *   TILED       a workgroup per (tile of planes, walker); halo tiles, up to
- *               PT_MAX_SWEEPS_PER_LAUNCH sweeps per launch; exchanges run in the
- *               epilogue of the last workgroup.
+ *               PT_MAX_SWEEPS_PER_LAUNCH sweeps per launch; with halo tiles an
+ *               exchange step runs in the epilogue of the launch's last
+ *               workgroup, with whole replicas as a launch of its own.
  *   PERSISTENT  one co-resident workgroup per walker keeps its lattice in LDS
  *               for a whole pt_run call; exchange steps are decided pairwise
  *               between neighbouring slots without a global barrier.  With

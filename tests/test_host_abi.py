@@ -152,3 +152,13 @@ def test_probe_library_exports_its_entry_point(pt):
     assert f(0, 4, 256, 1, C.c_void_p(256), 1023, None, C.byref(ms)) != 0   # 1024 threads, 1023 words
     assert f(4, 1, 64, 1, C.c_void_p(256), 64, None, C.byref(ms)) != 0      # no such kind
     assert f(0, 1, 96, 1, C.c_void_p(256), 96, None, C.byref(ms)) != 0      # not whole waves
+
+
+def test_header_constants_match_the_binding(pt):
+    """The binding's copies of the header's numeric constants agree with it."""
+    src = open(os.path.join(ROOT, "include", "pt.h")).read()
+    for name in ("PT_MAX_SWEEPS_PER_LAUNCH", "PT_STATIC_SCRATCH_BYTES"):
+        m = re.search(r"#define\s+%s\s+\(?(\d+)u(?:\s*<<\s*(\d+))?\)?" % name, src)
+        assert m, name
+        value = int(m.group(1)) << int(m.group(2) or 0)
+        assert getattr(pt, name) == value, name

@@ -605,9 +605,9 @@ def main():
     if args.form == "served" and args.gpus == 1:
         return bench_served(args)
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
-              "(the path would shard by temperature slots, see the design notes)" % args.gpus,
-              file=sys.stderr)
+        print("bench.py: runs on one GPU only; --gpus %d is not supported (the path would "
+              "shard by temperature slots: each GPU a block of slots, the energies all-gathered "
+              "at every exchange step)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -92,7 +92,7 @@ def parse():
                     help="served form: arrival rate in jobs/s (0: rho x measured capacity / mean job)")
     ap.add_argument("--plain-sample", type=int, default=100,
                     help="served form: jobs of the stream also served one at a time by the plain "
-                         "path, end to end at their arrival times")
+                         "path, end to end at their arrival times (0: none)")
     ap.add_argument("--latencies-out", default="",
                     help="served form: write every job's arrival, finish and size to this JSON file")
     ap.add_argument("--rho", type=float, default=0.8, help="served form: offered load / capacity")
@@ -420,8 +420,8 @@ def bench_served(args):
     # the plain per-instance path, end to end on a sample: the first jobs of
     # the segment at the same arrival times, one at a time
     m = min(args.plain_sample, len(ws))
-    plain_lat, busy = _plain_fifo(pt, cfgs[:m], ws[:m], arrivals[:m])
-    plain_capacity = att[:m].sum() / busy
+    plain_lat, busy = _plain_fifo(pt, cfgs[:m], ws[:m], arrivals[:m]) if m else ([], 0.0)
+    plain_capacity = float(att[:m].sum() / busy) if m else None
     out = {"metric": "served-job latency p50/p99 + flip attempts/s", "value": value,
            "unit": "flip attempts/s", "n_gpus": 1, "steps": len(ws), "warmup": 0,
            "ms_per_step": dt / len(ws) * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -436,12 +436,12 @@ def bench_served(args):
                         "sample": "served: first %d jobs cut to 2000 sweeps, all at t=0 (%.1f s); "
                                   "plain: the segment's first %d jobs run end to end one at a time "
                                   "(%.1f s of service)" % (len(cut), cap_dt, m, busy)},
-           "plain_fifo_latency_s": {"jobs": m, "p50": float(np.percentile(plain_lat, 50)),
-                                    "p99": float(np.percentile(plain_lat, 99)),
-                                    "max": float(max(plain_lat))},
-           "served_latency_same_jobs_s": {"p50": float(np.percentile(lat[:m], 50)),
-                                          "p99": float(np.percentile(lat[:m], 99))},
-           "speedup_vs_per_instance": C / plain_capacity,
+           "plain_fifo_latency_s": ({"jobs": m, "p50": float(np.percentile(plain_lat, 50)),
+                                     "p99": float(np.percentile(plain_lat, 99)),
+                                     "max": float(max(plain_lat))} if m else None),
+           "served_latency_same_jobs_s": ({"p50": float(np.percentile(lat[:m], 50)),
+                                           "p99": float(np.percentile(lat[:m], 99))} if m else None),
+           "speedup_vs_per_instance": C / plain_capacity if m else None,
            "roofline": batched_roofline(C)}
     out["roofline"]["kernel"] = "served capacity (batched and tiled lanes)"
     if not args.no_cpu_baseline:

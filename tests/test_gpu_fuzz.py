@@ -53,12 +53,45 @@ def draw_case(i):
                 plan=plan, primitive=primitive)
 
 
+def draw_even_side_case(i):
+    """2D cases on even sides that are not powers of two (the phased rows) and
+    on larger powers of two (the split plans, with their handshakes overlapped
+    between exchange steps), any plan, up to 16 sweeps per launch."""
+    rng = np.random.default_rng([2025, i])
+    L = int(rng.choice([10, 12, 14, 18, 20, 22, 26, 30, 36, 46, 50, 60, 62, 72, 100, 64, 128]))
+    R = int(rng.integers(2, 13))
+    h = float(rng.choice([0.0, 0.0, rng.uniform(-0.2, 0.2)]))
+    beta = beta_linear(0.2, 0.7, R) if rng.random() < 0.5 else beta_geometric(0.2, 0.7, R)
+    sweeps = int(rng.integers(5, 41))
+    every = int(rng.choice([0, 1, 2, 3, 5, 7]))
+    rec = int(rng.choice([0, 1, 2, 3]))
+    mode = int(rng.choice([TILED, TILED, PERSISTENT, PERSISTENT, FUSED]))
+    plan = dict(mode=mode, block_threads=int(rng.integers(1, 17)) * 64)
+    if mode == TILED:
+        plan.update(tile_planes=int(rng.choice([L, L, max(1, L // 2), int(rng.integers(1, L + 1))])),
+                    sweeps_per_launch=int(rng.integers(1, 17)))
+    elif mode == PERSISTENT:
+        plan.update(tile_planes=int(rng.choice([L, L // 2, L // 4, L // 8])))
+    primitive = bool(rng.random() < 0.3)
+    return dict(model=0, L=L, R=R, h=h, beta=beta, seed=int(rng.integers(1, 1 << 30)),
+                coupling_seed=int(rng.integers(1, 1 << 30)), sweeps=sweeps, every=every, rec=rec,
+                plan=plan, primitive=primitive)
+
+
 @pytest.mark.parametrize("i", range(N_CASES))
 def test_random_case_matches_oracle(oracle_mod, i):
+    run_random_case(oracle_mod, "fuzz %d" % i, draw_case(i))
+
+
+@pytest.mark.parametrize("i", range(60))
+def test_random_even_side_case_matches_oracle(oracle_mod, i):
+    run_random_case(oracle_mod, "fuzz-even %d" % i, draw_even_side_case(i))
+
+
+def run_random_case(oracle_mod, name, c):
     from paper_2512_03825_amd import pt
-    c = draw_case(i)
-    tag = "fuzz %d: model %d L %d R %d h %.3f sweeps %d every %d rec %d plan %s primitive %s" % (
-        i, c["model"], c["L"], c["R"], c["h"], c["sweeps"], c["every"], c["rec"], c["plan"],
+    tag = "%s: model %d L %d R %d h %.3f sweeps %d every %d rec %d plan %s primitive %s" % (
+        name, c["model"], c["L"], c["R"], c["h"], c["sweeps"], c["every"], c["rec"], c["plan"],
         c["primitive"])
     say(tag)
     nrec = c["sweeps"] // c["rec"] if c["rec"] else 0
